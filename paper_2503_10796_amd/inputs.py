@@ -1,0 +1,104 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/benchmarks and the oracle.
+
+This module holds no arithmetic of the method: it only draws populations
+(positions, diameters, volumes, growth rates) and sweep parameters from
+seeded numpy generators.  Every workload is synthetic; the thesis measures
+on no public dataset for this path.
+
+Recipes (sizes and distributions of the thesis's tissue benchmarks):
+  plain(n, side, seed)      centres uniform in [0, side)^3, diameters U[10, 15)
+  at_density(n, seed)       same, side chosen for 1 agent per 1000 um^3
+  relaxed_lattice(n, seed)  jittered cubic lattice (spacing 15.5 um, jitter 0.2 um,
+                            diameters U[10, 15)) with 5 % of agents moved 8-12 um
+                            from a lattice neighbour, so most agents start static
+  spheroid(n, seed, ...)    centres uniform in a ball (radius 50 um at 1000 cells,
+                            constant density otherwise), diameter 8 um, volume
+                            pi d^3 / 6, growth rate lognormal with arithmetic
+                            mean 1 and log-sd 0.2 (um^3 per step)
+  sweep_params(n, seed)     Latin hypercube over growth scale [0.5, 1.5],
+                            division diameter [6, 18] um, adherence [0.9, 2.7],
+                            and log-uniform initial counts in [1e3, 5e4]
+"""
+import math
+
+import numpy as np
+
+DENSITY = 1.0e-3  # agents per um^3
+
+
+def plain(n, side=160.0, seed=0, dmin=10.0, dmax=15.0):
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, side, size=(n, 3))
+    diam = rng.uniform(dmin, dmax, size=n)
+    return pos, diam
+
+
+def cube_side(n, density=DENSITY):
+    return (n / density) ** (1.0 / 3.0)
+
+
+def at_density(n, seed=1, density=DENSITY):
+    return plain(n, side=cube_side(n, density), seed=seed)
+
+
+def relaxed_lattice(n_side, seed=2, spacing=15.5, jitter=0.2, frac_moved=0.05):
+    """Pre-relaxed population: a jittered lattice where no pair touches, plus a
+    random 5 % of agents moved along a lattice line to 8-12 um from a lattice
+    neighbour.  Returns pos, diam."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(n_side, dtype=np.float64) * spacing
+    zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    n = pos.shape[0]
+    pos += rng.uniform(-jitter, jitter, size=pos.shape)
+    diam = rng.uniform(10.0, 15.0, size=n)
+    moved = rng.random(n) < frac_moved
+    idx = np.nonzero(moved)[0]
+    axis = rng.integers(0, 3, size=idx.size)
+    sign = rng.choice([-1.0, 1.0], size=idx.size)
+    gap = rng.uniform(8.0, 12.0, size=idx.size)
+    # move towards the chosen neighbour so that it sits `gap` away from it
+    pos[idx, axis] += sign * (spacing - gap)
+    return pos, diam
+
+
+def ball(n, radius, rng):
+    out = np.empty((0, 3))
+    while out.shape[0] < n:
+        c = rng.uniform(-radius, radius, size=(2 * n, 3))
+        c = c[(c * c).sum(axis=1) < radius * radius]
+        out = np.concatenate([out, c], axis=0)
+    return out[:n]
+
+
+def spheroid(n=1000, seed=3, diameter=8.0, growth_mean=1.0, growth_sigma=0.2, growth_scale=1.0,
+             radius=None):
+    rng = np.random.default_rng(seed)
+    if radius is None:
+        radius = 50.0 * (n / 1000.0) ** (1.0 / 3.0)
+    pos = ball(n, radius, rng)
+    diam = np.full(n, diameter)
+    vol = np.full(n, math.pi * diameter ** 3 / 6.0)
+    mu = math.log(growth_mean) - 0.5 * growth_sigma ** 2
+    growth = rng.lognormal(mean=mu, sigma=growth_sigma, size=n) * growth_scale
+    return pos, diam, vol, growth
+
+
+def division_volume(d_div):
+    return math.pi * d_div ** 3 / 6.0
+
+
+def sweep_params(n_sims, seed=4, n_lo=1.0e3, n_hi=5.0e4):
+    """Latin-hypercube sweep: one stratum per simulation in every dimension."""
+    rng = np.random.default_rng(seed)
+    n0 = np.rint(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), size=n_sims))).astype(np.int64)
+
+    def lhs(lo, hi):
+        perm = rng.permutation(n_sims)
+        u = (perm + rng.random(n_sims)) / n_sims
+        return lo + (hi - lo) * u
+
+    gscale = lhs(0.5, 1.5)
+    d_div = lhs(6.0, 18.0)
+    adherence = lhs(0.9, 2.7)
+    return n0, gscale, d_div, adherence

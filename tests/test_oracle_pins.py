@@ -1,0 +1,396 @@
+"""Pins of the FP64 oracle against what the thesis and mathematics fix.
+
+Each test names the passage it follows.  None of them compares the oracle
+with itself: the checks are closed forms, worked examples printed in the
+thesis, brute force, exact invariants and statistics of known distributions.
+"""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import sim
+from oracle import mlp
+from paper_2503_10796_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def c0_params(**kw):
+    c = golden("table4_2_constants.json")
+    base = dict(dt=0.01, k=c["k"], gamma=c["gamma"], adherence=c["adherence"], mass=c["mass"],
+                max_disp=3.0, box_len=15.0)
+    base.update(kw)
+    return sim.make_params(**base)
+
+
+# --- Eq 4.1-4.2: closed-form two-sphere forces -----------------------------------------
+@pytest.mark.parametrize("d1,d2,dist,expected", [
+    (10.0, 10.0, 8.0, 4.0 - math.sqrt(5.0)),     # delta 2, rbar 2.5
+    (10.0, 10.0, 6.0, 8.0 - math.sqrt(10.0)),    # delta 4, rbar 2.5
+    (12.0, 8.0, 9.0, 2.0 - math.sqrt(2.4)),      # delta 1, rbar 2.4
+    (10.0, 10.0, 9.0, 2.0 - math.sqrt(2.5)),     # delta 1, rbar 2.5
+])
+def test_two_sphere_force_closed_form(d1, d2, dist, expected):
+    p = c0_params(box_len=0.0)
+    s = sim.OracleSim(np.array([[0.0, 0.0, 0.0], [dist, 0.0, 0.0]]), np.array([d1, d2]), p)
+    s.step()
+    f = s.force()
+    # positive F_N pushes the pair apart along the centre line (agent 0 towards -x)
+    assert f[0, 0] == pytest.approx(-expected, rel=1e-14)
+    assert f[1, 0] == pytest.approx(expected, rel=1e-14)
+    assert f[0, 1] == 0.0 and f[0, 2] == 0.0
+    assert s.contacts[0] == 1 and s.nz[0] == 1 and s.nbr[0] == 1
+    assert sim.pair_force(d1 / 2, d2 / 2, d1 / 2 + d2 / 2 - dist) == pytest.approx(expected, rel=1e-14)
+
+
+def test_force_zero_and_minimum_of_eq_4_1():
+    # F_N = k d - g sqrt(r d) vanishes at d* = g^2 r / k^2 and is smallest, -g^2 r/(4k), at d*/4.
+    k, g = 2.0, 1.0
+    for r1, r2 in [(5.0, 5.0), (7.5, 7.5), (6.0, 4.0)]:
+        rbar = r1 * r2 / (r1 + r2)
+        dstar = g * g * rbar / (k * k)
+        assert abs(sim.pair_force(r1, r2, dstar)) < 1e-15
+        dmin = dstar / 4.0
+        fmin = sim.pair_force(r1, r2, dmin)
+        assert fmin == pytest.approx(-g * g * rbar / (4 * k), rel=1e-14)
+        for eps in (1e-3, -1e-3):
+            assert sim.pair_force(r1, r2, dmin + eps) > fmin
+        # the largest attraction for diameters up to 15 stays below the smallest adherence of the sweeps
+        assert -fmin < 0.9 or rbar > 3.75
+
+
+def test_coincident_centres_give_no_force():
+    p = c0_params(box_len=0.0)
+    s = sim.OracleSim(np.array([[1.0, 2.0, 3.0], [1.0, 2.0, 3.0]]), np.array([10.0, 10.0]), p)
+    s.step()
+    assert np.all(s.force() == 0.0)
+    assert s.contacts[0] == 1  # overlapping, but the direction is undefined
+
+
+# --- Supplementary tutorial (ForEachNeighbor): three spheres on a line ----------------
+def test_tutorial_neighbour_example():
+    gd = golden("tutorial_neighbours.json")
+    pos = np.array(gd["positions"], dtype=np.float64)
+    p = c0_params(box_len=0.0)
+    s = sim.OracleSim(pos, np.full(3, gd["diameter"], dtype=np.float64), p)
+    for i, expect in enumerate(gd["neighbours"]):
+        assert list(s.neighbour_uids(i)) == expect
+        assert list(s.neighbour_uids(i, brute=True)) == expect
+    s.step()
+    assert list(s.nbr[:3]) == [len(e) for e in gd["neighbours"]]
+
+
+# --- Sec 4.4.3: 27-box search equals brute force; box index formula ---------------------
+def test_grid_matches_brute_force_on_c0_first_256():
+    pos, diam = inputs.plain(4096, 160.0, seed=0)
+    s = sim.OracleSim(pos, diam, c0_params())
+    lo, L, dims, box = s.grid()
+    assert L == 15.0
+    assert np.array_equal(lo, pos.min(axis=0))
+    b = np.floor((pos - lo) / L).astype(np.int64)
+    b = np.minimum(np.maximum(b, 0), dims - 1)
+    assert np.array_equal(box, b[:, 0] + dims[0] * (b[:, 1] + dims[1] * b[:, 2]))
+    for i in range(256):
+        g = s.neighbour_uids(i)
+        bf = s.neighbour_uids(i, brute=True)
+        assert np.array_equal(g, bf)
+        # brute force by numpy, independent of the oracle's loops
+        d = pos - pos[i]
+        d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
+        mask = d2 < L * L
+        mask[i] = False
+        assert set(np.nonzero(mask)[0].tolist()) == set(g.tolist())
+        # every neighbour lies in the 27-box neighbourhood of box(i)
+        assert np.all(np.abs(b[g.astype(np.int64)] - b[i]) <= 1)
+
+
+# --- Pairwise antisymmetry: net force vanishes ----------------------------------------
+def test_net_force_vanishes_on_c0():
+    pos, diam = inputs.plain(4096, 160.0, seed=0)
+    s = sim.OracleSim(pos, diam, c0_params())
+    s.step()
+    f = s.force()
+    assert np.linalg.norm(f.sum(axis=0)) <= 1e-12 * np.linalg.norm(f, axis=1).sum()
+    assert (s.contacts[:4096] > 0).mean() > 0.9  # dense start: almost every agent touches another
+
+
+# --- Worked two-body relaxation (Eq 4.1, threshold of Sec 5.5, F dt / m) ---------------
+def test_two_body_relaxation_iterates_closed_form():
+    p = c0_params(box_len=0.0, detect_static=True)
+    s = sim.OracleSim(np.array([[0.0, 0.0, 0.0], [6.0, 0.0, 0.0]]), np.array([10.0, 10.0]), p)
+    dist, disps = [], []
+    statics = []
+    for _ in range(6):
+        statics.append(tuple(s.is_static[:2]))
+        s.step()
+        dist.append(s.x[1] - s.x[0])
+        disps.append(s.dx[1])
+    # closed form: each step the pair separates by 2 * 0.1 * (k delta - sqrt(rbar delta)), rbar = 2.5
+    d, expect = 6.0, []
+    for _ in range(6):
+        delta = 10.0 - d
+        f = 2.0 * delta - math.sqrt(2.5 * delta)
+        if f > 1.8:
+            d = d + 2.0 * 0.1 * f
+        expect.append(d)
+    assert dist == pytest.approx(expect, rel=1e-14)
+    assert dist[:3] == pytest.approx([6.967544467966, 7.629849322245, 8.091067660297], abs=1e-11)
+    assert disps[:3] == pytest.approx([0.483772233983, 0.331152427139, 0.230609169026], abs=1e-11)
+    assert dist[3] == dist[2]
+    # static from the fifth iteration: iteration 3 moved nothing and each has one non-zero force
+    assert statics[:4] == [(0, 0)] * 4
+    assert statics[4] == (1, 1) and statics[5] == (1, 1)
+
+
+# --- Maximum displacement: cap on the Euclidean norm -----------------------------------
+def test_cap_branch():
+    # two d = 15 spheres 0.5 apart: delta = 14.5, rbar = 3.75
+    f = 2.0 * 14.5 - math.sqrt(3.75 * 14.5)
+    p = c0_params(box_len=0.0)
+    s = sim.OracleSim(np.array([[0.0, 0.0, 0.0], [0.5, 0.0, 0.0]]), np.array([15.0, 15.0]), p)
+    s.step()
+    assert s.fx[1] == pytest.approx(f, rel=1e-14)
+    assert s.dx[1] == pytest.approx(0.1 * f, rel=1e-14) and 0.1 * f < 3.0
+    d = sim.displacement(np.array([3.0, -4.0, 12.0]) * 10.0, 1.8, 0.01, 0.1, 3.0)
+    assert np.linalg.norm(d) == pytest.approx(3.0, rel=1e-15)
+    assert d / np.linalg.norm(d) == pytest.approx(np.array([3.0, -4.0, 12.0]) / 13.0, rel=1e-14)
+    # below the threshold nothing moves, including exactly at it
+    assert np.all(sim.displacement(np.array([1.8, 0.0, 0.0])) == 0.0)
+    assert sim.displacement(np.array([1.8000001, 0.0, 0.0]))[0] > 0.0
+
+
+# --- Static skip (Sec 5.5) is exact: detection on and off give identical trajectories ----
+def test_static_skip_is_exact_on_c0():
+    pos, diam = inputs.plain(4096, 160.0, seed=0)
+    a = sim.OracleSim(pos, diam, c0_params(detect_static=False))
+    b = sim.OracleSim(pos, diam, c0_params(detect_static=True))
+    skipped = 0
+    for _ in range(10):
+        skipped += int(b.is_static[:b.n].sum())
+        a.step(); b.step()
+        assert np.array_equal(a.pos(), b.pos())
+    assert skipped > 0
+
+
+def test_static_on_a_non_touching_lattice():
+    g = np.arange(6) * 16.0
+    zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+    pos = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+    s = sim.OracleSim(pos, np.full(pos.shape[0], 15.0), c0_params(detect_static=True))
+    s.step()
+    assert np.all(s.is_static[:s.n] == 1)
+    s.step()
+    assert np.all(s.nbr[:s.n] == -1)  # nothing computed on the second iteration
+
+
+def test_static_flags_match_brute_force_rule():
+    pos, diam = inputs.plain(1500, 120.0, seed=5)
+    pg = c0_params(detect_static=True)
+    pb = c0_params(detect_static=True, brute_force=True)
+    a = sim.OracleSim(pos, diam, pg)
+    b = sim.OracleSim(pos, diam, pb)
+    for _ in range(6):
+        a.step(); b.step()
+        assert np.array_equal(a.is_static[:a.n], b.is_static[:b.n])
+        assert np.array_equal(a.pos(), b.pos())
+
+
+# --- Storage-order and translation invariance -------------------------------------------
+def test_permutation_and_translation_invariance():
+    pos, diam = inputs.plain(2048, 130.0, seed=7)
+    pos = np.round(pos * 2.0 ** 30) / 2.0 ** 30  # on a grid where +1024 is exact
+    p = c0_params()
+    a = sim.OracleSim(pos, diam, p)
+    perm = np.random.default_rng(1).permutation(pos.shape[0])
+    b = sim.OracleSim(pos[perm], diam[perm], p, uid=np.arange(pos.shape[0])[perm])
+    c = sim.OracleSim(pos + 1024.0, diam, p)
+    a.step(); b.step(); c.step()
+    inv = np.argsort(perm)
+    assert np.array_equal(a.force(), b.force()[inv])
+    assert np.array_equal(a.nbr[:2048], b.nbr[:2048][inv])
+    assert np.array_equal(a.force(), c.force())
+    # committed positions differ only by the rounding of x + delta at the shifted magnitude
+    assert np.allclose(a.pos() + 1024.0, c.pos(), rtol=0, atol=2.5e-13)
+
+
+# --- Checkpoint and resume: 10 iterations = 5 + restore + 5 ----------------------------
+def test_checkpoint_resume_bitwise():
+    pos, diam, vol, growth = inputs.spheroid(300, seed=11, growth_scale=40.0)
+    p = c0_params(box_len=0.0, div_vol=inputs.division_volume(9.0), detect_static=True, seed=9)
+    a = sim.OracleSim(pos, diam, p, vol=vol, growth=growth, cap=4096)
+    a.step(10)
+    b = sim.OracleSim(pos, diam, p, vol=vol, growth=growth, cap=4096)
+    b.step(5)
+    n = b.n
+    c = sim.OracleSim(b.pos(), b.diam[:n], p, vol=b.vol[:n], growth=b.growth[:n], uid=b.uid[:n], cap=4096,
+                      next_uid=b.state.next_uid, is_static=b.is_static[:n], nz=b.nz[:n], iteration=b.iteration)
+    c.step(5)
+    assert a.n == c.n and a.n > 300
+    assert np.array_equal(a.pos(), c.pos())
+    assert np.array_equal(a.uid[:a.n], c.uid[:c.n])
+    assert np.array_equal(a.vol[:a.n], c.vol[:c.n])
+
+
+# --- Algorithm 2 grow-or-divide: volume closed form and lineage counts -------------------
+def test_growth_division_counts_follow_lineages():
+    pos, diam, vol, growth = inputs.spheroid(1000, seed=3)
+    vdiv = inputs.division_volume(12.0)
+    p = c0_params(box_len=0.0, div_vol=vdiv, seed=3)
+    s = sim.OracleSim(pos, diam, p, vol=vol, growth=growth, cap=8192)
+    T = 700
+    # each cell's lineage: grow by g per step below vdiv, otherwise halve (two identical cells)
+    v = vol.copy(); k = np.zeros(1000, dtype=np.int64)
+    expect = []
+    for _ in range(T):
+        div = v >= vdiv
+        v = np.where(div, 0.5 * v, v + growth)
+        k = k + div
+        expect.append(int((2 ** k).sum()))
+    got = []
+    for _ in range(T):
+        s.step()
+        got.append(s.n)
+    assert got == expect
+    assert got[-1] > 1000
+    # the first division happens on the step after ceil((V(12) - V(8)) / g) growth steps
+    tf = int(np.ceil((vdiv - vol) / growth).min())
+    assert got[tf - 1] == 1000 and got[tf] > 1000
+
+
+def test_division_invariants():
+    vdiv = inputs.division_volume(12.0)
+    pos = np.array([[0.0, 0.0, 0.0], [100.0, 0.0, 0.0]])
+    vol = np.array([vdiv + 1.0, 10.0])
+    diam = np.array([sim.diameter_from_volume(vol[0]), sim.diameter_from_volume(10.0)])
+    p = c0_params(box_len=0.0, div_vol=vdiv, seed=17, shift_frac=0.125)
+    s = sim.OracleSim(pos, diam, p, vol=vol, growth=np.array([1.0, 1.0]), cap=8)
+    s.step()
+    assert s.n == 3
+    assert s.uid[2] == 2 and s.is_new[2] == 1 and s.divided[0] == 1
+    assert s.vol[0] + s.vol[2] == vol[0]
+    mid = 0.5 * (s.pos()[0] + s.pos()[2])
+    assert np.allclose(mid, pos[0], atol=1e-15)
+    sep = np.linalg.norm(s.pos()[0] - s.pos()[2])
+    assert sep == pytest.approx(2 * 0.125 * diam[0] / 2, rel=1e-14)
+    assert s.diam[0] == pytest.approx(diam[0] / 2 ** (1 / 3), rel=1e-15)
+    u = (s.pos()[2] - s.pos()[0]) / sep
+    assert u == pytest.approx(sim.direction(17, 0, 0, 0), abs=1e-14)
+    # the other cell grew by exactly g
+    assert s.vol[1] == 11.0 and s.grew[1] == 1
+
+
+def _cr_cbrt(t):
+    """Correctly rounded cube root by exact rational comparison with the midpoints."""
+    c = t ** (1.0 / 3.0)
+    T = Fraction(t)
+    while (Fraction(c) + Fraction(math.nextafter(c, math.inf))) ** 3 / 8 < T:
+        c = math.nextafter(c, math.inf)
+    while (Fraction(c) + Fraction(math.nextafter(c, -math.inf))) ** 3 / 8 > T:
+        c = math.nextafter(c, -math.inf)
+    return c
+
+
+def test_diameter_from_volume_is_correctly_rounded():
+    rng = np.random.default_rng(0)
+    for v in list(rng.uniform(100.0, 3000.0, size=400)) + [math.pi * 512 / 6, math.pi * 1728 / 6]:
+        t = (6.0 * v) / math.pi
+        assert sim.diameter_from_volume(v) == _cr_cbrt(t)
+
+
+# --- Counter-based generator (Sec 7.1.4) and the division direction ----------------------
+def test_philox_known_answers():
+    for vec in golden("philox_kat.json")["vectors"]:
+        ctr = [int(v, 16) for v in vec["ctr"]]
+        key = [int(v, 16) for v in vec["key"]]
+        assert sim.philox4x32_10(ctr, key) == [int(v, 16) for v in vec["out"]]
+
+
+def test_direction_is_uniform_on_the_sphere():
+    m = 100_000
+    u = np.array([sim.direction(1234, 3, i, 7) for i in range(m)])
+    assert np.allclose(np.linalg.norm(u, axis=1), 1.0, atol=1e-15)
+    se = 1.0 / math.sqrt(m)
+    assert np.all(np.abs(u.mean(axis=0)) < 5 * math.sqrt(1 / 3) * se)
+    cov = u.T @ u / m
+    # Var(u_a^2) = 1/5 - 1/9 for a uniform direction; off-diagonals have variance 1/15
+    assert np.all(np.abs(np.diag(cov) - 1 / 3) < 5 * math.sqrt(1 / 5 - 1 / 9) * se)
+    off = cov[~np.eye(3, dtype=bool)]
+    assert np.all(np.abs(off) < 5 * math.sqrt(1 / 15) * se)
+
+
+# --- Fig 5.4 worked example: Morton convention (x in bit 0) -----------------------------
+def test_morton_worked_example():
+    gd = golden("fig5_4_morton.json")
+    nx, ny = gd["grid"]
+    codes = sorted(sim.morton2(x, y) for x in range(nx) for y in range(ny))
+    assert codes == gd["sorted_morton_codes"]
+    # gaps: (box counter, offset) whenever the sequence of in-grid codes jumps
+    offs, expect_offset = [], 0
+    for counter, code in enumerate(codes):
+        if code - counter != expect_offset or counter == 0:
+            offs.append([counter, code - counter]); expect_offset = code - counter
+    assert offs == gd["gap_offsets"]
+    assert list(np.cumsum(gd["agents_per_box_in_morton_order"])) == gd["inclusive_prefix_sum"]
+    assert [sim.morton3(1, 0, 0), sim.morton3(0, 1, 0), sim.morton3(0, 0, 1), sim.morton3(2, 0, 0)] == [1, 2, 4, 8]
+    assert sim.morton3(1023, 1023, 1023) == 2 ** 30 - 1
+
+
+# --- Spheroid statistics ------------------------------------------------------------------
+def test_histogram_counts_and_uniform_ball_density():
+    rng = np.random.default_rng(2)
+    n, R = 200_000, 300.0
+    pos = inputs.ball(n, R, rng) + np.array([10.0, -5.0, 7.0])
+    c, rg, rmax, h, cnt = sim.stats(pos, 400.0)
+    assert int(cnt.sum()) == n
+    assert np.allclose(c, [10.0, -5.0, 7.0], atol=3.0)
+    assert rg == pytest.approx(R * math.sqrt(3 / 5), rel=5e-3)
+    assert rmax <= R + np.linalg.norm(c - np.array([10.0, -5.0, 7.0])) + 1e-9
+    rho = 3 * n / (4 * math.pi * R ** 3) * 1000.0
+    inner = h[4:22]  # shells well inside R = 300 (bin width 12.5)
+    assert np.all(np.abs(inner / rho - 1.0) < 0.08)
+    assert np.all(h[25:] == 0.0)
+
+
+def test_histogram_overflow_goes_to_last_bin():
+    pos = np.array([[0.0, 0.0, 0.0], [1000.0, 0.0, 0.0]])
+    c, rg, rmax, h, cnt = sim.stats(pos, 400.0)
+    assert cnt[31] == 2 and cnt.sum() == 2  # both 500 um from the centroid
+
+
+# --- Surrogate MLP oracle: central differences --------------------------------------------
+def test_mlp_gradient_matches_central_differences():
+    rng = np.random.default_rng(0)
+    dims = mlp.DIMS
+    theta = np.concatenate([
+        np.concatenate([rng.normal(0, math.sqrt(2 / dims[i]), dims[i + 1] * dims[i]), rng.normal(0, 0.1, dims[i + 1])])
+        for i in range(len(dims) - 1)])
+    x = rng.normal(size=(64, 35)); y = rng.normal(size=(64, 32))
+    L, g = mlp.grads(theta, x, y)
+    assert L == pytest.approx(mlp.loss(theta, x, y), rel=1e-15)
+    idx = np.concatenate([rng.choice(theta.size, 300, replace=False), np.arange(theta.size - 32, theta.size)])
+    h = 1e-6
+    for i in idx:
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        fd = (mlp.loss(tp, x, y) - mlp.loss(tm, x, y)) / (2 * h)
+        # central differences: truncation O(h^2), rounding about eps * |L| / h
+        assert abs(fd - g[i]) <= 1e-6 * abs(g[i]) + 1e-9
+
+
+def test_mlp_gelu_and_adam_definitions():
+    x = np.array([-3.0, -1.0, 0.0, 0.5, 2.0])
+    phi = 0.5 * (1 + np.array([math.erf(v / math.sqrt(2)) for v in x]))
+    assert np.allclose(mlp.gelu(x), x * phi, rtol=1e-15)
+    # one Adam step with bias correction moves every coordinate by lr * sign(g) (|g| >> eps)
+    opt = mlp.Adam(np.zeros(3), lr=1e-3)
+    th = opt.step(np.array([0.5, -2.0, 1e-3]))
+    assert np.allclose(th, -1e-3 * np.sign([0.5, -2.0, 1e-3]), rtol=1e-4)
