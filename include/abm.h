@@ -1,0 +1,228 @@
+/*
+ * abm.h -- C ABI of the MI355X spherical-agent mechanics library (libabm.so).
+ *
+ * One iteration of the thesis's agent-based mechanics (arXiv 2503.10796):
+ *   - uniform-grid neighbour search: box length = largest agent diameter or a
+ *     user value, agent box from its centre, 27 surrounding boxes (Sec 4.4.3,
+ *     Sec 5.3.1), open boundary: the grid spans the agents' bounding box
+ *     (Sec 4.4.11);
+ *   - pairwise sphere-sphere force F_N = k*delta - gamma*sqrt(r*delta),
+ *     r = r1*r2/(r1+r2), along the centre line (Sec 4.5.1, Eq 4.1-4.2);
+ *   - displacement F*dt/m when |F| exceeds the adherence threshold, capped in
+ *     norm at the maximum displacement (Sec 5.5; Tutorial E.15);
+ *   - static-agent skip of the force calculation (Sec 5.5);
+ *   - grow-or-divide cell rule with appended daughters (Algorithm 2,
+ *     Sec 5.3.2);
+ *   - periodic Morton-order re-sort of agent storage (Sec 5.4.2, Fig 5.4);
+ *   - copy semantics: every agent reads the start-of-iteration state and new
+ *     agents appear in the next iteration (Sec 5.2.1).
+ * Plus batched independent simulations (parameter sweeps, Sec 4.3 execution
+ * modes C-E) and a surrogate MLP trained with BF16 matrix-core kernels.
+ *
+ * Conventions for every entry point:
+ *   - Return value: ABM_OK (0) or a negative ABM_ERR_* code; the message of
+ *     the last failure on the calling thread is abm_last_error().
+ *   - Pointers flagged "on_device" are HIP device pointers, otherwise host
+ *     pointers.  The caller owns every buffer it passes; the library reads or
+ *     writes it only during the call, in stream order on the handle's stream,
+ *     and has finished with it when the call returns.
+ *   - All device state of a handle lives inside the caller's workspace
+ *     (size from the *_workspace_bytes call, 256-byte aligned); the library
+ *     allocates no device memory in create/step/query.  The workspace must
+ *     outlive the handle.
+ *   - Handles are not thread-safe; one handle per thread at a time.
+ *   - Nothing falls back to the CPU: every step runs in HIP kernels.
+ */
+#ifndef ABM_H
+#define ABM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ABM_OK 0
+#define ABM_ERR_ARG (-1)       /* bad parameters or sizes */
+#define ABM_ERR_CAPACITY (-2)  /* agents or grid boxes would exceed the capacity */
+#define ABM_ERR_NONFINITE (-3) /* a non-finite position, diameter or force */
+#define ABM_ERR_HIP (-4)       /* HIP runtime failure */
+
+/* flags of abm_params.flags */
+#define ABM_DIAG 1u /* record forces, displacements and neighbour/contact counts */
+
+/* Model parameters of one simulation.
+ * dt, k, gamma: time step and the constants of Eq 4.1 (k = 2, gamma = 1 in the thesis).
+ * adherence: force threshold that |F| must exceed to move the agent (Sec 5.5; Table 4.2: 1.8).
+ * mass: agent mass in F*dt/m (Tutorial E.15 uses 0.1).
+ * max_disp: cap on the Euclidean norm of one step's displacement.
+ * box_len: grid box length; 0 = largest agent diameter (Sec 4.4.3).
+ * div_vol: > 0 enables Algorithm 2: cells grow by their growth rate per step
+ *          below this volume and divide at or above it; 0 = no growth.
+ * shift_frac: on division mother and daughter move shift_frac * r_mother in
+ *          opposite directions along a uniformly random unit vector.
+ * detect_static: 1 = skip the force of agents meeting the four conditions of Sec 5.5.
+ * resort_every: Morton re-sort of agent storage every so many iterations (0 = never).
+ * seed, sim_id: key and counter word of the Philox4x32-10 division directions. */
+typedef struct abm_params {
+    double dt, k, gamma, adherence, mass, max_disp;
+    double box_len;
+    double div_vol;
+    double shift_frac;
+    int32_t detect_static;
+    int32_t resort_every;
+    uint64_t seed;
+    uint32_t sim_id;
+    uint32_t flags;
+} abm_params;
+
+/* Fields for abm_*_query.  Arrays are in the library's current storage order
+ * (it changes on a Morton re-sort); match agents across calls by ABM_UID.
+ * Element types: POS, FORCE, DISP: 3 doubles per agent (x,y,z interleaved);
+ * DIAM, VOL, GROWTH: double; UID: uint64; STATIC: uint8; NZ, NBR_COUNT,
+ * CONTACT_COUNT: int32; BOX: int64 linear box id (x fastest) in the grid of
+ * the last iteration.  FORCE, DISP, NBR_COUNT, CONTACT_COUNT and BOX are the
+ * values of the last iteration run with ABM_DIAG set (NBR_COUNT and
+ * CONTACT_COUNT are -1 and FORCE is 0 for agents skipped as static). */
+enum abm_field {
+    ABM_POS = 0, ABM_DIAM = 1, ABM_VOL = 2, ABM_GROWTH = 3, ABM_UID = 4, ABM_STATIC = 5,
+    ABM_NZ = 6, ABM_NBR_COUNT = 7, ABM_CONTACT_COUNT = 8, ABM_FORCE = 9, ABM_DISP = 10,
+    ABM_BOX = 11
+};
+
+typedef struct abm_batch abm_batch;
+typedef struct abm_batch abm_pop; /* a population is a batch of one simulation */
+
+/* ------------------------------------------------------------------------- */
+/* Batched simulations: n_sims independent populations advanced together,     */
+/* one captured HIP graph launch per iteration.                                */
+/* ------------------------------------------------------------------------- */
+
+/* Workspace bytes for n_sims simulations with these agent and grid-box
+ * capacities (arrays of n_sims).  Returns 0 for invalid sizes. */
+size_t abm_batch_workspace_bytes(int n_sims, const int64_t *capacity, const int64_t *box_capacity);
+
+/* Create a batch.  per_sim: n_sims parameter sets.  n0: initial agents per
+ * simulation.  xyz (sum(n0) x 3, simulation-major), diam, vol, growth and uid
+ * (sum(n0) each) are host or device arrays per inputs_on_device; vol = NULL
+ * derives pi d^3/6, growth = NULL means 0, uid = NULL numbers each
+ * simulation's agents 0..n0-1.  Capacities as in abm_batch_workspace_bytes.
+ * hip_stream: stream for all work of this handle (NULL = default stream).
+ * Errors: ABM_ERR_ARG (n0 > capacity, bad parameters, workspace too small),
+ * ABM_ERR_NONFINITE (non-finite input), ABM_ERR_HIP. */
+int abm_batch_create(int n_sims, const abm_params *per_sim, const int64_t *n0, const double *xyz,
+                     const double *diam, const double *vol, const double *growth, const uint64_t *uid,
+                     int inputs_on_device, const int64_t *capacity, const int64_t *box_capacity,
+                     void *workspace, size_t ws_bytes, void *hip_stream, abm_batch **out);
+
+/* Restore per-agent static flags and non-zero-force counts, the next uid and
+ * the iteration counter of every simulation (checkpoint resume).  is_static
+ * (uint8) and nz (int32) are sum(n) arrays in the creation order; next_uid
+ * has n_sims entries.  Must be called right after abm_batch_create. */
+int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const int32_t *nz, const uint64_t *next_uid,
+                      int64_t iteration, int on_device);
+
+/* Advance every simulation by n_iter iterations (stream-ordered, graph
+ * launched; the call waits for the stream once at the end to read the status).
+ * ABM_ERR_CAPACITY: a division or the grid would exceed a capacity; the
+ * batch is left at the last completed iteration.  ABM_ERR_NONFINITE: a
+ * non-finite position or force appeared. */
+int abm_batch_step(abm_batch *b, int n_iter);
+
+/* Current agent counts (n_sims entries, host). */
+int abm_batch_num_agents(abm_batch *b, int64_t *n_out);
+
+/* Copy one field of simulation `sim` into dst (capacity `cap` elements of the
+ * field's type); *n_out receives the number of agents. */
+int abm_batch_query(abm_batch *b, int sim, int field, void *dst, int dst_on_device, int64_t cap, int64_t *n_out);
+
+/* Grid of the last iteration of simulation `sim`: lo[3], L, dims[3]. */
+int abm_batch_grid(abm_batch *b, int sim, double lo[3], double *L, int64_t dims[3]);
+
+/* Spheroid statistics of every simulation: centroid (n_sims x 3), radius of
+ * gyration and largest distance from the centroid (n_sims each), and the
+ * 32-bin radial density histogram on [0, hist_rmax) in agents per 1000 um^3
+ * (agents beyond hist_rmax go to the last bin) (n_sims x 32).  Host arrays;
+ * any may be NULL.  FP64 reductions in a fixed order (deterministic). */
+int abm_batch_stats(abm_batch *b, double hist_rmax, double *centroid, double *r_gyr, double *r_max, float *hist);
+
+/* Histograms only, to host or device memory (n_sims x 32 floats). */
+int abm_batch_hist(abm_batch *b, double hist_rmax, float *out, int out_on_device);
+
+/* Autotune the launch schedule (threads per block of the force sweep and
+ * the Morton re-sort period when a simulation sets resort_every < 0) by
+ * timing n_trial_iters iterations per candidate on a scratch copy of the
+ * state; the batch itself is left unchanged.  Writes the chosen block size
+ * to *block_out (may be NULL). */
+int abm_batch_tune(abm_batch *b, int n_trial_iters, int *block_out);
+
+/* Set the force-sweep block size (64, 128, 256, 512 or 1024). */
+int abm_batch_set_block(abm_batch *b, int block);
+
+/* Measurement: with timing on, abm_batch_step replays each iteration as two
+ * graph launches (the force sweep, then the rest) with HIP events recorded on
+ * the handle's stream around the sweep.  abm_batch_sweep_time returns the
+ * summed sweep milliseconds and the number of sweeps since its last call
+ * (and resets both).  Results are identical with timing on or off. */
+int abm_batch_set_timing(abm_batch *b, int on);
+int abm_batch_sweep_time(abm_batch *b, double *ms_total, int64_t *n_sweeps);
+
+/* Release the handle (the workspace stays the caller's). */
+int abm_batch_destroy(abm_batch *b);
+
+/* ------------------------------------------------------------------------- */
+/* Single population: thin wrappers of the batch calls with n_sims = 1.       */
+/* ------------------------------------------------------------------------- */
+size_t abm_pop_workspace_bytes(const abm_params *p, int64_t capacity, int64_t box_capacity);
+int abm_pop_create(const abm_params *p, int64_t n, const double *xyz, const double *diam, const double *vol,
+                   const double *growth, const uint64_t *uid, int inputs_on_device, void *workspace,
+                   size_t ws_bytes, int64_t capacity, int64_t box_capacity, void *hip_stream, abm_pop **out);
+int abm_pop_step(abm_pop *p, int n_iter);
+int abm_pop_num_agents(abm_pop *p, int64_t *n);
+int abm_pop_query(abm_pop *p, int field, void *dst, int dst_on_device, int64_t cap, int64_t *n_out);
+int abm_pop_stats(abm_pop *p, double hist_rmax, double centroid[3], double *r_gyr, double *r_max, float hist[32]);
+int abm_pop_destroy(abm_pop *p);
+
+/* ------------------------------------------------------------------------- */
+/* Surrogate MLP (35 -> 256 -> 256 -> 256 -> 32, exact-erf GELU on the hidden */
+/* layers), BF16 matrix-core GEMMs with FP32 accumulation, FP32 master        */
+/* weights, mean-squared-error loss, Adam.  Parameter layout of get/set: per  */
+/* layer W as [out, in] row-major then b as [out].                            */
+/* ------------------------------------------------------------------------- */
+typedef struct abm_mlp abm_mlp;
+
+/* Workspace bytes for an MLP with these layer widths and maximum batch. */
+size_t abm_mlp_workspace_bytes(const int *dims, int n_dims, int max_batch);
+
+/* Create with He-normal weights (std sqrt(2/fan_in)) and zero biases drawn
+ * from Philox4x32-10 keyed by seed.  dims must be 35,256,256,256,32 or any
+ * widths that are multiples of 16 except the input width. */
+int abm_mlp_create(const int *dims, int n_dims, int max_batch, uint64_t seed, void *workspace, size_t ws_bytes,
+                   void *hip_stream, abm_mlp **out);
+
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the MSE of a batch
+ * (x: batch x dims[0], y: batch x dims[last], device FP32).  The loss is
+ * written to *loss_out (host) when loss_out is not NULL. */
+int abm_mlp_train_step(abm_mlp *m, const float *x, const float *y, int batch, float lr, float *loss_out);
+
+/* Loss and gradient (FP32, parameter layout above, device pointer) of a batch
+ * without updating the weights. */
+int abm_mlp_grads(abm_mlp *m, const float *x, const float *y, int batch, float *grads_out, float *loss_out);
+
+/* Forward pass: y = MLP(x) for a batch (device FP32). */
+int abm_mlp_infer(abm_mlp *m, const float *x, float *y, int batch);
+
+/* Copy the FP32 master parameters out of / into the handle (device FP32). */
+int abm_mlp_get_params(abm_mlp *m, float *dst, size_t n);
+int abm_mlp_set_params(abm_mlp *m, const float *src, size_t n);
+size_t abm_mlp_num_params(abm_mlp *m);
+int abm_mlp_destroy(abm_mlp *m);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *abm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ABM_H */

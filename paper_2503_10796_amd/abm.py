@@ -1,0 +1,267 @@
+"""ctypes binding of libabm (the C ABI in include/abm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of ``libabm.so``.  PyTorch provides device memory (the workspace) and the
+stream.  Importing this module fails loudly when the library is not built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libabm.so")
+
+POS, DIAM, VOL, GROWTH, UID, STATIC, NZ, NBR_COUNT, CONTACT_COUNT, FORCE, DISP, BOX = range(12)
+_FIELD_TYPES = {POS: (np.float64, 3), DIAM: (np.float64, 1), VOL: (np.float64, 1), GROWTH: (np.float64, 1),
+                UID: (np.uint64, 1), STATIC: (np.uint8, 1), NZ: (np.int32, 1), NBR_COUNT: (np.int32, 1),
+                CONTACT_COUNT: (np.int32, 1), FORCE: (np.float64, 3), DISP: (np.float64, 3), BOX: (np.int64, 1)}
+DIAG = 1
+
+OK, ERR_ARG, ERR_CAPACITY, ERR_NONFINITE, ERR_HIP = 0, -1, -2, -3, -4
+
+
+class AbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libabm error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_double), ("k", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("adherence", ctypes.c_double), ("mass", ctypes.c_double), ("max_disp", ctypes.c_double),
+        ("box_len", ctypes.c_double), ("div_vol", ctypes.c_double), ("shift_frac", ctypes.c_double),
+        ("detect_static", ctypes.c_int32), ("resort_every", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("sim_id", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+    ]
+
+
+def params(dt=0.01, k=2.0, gamma=1.0, adherence=1.8, mass=0.1, max_disp=3.0, box_len=15.0, div_vol=0.0,
+           shift_frac=0.125, detect_static=False, resort_every=0, seed=0, sim_id=0, diag=False):
+    return Params(dt, k, gamma, adherence, mass, max_disp, box_len, div_vol, shift_frac, int(bool(detect_static)),
+                  int(resort_every), int(seed), int(sim_id), DIAG if diag else 0)
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i64p = ctypes.POINTER(ctypes.c_int64)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2503_10796_amd.build` "
+                               "(the HIP library is the only compute path)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.abm_last_error.restype = ctypes.c_char_p
+        L.abm_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.abm_batch_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p]
+        L.abm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Params), _i64p, _vp, _vp, _vp, _vp, _vp,
+                                       ctypes.c_int, _i64p, _i64p, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
+        L.abm_batch_restore.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int]
+        L.abm_batch_step.argtypes = [_vp, ctypes.c_int]
+        L.abm_batch_num_agents.argtypes = [_vp, _i64p]
+        L.abm_batch_query.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64, _i64p]
+        L.abm_batch_grid.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
+        L.abm_batch_stats.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+        L.abm_batch_hist.argtypes = [_vp, ctypes.c_double, _vp, ctypes.c_int]
+        L.abm_batch_tune.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.abm_batch_set_block.argtypes = [_vp, ctypes.c_int]
+        L.abm_batch_destroy.argtypes = [_vp]
+        L.abm_batch_set_timing.argtypes = [_vp, ctypes.c_int]
+        L.abm_batch_sweep_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
+        L.abm_pop_workspace_bytes.restype = ctypes.c_size_t
+        L.abm_pop_workspace_bytes.argtypes = [ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int64]
+        L.abm_pop_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, ctypes.c_int,
+                                     _vp, ctypes.c_size_t, ctypes.c_int64, ctypes.c_int64, _vp, ctypes.POINTER(_vp)]
+        L.abm_pop_step.argtypes = [_vp, ctypes.c_int]
+        L.abm_pop_num_agents.argtypes = [_vp, _i64p]
+        L.abm_pop_query.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64, _i64p]
+        L.abm_pop_stats.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+        L.abm_pop_destroy.argtypes = [_vp]
+        _lib = L
+    return _lib
+
+
+def check(rc):
+    if rc != 0:
+        raise AbmError(rc, lib().abm_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _arg(a, dtype, on_device, keep):
+    """Host numpy array or device tensor -> pointer (kept alive in `keep`)."""
+    if a is None:
+        return None
+    if on_device:
+        keep.append(a)
+        return ctypes.c_void_p(a.data_ptr())
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    keep.append(arr)
+    return arr.ctypes.data_as(ctypes.c_void_p)
+
+
+class Batch:
+    """Independent simulations advanced together (one graph launch per iteration).
+
+    pos, diam, vol, growth, uid: concatenated over simulations (simulation-major),
+    numpy arrays (host) or CUDA tensors (device, float64/uint64)."""
+
+    def __init__(self, plist, n0, pos, diam, vol=None, growth=None, uid=None, capacity=None,
+                 box_capacity=None, stream=None):
+        torch = _torch()
+        L = lib()
+        self.n_sims = len(plist)
+        n0 = np.asarray(n0, dtype=np.int64)
+        cap = np.asarray(capacity if capacity is not None else n0, dtype=np.int64).reshape(-1)
+        if cap.size == 1 and self.n_sims > 1:
+            cap = np.full(self.n_sims, cap[0], dtype=np.int64)
+        bcap = (np.asarray(box_capacity, dtype=np.int64).reshape(-1) if box_capacity is not None
+                else 2 * cap + 65536)
+        if bcap.size == 1 and self.n_sims > 1:
+            bcap = np.full(self.n_sims, bcap[0], dtype=np.int64)
+        self._n0, self._cap, self._bcap = n0, cap, bcap
+        self._params = (Params * self.n_sims)(*plist)
+        nbytes = L.abm_batch_workspace_bytes(self.n_sims, cap.ctypes.data_as(_i64p), bcap.ctypes.data_as(_i64p))
+        if nbytes == 0:
+            raise AbmError(ERR_ARG, "invalid capacities")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        on_dev = hasattr(pos, "data_ptr")
+        keep = []
+        h = ctypes.c_void_p()
+        self._stream = _stream_handle(stream)
+        rc = L.abm_batch_create(self.n_sims, self._params, n0.ctypes.data_as(_i64p),
+                                _arg(pos, np.float64, on_dev, keep), _arg(diam, np.float64, on_dev, keep),
+                                _arg(vol, np.float64, on_dev, keep), _arg(growth, np.float64, on_dev, keep),
+                                _arg(uid, np.uint64, on_dev, keep), int(on_dev), cap.ctypes.data_as(_i64p),
+                                bcap.ctypes.data_as(_i64p), ctypes.c_void_p(self.workspace.data_ptr()),
+                                nbytes + 256, self._stream, ctypes.byref(h))
+        check(rc)
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.abm_batch_destroy(h)
+            self.h = None
+
+    def close(self):
+        self.__del__()
+
+    def step(self, n_iter=1):
+        check(lib().abm_batch_step(self.h, int(n_iter)))
+
+    def num_agents(self):
+        out = np.zeros(self.n_sims, dtype=np.int64)
+        check(lib().abm_batch_num_agents(self.h, out.ctypes.data_as(_i64p)))
+        return out
+
+    def query(self, field, sim=0):
+        dt, width = _FIELD_TYPES[field]
+        n = int(self.num_agents()[sim])
+        out = np.zeros((max(n, 1), width) if width > 1 else max(n, 1), dtype=dt)
+        got = ctypes.c_int64(0)
+        check(lib().abm_batch_query(self.h, int(sim), int(field), out.ctypes.data_as(ctypes.c_void_p), 0,
+                                    max(n, 1), ctypes.byref(got)))
+        return out[: got.value]
+
+    def query_device(self, field, dst, sim=0):
+        got = ctypes.c_int64(0)
+        dt, width = _FIELD_TYPES[field]
+        check(lib().abm_batch_query(self.h, int(sim), int(field), ctypes.c_void_p(dst.data_ptr()), 1,
+                                    dst.numel() // width, ctypes.byref(got)))
+        return got.value
+
+    def grid(self, sim=0):
+        lo = np.zeros(3)
+        L = ctypes.c_double(0)
+        dims = np.zeros(3, dtype=np.int64)
+        check(lib().abm_batch_grid(self.h, int(sim), lo.ctypes.data_as(ctypes.c_void_p), ctypes.byref(L),
+                                   dims.ctypes.data_as(ctypes.c_void_p)))
+        return lo, L.value, dims
+
+    def stats(self, hist_rmax=400.0):
+        c = np.zeros((self.n_sims, 3)); rg = np.zeros(self.n_sims); rm = np.zeros(self.n_sims)
+        h = np.zeros((self.n_sims, 32), dtype=np.float32)
+        check(lib().abm_batch_stats(self.h, float(hist_rmax), c.ctypes.data_as(ctypes.c_void_p),
+                                    rg.ctypes.data_as(ctypes.c_void_p), rm.ctypes.data_as(ctypes.c_void_p),
+                                    h.ctypes.data_as(ctypes.c_void_p)))
+        return c, rg, rm, h
+
+    def hist_device(self, out, hist_rmax=400.0):
+        check(lib().abm_batch_hist(self.h, float(hist_rmax), ctypes.c_void_p(out.data_ptr()), 1))
+
+    def restore(self, is_static=None, nz=None, next_uid=None, iteration=0):
+        keep = []
+        check(lib().abm_batch_restore(self.h, _arg(is_static, np.uint8, False, keep), _arg(nz, np.int32, False, keep),
+                                      _arg(next_uid, np.uint64, False, keep), int(iteration), 0))
+
+    def tune(self, n_trial_iters=3):
+        b = ctypes.c_int(0)
+        check(lib().abm_batch_tune(self.h, int(n_trial_iters), ctypes.byref(b)))
+        return b.value
+
+    def set_block(self, block):
+        check(lib().abm_batch_set_block(self.h, int(block)))
+
+    def set_timing(self, on=True):
+        check(lib().abm_batch_set_timing(self.h, int(bool(on))))
+
+    def sweep_time(self):
+        """(summed sweep milliseconds, number of sweeps) since the last call."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        check(lib().abm_batch_sweep_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+class Population(Batch):
+    """One simulation (the abm_pop_* entry points)."""
+
+    def __init__(self, p, pos, diam, vol=None, growth=None, uid=None, capacity=None, box_capacity=None,
+                 stream=None):
+        torch = _torch()
+        L = lib()
+        self.n_sims = 1
+        n = int(pos.shape[0])
+        cap = int(capacity if capacity is not None else n)
+        bcap = int(box_capacity if box_capacity is not None else 2 * cap + 65536)
+        self._params = (Params * 1)(p)
+        nbytes = L.abm_pop_workspace_bytes(self._params, cap, bcap)
+        if nbytes == 0:
+            raise AbmError(ERR_ARG, "invalid capacities")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        on_dev = hasattr(pos, "data_ptr")
+        keep = []
+        h = ctypes.c_void_p()
+        self._stream = _stream_handle(stream)
+        check(L.abm_pop_create(self._params, n, _arg(pos, np.float64, on_dev, keep), _arg(diam, np.float64, on_dev, keep),
+                               _arg(vol, np.float64, on_dev, keep), _arg(growth, np.float64, on_dev, keep),
+                               _arg(uid, np.uint64, on_dev, keep), int(on_dev),
+                               ctypes.c_void_p(self.workspace.data_ptr()), nbytes + 256, cap, bcap, self._stream,
+                               ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n_iter=1):
+        check(lib().abm_pop_step(self.h, int(n_iter)))
+
+    def query(self, field, sim=0):
+        dt, width = _FIELD_TYPES[field]
+        n = int(self.num_agents()[0])
+        out = np.zeros((max(n, 1), width) if width > 1 else max(n, 1), dtype=dt)
+        got = ctypes.c_int64(0)
+        check(lib().abm_pop_query(self.h, int(field), out.ctypes.data_as(ctypes.c_void_p), 0, max(n, 1),
+                                  ctypes.byref(got)))
+        return out[: got.value]

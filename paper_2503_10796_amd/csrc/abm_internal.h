@@ -1,0 +1,161 @@
+// abm_internal.h -- device data layout and helpers of libabm (gfx950).
+//
+// Every simulation of a batch owns a contiguous agent range [a_off, a_off+cap)
+// of the flattened structure-of-arrays state and a grid-box range.  Positions
+// are FP64 and double-buffered (the force sweep reads the start-of-iteration
+// buffer and writes the other one: copy semantics, Sec 5.2.1).  The other
+// per-agent fields are double-buffered only for the periodic Morton re-sort.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "abm.h"
+
+namespace abm {
+
+constexpr int kTile = 256;           // agents per work tile
+constexpr int kBoxTile = 1024;       // boxes per scan tile (256 threads x 4)
+constexpr int kMaxSims = 4096;
+constexpr int kDimX = 2048, kDimY = 2048, kDimZ = 1024;  // packed box key 11/11/10 bits
+
+// per-agent flag bits (flags[]): static for the coming iteration, position
+// buffers differ, and what changed in the last iteration (moved, grew,
+// divided, new) -- kept in the flags so they follow the Morton re-sort.
+constexpr uint8_t kStatic = 1;
+constexpr uint8_t kBufDiff = 2;
+constexpr uint8_t kMoved = 4, kGrew = 8, kDivided = 16, kNew = 32;
+constexpr uint8_t kChgMask = kMoved | kGrew | kDivided | kNew;
+
+// error bits (SimDesc::err, Ctl::err)
+constexpr int kErrCapacity = 1, kErrNonfinite = 2, kErrGrid = 4;
+
+struct alignas(256) SimDesc {
+    // set at creation
+    int64_t a_off, cap;      // agent range
+    int64_t b_off, box_cap;  // count/dirty/mrank range
+    int64_t sb_off;          // box_start range: box_cap + 1 entries
+    double dt, k, gamma, adherence, mass, max_disp, box_len, div_vol, shift_frac;
+    int32_t detect_static, resort_every;
+    uint64_t seed;
+    uint32_t sim_id, flags;
+    // dynamic
+    int64_t n, n_start, next_uid, n_div;
+    double lo[3], hi[3], L;
+    double L_prev;  // box length of the previous grid (static rule radius)
+    int32_t dims[3];
+    int32_t err;
+    int64_t nboxes;
+    unsigned long long enc_lo[3], enc_hi[3], enc_maxd;
+    unsigned int nonfinite;
+    float e_delta;  // bound on the FP32 error of an overlap in this grid
+};
+
+struct alignas(256) Ctl {
+    int64_t iter;
+    int32_t pos_par, lay_par;
+    int32_t err;
+    int32_t abort;
+    uint32_t n_fix;
+    uint32_t n_unc_pairs;  // statistics: agents sent to the FP64 path
+    int64_t total_tiles, total_btiles, total_utiles;
+    int32_t resort_now;
+    int32_t any_growth;
+};
+
+// Device pointers of one batch (passed by value to every kernel).
+struct Dev {
+    int n_sims;
+    int resort_every;
+    SimDesc *sims;
+    Ctl *ctl;
+    int64_t *tile_begin;   // n_sims + 1: prefix of agent tiles
+    int64_t *btile_begin;  // n_sims + 1: prefix of box tiles
+    int64_t *utile_begin;  // n_sims + 1: prefix of uid tiles
+    int64_t *a_begin;      // n_sims + 1: agent range starts (for agent -> sim)
+    double *pos[2];        // each 3*A: x block, y block, z block
+    double *diam[2], *vol[2], *growth[2];
+    uint64_t *uid[2];
+    uint8_t *flags[2], *nz[2];
+    uint8_t *stage8;  // byte staging for host transfers (free between steps)
+    uint32_t *key, *rank;
+    float4 *payload;
+    uint32_t *sorted_idx;
+    int32_t *nbr, *contacts;
+    double *force, *disp;  // 3*A interleaved
+    int64_t *boxid;
+    uint32_t *count, *box_start, *mrank;
+    uint8_t *dirty;   // boxes holding the start position of a changed agent
+    uint8_t *arrive;  // boxes of the new grid holding a changed agent
+    uint32_t *tile_sum, *tile_off;
+    uint32_t *fix_list;
+    uint32_t *divflag, *divrank;
+    double *stat_part;  // per agent tile: 6 doubles
+    unsigned int *hist_cnt;  // n_sims x 32
+    int64_t A;             // total agent capacity
+};
+
+// ---------------------------------------------------------------- helpers
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Tile t -> simulation (tile prefix `begin` has n_sims + 1 entries, begin[0] = 0).
+__device__ inline int find_sim(const int64_t *__restrict__ begin, int n_sims, int64_t t) {
+    int lo = 0, hi = n_sims;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (begin[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Order-preserving map of doubles to unsigned integers (for atomic min/max).
+__device__ inline unsigned long long enc_double(double v) {
+    unsigned long long b = __double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__host__ __device__ inline double dec_double(unsigned long long e) {
+    unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+    double v;
+    memcpy(&v, &b, sizeof v);
+    return v;
+}
+
+// Box coordinate of v (floor((v-lo)/L), clamped to [0, dim-1]), FP64 division.
+__device__ inline int box_coord(double v, double lo, double L, int dim) {
+    double q = floor((v - lo) / L);
+    int b = (int)q;
+    if (q < 0.0) b = 0;
+    if (q > (double)(dim - 1)) b = dim - 1;
+    return b;
+}
+
+__device__ inline uint32_t pack_key(int bx, int by, int bz) {
+    return (uint32_t)bx | ((uint32_t)by << 11) | ((uint32_t)bz << 22);
+}
+__device__ inline void unpack_key(uint32_t k, int &bx, int &by, int &bz) {
+    bx = (int)(k & 2047u);
+    by = (int)((k >> 11) & 2047u);
+    bz = (int)(k >> 22);
+}
+__device__ inline int64_t linear_box(int bx, int by, int bz, const int32_t dims[3]) {
+    return (int64_t)bx + (int64_t)dims[0] * ((int64_t)by + (int64_t)dims[1] * (int64_t)bz);
+}
+
+// Box-relative FP32 coordinate of an agent (shared by the scatter and sweep,
+// so that an agent's own payload and its view of itself are bitwise equal).
+__device__ inline float rel_coord(double v, double lo, double L, int b) {
+    double origin = lo + (double)b * L;
+    return (float)(v - origin);
+}
+
+// Host-side launch helpers implemented in the .hip files.
+void launch_iteration(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, int sweep_block, bool diag,
+                      bool any_growth, bool any_static, bool resort);
+void launch_grid_build(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool any_static);
+void launch_sweep(const Dev &d, hipStream_t s, int grid_agents, int sweep_block, bool diag);
+void launch_after_sweep(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool diag, bool any_growth,
+                        bool any_static, bool resort);
+void launch_stats(const Dev &d, hipStream_t s, int grid_agents, double hist_rmax, double *out_dev);
+void launch_gather_pos(const Dev &d, hipStream_t s, int sim, double *dst, int64_t n, int64_t a_off);
+void launch_scatter_init(const Dev &d, hipStream_t s, int grid_agents);
+
+}  // namespace abm
