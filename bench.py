@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--agents", type=int, default=100_000_000)
     ap.add_argument("--workload", choices=["uniform", "relaxed"], default="uniform")
     ap.add_argument("--resort-every", type=int, default=10)
-    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--sweep-grid", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-agents", type=int, default=1_000_000)
     ap.add_argument("--cpu-sample-iters", type=int, default=5)
@@ -126,7 +126,7 @@ def main():
     p = abm.params(box_len=15.0, resort_every=args.resort_every, detect_static=(args.workload == "relaxed"))
     pop = abm.Population(p, pos, diam, capacity=n, box_capacity=box_cap)
     del pos, diam
-    pop.set_block(args.block)
+    pop.set_sweep_grid(args.sweep_grid)
     pop.set_timing(True)  # graphs are captured during the warmup
     torch.cuda.synchronize()
     log(f"[bench] population created; workspace {pop.workspace.numel() / 2**30:.1f} GiB")
@@ -164,7 +164,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": workload, "agents": n, "box_len_um": 15.0, "grid_boxes": nboxes,
-                   "static_fraction_end": static_frac, "sweep_block": args.block},
+                   "static_fraction_end": static_frac, "sweep_workgroups": args.sweep_grid},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sweep", "kernel_ms": sweep_avg_s * 1e3,

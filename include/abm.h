@@ -150,15 +150,17 @@ int abm_batch_stats(abm_batch *b, double hist_rmax, double *centroid, double *r_
 /* Histograms only, to host or device memory (n_sims x 32 floats). */
 int abm_batch_hist(abm_batch *b, double hist_rmax, float *out, int out_on_device);
 
-/* Autotune the launch schedule (threads per block of the force sweep and
- * the Morton re-sort period when a simulation sets resort_every < 0) by
- * timing n_trial_iters iterations per candidate on a scratch copy of the
- * state; the batch itself is left unchanged.  Writes the chosen block size
- * to *block_out (may be NULL). */
-int abm_batch_tune(abm_batch *b, int n_trial_iters, int *block_out);
+/* Autotune the launch schedule (the number of persistent workgroups of the
+ * force sweep, and the Morton re-sort period when simulation 0 sets
+ * resort_every < 0) by timing n_trial_iters iterations per candidate from a
+ * snapshot of the state; the batch is restored afterwards, so results are
+ * unchanged.  This call allocates (and frees) one snapshot of the workspace.
+ * Writes the chosen workgroup count to *grid_out (may be NULL). */
+int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out);
 
-/* Set the force-sweep block size (64, 128, 256, 512 or 1024). */
-int abm_batch_set_block(abm_batch *b, int block);
+/* Set the number of persistent workgroups of the force sweep (a multiple of
+ * 8, one share per XCD; default 2048). */
+int abm_batch_set_sweep_grid(abm_batch *b, int workgroups);
 
 /* Measurement: with timing on, abm_batch_step replays each iteration as two
  * graph launches (the force sweep, then the rest) with HIP events recorded on

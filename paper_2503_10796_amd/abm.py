@@ -68,7 +68,7 @@ def lib():
         L.abm_batch_stats.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
         L.abm_batch_hist.argtypes = [_vp, ctypes.c_double, _vp, ctypes.c_int]
         L.abm_batch_tune.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-        L.abm_batch_set_block.argtypes = [_vp, ctypes.c_int]
+        L.abm_batch_set_sweep_grid.argtypes = [_vp, ctypes.c_int]
         L.abm_batch_destroy.argtypes = [_vp]
         L.abm_batch_set_timing.argtypes = [_vp, ctypes.c_int]
         L.abm_batch_sweep_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
@@ -213,8 +213,8 @@ class Batch:
         check(lib().abm_batch_tune(self.h, int(n_trial_iters), ctypes.byref(b)))
         return b.value
 
-    def set_block(self, block):
-        check(lib().abm_batch_set_block(self.h, int(block)))
+    def set_sweep_grid(self, workgroups):
+        check(lib().abm_batch_set_sweep_grid(self.h, int(workgroups)))
 
     def set_timing(self, on=True):
         check(lib().abm_batch_set_timing(self.h, int(bool(on))))

@@ -52,7 +52,7 @@ struct Carver {
 };
 
 struct Layout {
-    size_t sims, ctl, tile_begin, btile_begin, utile_begin, a_begin;
+    size_t sims, ctl, tile_begin, btile_begin, utile_begin, a_begin, wblk_begin, bnd, blist;
     size_t pos[2], diam[2], vol[2], growth[2], uid[2], flags[2], nz[2];
     size_t stage8, key, rank, payload, sorted_idx, nbr, contacts, force, disp, boxid;
     size_t count, box_start, mrank, dirty, arrive, tile_sum, tile_off, fix_list, divflag, divrank;
@@ -83,6 +83,8 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
     L.btile_begin = c.take<int64_t>(n_sims + 1);
     L.utile_begin = c.take<int64_t>(n_sims + 1);
     L.a_begin = c.take<int64_t>(n_sims + 1);
+    L.wblk_begin = c.take<int64_t>(n_sims + 1);
+    L.bnd = c.take<unsigned long long>((size_t)n_sims * kBndSlots * 7);
     for (int b = 0; b < 2; ++b) {
         L.pos[b] = c.take<double>(3 * A);
         L.diam[b] = c.take<double>(A);
@@ -105,6 +107,7 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
     L.count = c.take<uint32_t>(B);
     L.box_start = c.take<uint32_t>(SB);
     L.mrank = c.take<uint32_t>(B);
+    L.blist = c.take<uint32_t>(B);
     L.dirty = c.take<uint8_t>(B);
     L.arrive = c.take<uint8_t>(B);
     L.tile_sum = c.take<uint32_t>(ST);
@@ -192,7 +195,7 @@ struct abm_batch {
     hipStream_t cap_stream = nullptr;  // private stream used only to capture the graph
     std::vector<SimDesc> host_sims;
     int64_t A = 0, T = 0, BT = 0;
-    int sweep_block = 256;
+    int sweep_grid = 2048;  // persistent workgroups of the force sweep (multiple of 8)
     int grid_agents = 2048, grid_boxes = 2048;
     bool any_growth = false, any_static = false;
     int resort_every = 0;
@@ -223,10 +226,10 @@ static int capture(abm_batch *b, int part, int diag) {
     b->d.resort_every = b->resort_every;
     bool resort = b->resort_every > 0;
     if (part == 0)
-        launch_iteration(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, b->sweep_block, diag != 0, b->any_growth,
+        launch_iteration(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, b->sweep_grid, diag != 0, b->any_growth,
                          b->any_static, resort);
     else if (part == 1)
-        launch_sweep(b->d, b->cap_stream, b->grid_agents, b->sweep_block, diag != 0);
+        launch_sweep(b->d, b->cap_stream, b->sweep_grid, diag != 0);
     else
         launch_after_sweep(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, diag != 0, b->any_growth, b->any_static,
                            resort);
@@ -297,6 +300,8 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     d.btile_begin = (int64_t *)(w + L.btile_begin);
     d.utile_begin = (int64_t *)(w + L.utile_begin);
     d.a_begin = (int64_t *)(w + L.a_begin);
+    d.wblk_begin = (int64_t *)(w + L.wblk_begin);
+    d.bnd = (unsigned long long *)(w + L.bnd);
     for (int k = 0; k < 2; ++k) {
         d.pos[k] = (double *)(w + L.pos[k]);
         d.diam[k] = (double *)(w + L.diam[k]);
@@ -319,6 +324,7 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     d.count = (uint32_t *)(w + L.count);
     d.box_start = (uint32_t *)(w + L.box_start);
     d.mrank = (uint32_t *)(w + L.mrank);
+    d.blist = (uint32_t *)(w + L.blist);
     d.dirty = (uint8_t *)(w + L.dirty);
     d.arrive = (uint8_t *)(w + L.arrive);
     d.tile_sum = (uint32_t *)(w + L.tile_sum);
@@ -544,12 +550,19 @@ extern "C" int abm_batch_step(abm_batch *b, int n_iter) {
     if (!b || n_iter < 0) return fail(ABM_ERR_ARG, "bad handle or iteration count");
     if (n_iter == 0) return ABM_OK;
     int diag = any_diag(b) ? 1 : 0;
-    int rc = b->timing ? (capture(b, 1, diag) || capture(b, 2, diag)) : capture(b, 0, diag);
+    int rc = b->timing ? capture(b, 1, diag) : capture(b, 0, diag);
+    if (!rc && b->timing) rc = capture(b, 2, diag);
     if (rc) return rc;
     if (!b->grid_valid) {
         // every iteration ends by building the grid of its result; the first
-        // step (and a step after an error) builds it first
+        // step (and a step after an error) builds it first, and puts agents
+        // into Morton order when re-sorting is on
+        b->d.resort_every = b->resort_every;
         launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);
+        if (b->resort_every > 0) {
+            launch_resort(b->d, b->stream, b->grid_agents, b->grid_boxes, true);
+            launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);
+        }
         HIPCHK(hipGetLastError());
         b->grid_valid = true;
     }
@@ -714,17 +727,18 @@ extern "C" int abm_batch_hist(abm_batch *b, double hist_rmax, float *out, int ou
     return ABM_OK;
 }
 
-extern "C" int abm_batch_set_block(abm_batch *b, int block) {
+extern "C" int abm_batch_set_sweep_grid(abm_batch *b, int workgroups) {
     g_err.clear();
-    if (!b || (block != 64 && block != 128 && block != 256)) return fail(ABM_ERR_ARG, "block must be 64, 128 or 256");
-    if (block != b->sweep_block) {
-        b->sweep_block = block;
+    if (!b || workgroups < 8 || workgroups > 65536 || workgroups % 8)
+        return fail(ABM_ERR_ARG, "workgroups must be a multiple of 8 in [8, 65536]");
+    if (workgroups != b->sweep_grid) {
+        b->sweep_grid = workgroups;
         destroy_graphs(b);
     }
     return ABM_OK;
 }
 
-extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *block_out) {
+extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out) {
     g_err.clear();
     if (!b || n_trial_iters < 1) return fail(ABM_ERR_ARG, "bad arguments");
     // snapshot of the whole workspace so that trials leave the batch unchanged
@@ -734,19 +748,19 @@ extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *block_out) {
     hipStream_t st = b->stream;
     hipError_t e = hipMemcpyAsync(snap, b->ws, bytes, hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) { hipFree(snap); return fail(ABM_ERR_HIP, "snapshot copy failed"); }
-    const int blocks[3] = {64, 128, 256};
+    const int grids[4] = {512, 1024, 2048, 4096};
     const int resorts[4] = {0, 5, 10, 20};
     bool tune_resort = false;
     for (auto &S : b->host_sims) tune_resort |= S.resort_every < 0;
-    int best_block = b->sweep_block, best_resort = b->resort_every;
+    int best_grid = b->sweep_grid, best_resort = b->resort_every;
     float best = 1e30f;
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     int rc = ABM_OK;
-    for (int bi = 0; bi < 3 && rc == ABM_OK; ++bi) {
+    for (int bi = 0; bi < 4 && rc == ABM_OK; ++bi) {
         for (int ri = 0; ri < (tune_resort ? 4 : 1) && rc == ABM_OK; ++ri) {
-            b->sweep_block = blocks[bi];
+            b->sweep_grid = grids[bi];
             if (tune_resort) b->resort_every = resorts[ri];
             destroy_graphs(b);
             if ((rc = capture(b, 0, 0))) break;
@@ -762,7 +776,7 @@ extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *block_out) {
             if ((rc = read_ctl(b, c))) break;
             if (!c.abort && ms < best) {
                 best = ms;
-                best_block = blocks[bi];
+                best_grid = grids[bi];
                 best_resort = b->resort_every;
             }
         }
@@ -773,10 +787,10 @@ extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *block_out) {
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
-    b->sweep_block = best_block;
+    b->sweep_grid = best_grid;
     b->resort_every = best_resort;
     destroy_graphs(b);
-    if (block_out) *block_out = best_block;
+    if (grid_out) *grid_out = best_grid;
     return ABM_OK;
 }
 

@@ -1,0 +1,92 @@
+// abm_device.h -- device helpers shared by the kernels of libabm.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "abm_internal.h"
+
+namespace abm {
+
+#define ABM_ABORTED(d) (__builtin_expect((d).ctl->abort != 0, 0))
+
+constexpr double kPi = 3.14159265358979323846;
+
+// 256 threads x 4 items: this thread's exclusive prefix of its first item and
+// the block total.
+__device__ inline uint32_t block_excl_scan_4(const uint32_t v[4], uint32_t *sh, uint32_t &total) {
+    uint32_t s = v[0] + v[1] + v[2] + v[3];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = s;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    uint32_t wpre = 0;
+    total = 0;
+    for (int w = 0; w < 4; ++w) {
+        if (w < wid) wpre += sh[w];
+        total += sh[w];
+    }
+    __syncthreads();
+    return wpre + x - s;
+}
+
+// Morton rank of box (bx,by,bz) in a dims[0] x dims[1] x dims[2] grid: the
+// number of in-grid boxes whose Morton code (x in the lowest bit, Fig 5.4) is
+// smaller.  For every set bit p of the code, the boxes that agree with the
+// code above p and have 0 at p are counted per axis in closed form: their free
+// low bits span a range that is intersected with the grid.  Ranks of the
+// in-grid boxes are dense, so they index box arrays directly.
+__device__ inline uint32_t morton_rank(int bx, int by, int bz, const int32_t dims[3]) {
+    const int c[3] = {bx, by, bz};
+    uint64_t rank = 0;
+    for (int level = 10; level >= 0; --level) {
+        for (int a = 2; a >= 0; --a) {
+            if (!((c[a] >> level) & 1)) continue;
+            const int p = 3 * level + a;
+            uint64_t prod = 1;
+            for (int b = 0; b < 3; ++b) {
+                int freebits;
+                int64_t base;
+                if (b == a) {
+                    freebits = level;
+                    base = (int64_t)(c[b] >> (level + 1)) << (level + 1);
+                } else {
+                    freebits = p < b ? 0 : (p - b + 2) / 3;
+                    base = (int64_t)(c[b] >> freebits) << freebits;
+                }
+                int64_t span = (int64_t)1 << freebits;
+                int64_t cnt = (int64_t)dims[b] - base;
+                cnt = cnt < 0 ? 0 : (cnt > span ? span : cnt);
+                prod *= (uint64_t)cnt;
+            }
+            rank += prod;
+        }
+    }
+    return (uint32_t)rank;
+}
+
+// Morton rank of the box holding (x, y, z) in the current grid of S.
+__device__ inline uint32_t box_rank_of(const Dev &d, const SimDesc &S, double x, double y, double z) {
+    int bx = box_coord(x, S.lo[0], S.L, S.dims[0]);
+    int by = box_coord(y, S.lo[1], S.L, S.dims[1]);
+    int bz = box_coord(z, S.lo[2], S.L, S.dims[2]);
+    return d.mrank[S.b_off + linear_box(bx, by, bz, S.dims)];
+}
+
+__device__ inline uint32_t key_rank(const Dev &d, const SimDesc &S, uint32_t key) {
+    int bx, by, bz;
+    unpack_key(key, bx, by, bz);
+    return d.mrank[S.b_off + linear_box(bx, by, bz, S.dims)];
+}
+
+// Squared distance below L^2 with the neighbour predicate's exact expression.
+__device__ inline bool near_point(double x, double y, double z, double px, double py, double pz, double L2) {
+#pragma clang fp contract(off)
+    double ddx = x - px, ddy = y - py, ddz = z - pz;
+    return fma(ddz, ddz, fma(ddy, ddy, ddx * ddx)) < L2;
+}
+
+}  // namespace abm

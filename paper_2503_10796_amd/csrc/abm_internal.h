@@ -45,10 +45,16 @@ struct alignas(256) SimDesc {
     int32_t dims[3];
     int32_t err;
     int64_t nboxes;
-    unsigned long long enc_lo[3], enc_hi[3], enc_maxd;
+    int32_t dims_prev[3];  // dims of the Morton-rank tables
+    int32_t remap;         // the tables must be rebuilt for new dims
+    int64_t nblocks;       // aligned 4x4x4 box blocks (sweep work units)
+    double rmax;           // largest agent radius at the start of the iteration
     unsigned int nonfinite;
     float e_delta;  // bound on the FP32 error of an overlap in this grid
 };
+
+constexpr int kBndSlots = 64;  // spread of the bounds atomics (slots per simulation)
+constexpr int kBlk = 4;        // sweep work unit: kBlk^3 boxes, staged with a one-box halo
 
 struct alignas(256) Ctl {
     int64_t iter;
@@ -57,7 +63,7 @@ struct alignas(256) Ctl {
     int32_t abort;
     uint32_t n_fix;
     uint32_t n_unc_pairs;  // statistics: agents sent to the FP64 path
-    int64_t total_tiles, total_btiles, total_utiles;
+    int64_t total_tiles, total_btiles, total_utiles, total_units;
     int32_t resort_now;
     int32_t any_growth;
 };
@@ -72,6 +78,9 @@ struct Dev {
     int64_t *btile_begin;  // n_sims + 1: prefix of box tiles
     int64_t *utile_begin;  // n_sims + 1: prefix of uid tiles
     int64_t *a_begin;      // n_sims + 1: agent range starts (for agent -> sim)
+    int64_t *wblk_begin;   // n_sims + 1: prefix of sweep work units (box blocks)
+    unsigned long long *bnd;  // n_sims x kBndSlots x 7 bounds accumulators
+    uint32_t *blist;       // per simulation: packed block coords in Morton order
     double *pos[2];        // each 3*A: x block, y block, z block
     double *diam[2], *vol[2], *growth[2];
     uint64_t *uid[2];
@@ -83,7 +92,8 @@ struct Dev {
     int32_t *nbr, *contacts;
     double *force, *disp;  // 3*A interleaved
     int64_t *boxid;
-    uint32_t *count, *box_start, *mrank;
+    uint32_t *count, *box_start;  // indexed by Morton rank of the box
+    uint32_t *mrank;              // linear box id -> Morton rank
     uint8_t *dirty;   // boxes holding the start position of a changed agent
     uint8_t *arrive;  // boxes of the new grid holding a changed agent
     uint32_t *tile_sum, *tile_off;
@@ -148,12 +158,14 @@ __device__ inline float rel_coord(double v, double lo, double L, int b) {
 }
 
 // Host-side launch helpers implemented in the .hip files.
-void launch_iteration(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, int sweep_block, bool diag,
+void launch_iteration(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, int sweep_grid, bool diag,
                       bool any_growth, bool any_static, bool resort);
 void launch_grid_build(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool any_static);
-void launch_sweep(const Dev &d, hipStream_t s, int grid_agents, int sweep_block, bool diag);
+void launch_sweep(const Dev &d, hipStream_t s, int sweep_grid, bool diag);
 void launch_after_sweep(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool diag, bool any_growth,
                         bool any_static, bool resort);
+void launch_resort(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool force);
+void launch_end(const Dev &d, hipStream_t s, int grid_boxes, bool any_static);
 void launch_stats(const Dev &d, hipStream_t s, int grid_agents, double hist_rmax, double *out_dev);
 void launch_gather_pos(const Dev &d, hipStream_t s, int sim, double *dst, int64_t n, int64_t a_off);
 void launch_scatter_init(const Dev &d, hipStream_t s, int grid_agents);

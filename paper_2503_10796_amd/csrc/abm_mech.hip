@@ -1,19 +1,17 @@
-// abm_mech.hip -- HIP kernels of one mechanics iteration on gfx950.
+// abm_mech.hip -- force sweep, displacement, static rule, growth and division.
 //
-// Per iteration (all simulations of a batch in each launch):
-//   begin     per-simulation counters, agent-tile prefix
-//   bounds    open-boundary grid: min/max of positions, largest diameter (Sec 4.4.11, 4.4.3)
-//   grid      box length, dims, box-tile prefix
-//   bin       box key of every agent, per-box counts with arrival rank
-//   scan_*    per-box exclusive scan (counting sort, Sec 5.3.1)
-//   scatter   box-ordered FP32 payload (box-relative centre, radius) + index
+// Per iteration, on the grid built at the end of the previous one:
 //   sweep     27-box force sum (Eq 4.1-4.2), threshold + cap (Sec 5.5), commit
 //   fixup     FP64 re-evaluation of agents whose FP32 result cannot decide an
 //             integer outcome (contact, non-zero force, neighbour, move)
 //   div_*     grow-or-divide with prefix-sum append (Algorithm 2, Sec 5.3.2)
 //   static    static flags for the next iteration (Sec 5.5)
-//   end       commit: flip position buffers, counts, iteration
-//   resort    every R iterations: Morton-order counting sort of agent storage (Sec 5.4.2)
+//
+// The sweep works on aligned 4x4x4 blocks of boxes, visited in Morton order
+// with each XCD taking a contiguous range (its L2 then holds the shared halo).
+// A workgroup stages the FP32 payload of the block and its one-box halo
+// (6x6x6 boxes, about 730 agents at 3.4 agents per box) into LDS with
+// coalesced reads, then each thread sweeps one target's 27 boxes from LDS.
 //
 // Forces are summed as exact 64-bit fixed-point integers (2^-40 units), so the
 // result does not depend on the order in which neighbours are visited: every
@@ -21,294 +19,22 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "abm_internal.h"
+#include "abm_device.h"
 
 namespace abm {
 
-#define ABM_ABORTED(d) (__builtin_expect((d).ctl->abort != 0, 0))
-
 constexpr double kFixMagic = 6144.0;  // 1.5 * 2^12: fma(a, b, M) rounds a*b to 2^-40
 constexpr double kFixUnit = 0x1.0p-40;
-constexpr double kPi = 3.14159265358979323846;
+constexpr int kHalo = kBlk + 2;              // 6
+constexpr int kNb = kHalo * kHalo * kHalo;   // 216 staged boxes
+constexpr int kCore = kBlk * kBlk * kBlk;    // 64 target boxes
+constexpr int kStage = 2048;                 // staged agents (32 KB of float4)
 
-__device__ inline long long fixbits(double v) { return __double_as_longlong(v); }
-
-// ------------------------------------------------------------------ begin
-__global__ void k_begin(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    for (int s = threadIdx.x; s < d.n_sims; s += blockDim.x) {
-        SimDesc &S = d.sims[s];
-        S.n_start = S.n;
-        S.n_div = 0;
-        S.nonfinite = 0;
-        S.L_prev = S.L;
-        for (int a = 0; a < 3; ++a) {
-            S.enc_lo[a] = ~0ull;
-            S.enc_hi[a] = 0ull;
-        }
-        S.enc_maxd = 0ull;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int s = 0; s < d.n_sims; ++s) {
-            d.tile_begin[s] = t;
-            t += ceil_div(d.sims[s].n_start, kTile);
-        }
-        d.tile_begin[d.n_sims] = t;
-        d.ctl->total_tiles = t;
-        d.ctl->n_fix = 0;
-    }
-}
-
-// ------------------------------------------------------------------ bounds
-__global__ void __launch_bounds__(256) k_bounds(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    __shared__ double red[7][8];
-    const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
-    const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        double v[7];
-        bool ok = loc < S.n_start;
-        bool bad = false;
-        if (ok) {
-            int64_t i = S.a_off + loc;
-            double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
-            double dm = d.diam[lp][i];
-            bad = !(isfinite(x) && isfinite(y) && isfinite(z) && isfinite(dm));
-            v[0] = x; v[1] = y; v[2] = z; v[3] = -x; v[4] = -y; v[5] = -z; v[6] = dm;
-        } else {
-            for (int a = 0; a < 6; ++a) v[a] = __builtin_huge_val();
-            v[6] = -__builtin_huge_val();
-        }
-        // min of (x,y,z,-x,-y,-z) and max of d via wave then block reduction
-        for (int off = 32; off > 0; off >>= 1) {
-            for (int a = 0; a < 6; ++a) v[a] = fmin(v[a], __shfl_xor(v[a], off));
-            v[6] = fmax(v[6], __shfl_xor(v[6], off));
-        }
-        if (lane == 0)
-            for (int a = 0; a < 7; ++a) red[a][wid] = v[a];
-        if (bad) atomicOr(&d.sims[s].nonfinite, 1u);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int nw = blockDim.x >> 6;
-            for (int w = 1; w < nw; ++w) {
-                for (int a = 0; a < 6; ++a) red[a][0] = fmin(red[a][0], red[a][w]);
-                red[6][0] = fmax(red[6][0], red[6][w]);
-            }
-            SimDesc &W = d.sims[s];
-            for (int a = 0; a < 3; ++a) {
-                if (red[a][0] < __builtin_huge_val()) {
-                    atomicMin(&W.enc_lo[a], enc_double(red[a][0]));
-                    atomicMax(&W.enc_hi[a], enc_double(-red[3 + a][0]));
-                }
-            }
-            if (red[6][0] > -__builtin_huge_val()) atomicMax(&W.enc_maxd, enc_double(red[6][0]));
-        }
-        __syncthreads();
-    }
-}
-
-// ------------------------------------------------------------------ grid
-__global__ void k_grid(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    for (int s = threadIdx.x; s < d.n_sims; s += blockDim.x) {
-        SimDesc &S = d.sims[s];
-        if (S.nonfinite) {
-            S.err |= kErrNonfinite;
-            atomicOr(&d.ctl->err, kErrNonfinite);
-            atomicExch(&d.ctl->abort, 1);
-        }
-        if (S.n_start == 0) {
-            S.nboxes = 0;
-            S.dims[0] = S.dims[1] = S.dims[2] = 0;
-            continue;
-        }
-        double L = S.box_len > 0.0 ? S.box_len : dec_double(S.enc_maxd);
-        S.L = L;
-        int64_t nb = 1;
-        bool bad = !(L > 0.0);
-        for (int a = 0; a < 3; ++a) {
-            S.lo[a] = dec_double(S.enc_lo[a]);
-            S.hi[a] = dec_double(S.enc_hi[a]);
-            double q = floor((S.hi[a] - S.lo[a]) / L) + 1.0;
-            int lim = a == 2 ? kDimZ : (a == 1 ? kDimY : kDimX);
-            if (!(q <= (double)lim)) { bad = true; q = 1.0; }
-            S.dims[a] = (int32_t)q;
-            nb *= (int64_t)q;
-        }
-        if (bad || nb > S.box_cap) {
-            S.err |= kErrGrid;
-            atomicOr(&d.ctl->err, kErrGrid);
-            atomicExch(&d.ctl->abort, 1);
-            nb = 0;
-        }
-        S.nboxes = nb;
-        S.e_delta = (float)ldexp(L, -19);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int s = 0; s < d.n_sims; ++s) {
-            d.btile_begin[s] = t;
-            t += ceil_div(d.sims[s].nboxes, kBoxTile);
-        }
-        d.btile_begin[d.n_sims] = t;
-        d.ctl->total_btiles = t;
-    }
-}
-
-// ------------------------------------------------------------------ bin
-__global__ void __launch_bounds__(256) k_bin(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    const int P = d.ctl->pos_par;
-    const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n_start) continue;
-        int64_t i = S.a_off + loc;
-        double L = S.L;
-        int bx = box_coord(d.pos[P][i], S.lo[0], L, S.dims[0]);
-        int by = box_coord(d.pos[P][A + i], S.lo[1], L, S.dims[1]);
-        int bz = box_coord(d.pos[P][2 * A + i], S.lo[2], L, S.dims[2]);
-        int64_t lin = linear_box(bx, by, bz, S.dims);
-        d.key[i] = pack_key(bx, by, bz);
-        d.rank[i] = atomicAdd(&d.count[S.b_off + lin], 1u);
-        if (S.detect_static && (d.flags[d.ctl->lay_par][i] & kChgMask)) d.arrive[S.b_off + lin] = 1;
-    }
-}
-
-// ------------------------------------------------------------------ scan
-// Segmented exclusive scan of per-box counts into global slot starts.
-__device__ inline uint32_t block_excl_scan_4(uint32_t v[4], uint32_t *sh, uint32_t &total) {
-    // 256 threads x 4 items; returns this thread's exclusive prefix of its first item
-    uint32_t s = v[0] + v[1] + v[2] + v[3];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t x = s;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) sh[wid] = x;
-    __syncthreads();
-    uint32_t wpre = 0;
-    total = 0;
-    for (int w = 0; w < 4; ++w) {
-        if (w < wid) wpre += sh[w];
-        total += sh[w];
-    }
-    __syncthreads();
-    return wpre + x - s;
-}
-
-__global__ void __launch_bounds__(256) k_scan_tiles(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    __shared__ uint32_t sh[4];
-    const int64_t total = d.ctl->total_btiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t k0 = (t - d.btile_begin[s]) * kBoxTile + threadIdx.x * 4;
-        uint32_t v[4];
-        for (int q = 0; q < 4; ++q) v[q] = (k0 + q < S.nboxes) ? d.count[S.b_off + k0 + q] : 0u;
-        uint32_t tot;
-        block_excl_scan_4(v, sh, tot);
-        if (threadIdx.x == 0) d.tile_sum[t] = tot;
-    }
-}
-
-__global__ void __launch_bounds__(1024) k_scan_top(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    __shared__ uint32_t sh[16];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int s = 0; s < d.n_sims; ++s) {
-        int64_t b0 = d.btile_begin[s], b1 = d.btile_begin[s + 1];
-        uint32_t carry = 0;
-        for (int64_t c = b0; c < b1; c += blockDim.x) {
-            int64_t t = c + threadIdx.x;
-            uint32_t v = t < b1 ? d.tile_sum[t] : 0u;
-            uint32_t x = v;
-            for (int off = 1; off < 64; off <<= 1) {
-                uint32_t y = __shfl_up(x, off);
-                if (lane >= off) x += y;
-            }
-            if (lane == 63) sh[wid] = x;
-            __syncthreads();
-            uint32_t wpre = 0, tot = 0;
-            for (int w = 0; w < 16; ++w) {
-                if (w < wid) wpre += sh[w];
-                tot += sh[w];
-            }
-            if (t < b1) d.tile_off[t] = carry + wpre + x - v;
-            carry += tot;
-            __syncthreads();
-        }
-    }
-}
-
-// Writes box_start[sb_off + k] = a_off + prefix; zeroes the counts.
-__global__ void __launch_bounds__(256) k_scan_apply(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    __shared__ uint32_t sh[4];
-    const int64_t total = d.ctl->total_btiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t k0 = (t - d.btile_begin[s]) * kBoxTile + threadIdx.x * 4;
-        uint32_t v[4];
-        for (int q = 0; q < 4; ++q) v[q] = (k0 + q < S.nboxes) ? d.count[S.b_off + k0 + q] : 0u;
-        uint32_t tot;
-        uint32_t pre = block_excl_scan_4(v, sh, tot);
-        uint32_t base = (uint32_t)S.a_off + d.tile_off[t] + pre;
-        for (int q = 0; q < 4; ++q) {
-            if (k0 + q < S.nboxes) {
-                d.box_start[S.sb_off + k0 + q] = base;
-                d.count[S.b_off + k0 + q] = 0u;
-            }
-            base += v[q];
-        }
-        if (t == d.btile_begin[s + 1] - 1 && threadIdx.x == 0)
-            d.box_start[S.sb_off + S.nboxes] = (uint32_t)(S.a_off + S.n_start);
-    }
-}
-
-// ------------------------------------------------------------------ scatter
-__global__ void __launch_bounds__(256) k_scatter(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
-    const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n_start) continue;
-        int64_t i = S.a_off + loc;
-        int bx, by, bz;
-        unpack_key(d.key[i], bx, by, bz);
-        int64_t lin = linear_box(bx, by, bz, S.dims);
-        uint32_t slot = d.box_start[S.sb_off + lin] + d.rank[i];
-        float4 p;
-        p.x = rel_coord(d.pos[P][i], S.lo[0], S.L, bx);
-        p.y = rel_coord(d.pos[P][A + i], S.lo[1], S.L, by);
-        p.z = rel_coord(d.pos[P][2 * A + i], S.lo[2], S.L, bz);
-        p.w = (float)(0.5 * d.diam[lp][i]);
-        d.payload[slot] = p;
-        d.sorted_idx[slot] = (uint32_t)i;
-    }
-}
+__device__ inline unsigned long long fixbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
 // ------------------------------------------------------------------ commit helpers
-// Displacement exactly as the thesis's rule reads: no motion unless |F| > a,
-// else F*dt/m capped in Euclidean norm (FP64, IEEE ops, no contraction).
+// Displacement as the thesis's rule reads: no motion unless |F| > a, else
+// F*dt/m capped in Euclidean norm (FP64, IEEE ops, no contraction).
 __device__ inline bool displacement64(double fx, double fy, double fz, const SimDesc &S, double &dx, double &dy,
                                       double &dz) {
 #pragma clang fp contract(off)
@@ -332,10 +58,11 @@ __device__ inline bool displacement64(double fx, double fy, double fz, const Sim
 }
 
 // Writes the outcome of one agent's mechanics (shared by sweep and fixup).
+// m: Morton rank of the agent's box; lin: its linear id (diagnostics).
 template <bool DIAG>
 __device__ inline void commit_agent(const Dev &d, const SimDesc &S, int64_t i, int P, int lp, uint8_t fl, double x,
                                     double y, double z, double fx, double fy, double fz, int nz, int nbr,
-                                    int contacts) {
+                                    int contacts, uint32_t m, int64_t lin) {
     const int64_t A = d.A;
     double dx, dy, dz;
     bool moved = displacement64(fx, fy, fz, S, dx, dy, dz);
@@ -346,11 +73,7 @@ __device__ inline void commit_agent(const Dev &d, const SimDesc &S, int64_t i, i
         d.pos[1 - P][A + i] = y + dy;
         d.pos[1 - P][2 * A + i] = z + dz;
         d.flags[lp][i] = fl | kBufDiff | kMoved;
-        if (S.detect_static) {
-            int bx, by, bz;
-            unpack_key(d.key[i], bx, by, bz);
-            d.dirty[S.b_off + linear_box(bx, by, bz, S.dims)] = 1;
-        }
+        if (S.detect_static) d.dirty[S.b_off + m] = 1;  // start box of a changed agent
     } else {
         if (fl & kBufDiff) {
             d.pos[1 - P][i] = x;
@@ -369,14 +92,13 @@ __device__ inline void commit_agent(const Dev &d, const SimDesc &S, int64_t i, i
         d.disp[3 * i] = dx;
         d.disp[3 * i + 1] = dy;
         d.disp[3 * i + 2] = dz;
-        int bx, by, bz;
-        unpack_key(d.key[i], bx, by, bz);
-        d.boxid[i] = linear_box(bx, by, bz, S.dims);
+        d.boxid[i] = lin;
     }
 }
 
+// A static agent: no force, no motion, non-zero-force count kept (Sec 5.5).
 template <bool DIAG>
-__device__ inline void skip_static(const Dev &d, const SimDesc &S, int64_t i, int P, int lp, uint8_t fl) {
+__device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8_t fl, int64_t lin) {
     const int64_t A = d.A;
     if (fl & kBufDiff) {
         d.pos[1 - P][i] = d.pos[P][i];
@@ -391,139 +113,371 @@ __device__ inline void skip_static(const Dev &d, const SimDesc &S, int64_t i, in
             d.force[3 * i + a] = 0.0;
             d.disp[3 * i + a] = 0.0;
         }
-        int bx, by, bz;
-        unpack_key(d.key[i], bx, by, bz);
-        d.boxid[i] = linear_box(bx, by, bz, S.dims);
+        d.boxid[i] = lin;
     }
 }
 
+// Per-target accumulator of the FP32 sweep.
+struct Acc {
+    unsigned long long ax, ay, az;  // force components in 2^-40 units, plus nfix * magic bits (mod 2^64)
+    uint32_t eacc;         // error bound in 2^-26 units (rounded up per pair)
+    int contacts, nz, nbr, nfix;
+    bool unc;              // an integer outcome is not decidable in FP32
+};
+
+// Contact part of one pair: (ddx,ddy,ddz) = target minus candidate, d2 its
+// squared length, ri/rj the radii.  Decides contact (delta > 0) and non-zero
+// force, accumulates the force in fixed point and its error bound; marks the
+// target undecidable when FP32 cannot certify an integer outcome.
+__device__ inline void pair_contact(Acc &a, float ddx, float ddy, float ddz, float d2, float ri, float rj, float e,
+                                    float g, float kf, float gf, float L2m, float L2p) {
+    const float sr = ri + rj;
+    const float sg = sr + g;
+    if (!(d2 < sg * sg)) return;
+    if (d2 >= L2m) {  // only possible when the box length is below the largest diameter
+        if (d2 < L2p) a.unc = true;
+        return;
+    }
+    const float dist = sqrtf(d2);
+    const float delta = sr - dist;
+    if (delta <= e) {
+        if (delta >= -e) a.unc = true;
+        return;
+    }
+    ++a.contacts;
+    const float rbar = ri * rj * __builtin_amdgcn_rcpf(sr);
+    const float sq = sqrtf(rbar * delta);
+    const float kd = kf * delta, gs = gf * sq;
+    const float fn = kd - gs;
+    // bound on |fn error|: conditioning of Eq 4.1 times the overlap error,
+    // plus FP32 rounding relative to the magnitudes of both terms
+    const float ep = (kf + 0.5f * gs * __builtin_amdgcn_rcpf(delta)) * e + (kd + gs) * 0x1.0p-19f;
+    if (ep >= 0x1.0p-6f || fabsf(fn) <= ep) {
+        a.unc = true;
+        return;
+    }
+    ++a.nz;
+    const double f = (double)(fn * __builtin_amdgcn_rcpf(dist));
+    a.ax += fixbits(fma(f, (double)ddx, kFixMagic));
+    a.ay += fixbits(fma(f, (double)ddy, kFixMagic));
+    a.az += fixbits(fma(f, (double)ddz, kFixMagic));
+    ++a.nfix;
+    a.eacc += (uint32_t)ceilf(ep * 0x1.0p26f);
+}
+
+// One candidate pair in FP32 box-relative coordinates (global-memory path).
+// (qx,qy,qz) = target coordinate minus the box offset of the candidate's box.
+template <bool DIAG>
+__device__ inline void pair_fp32(Acc &a, float qx, float qy, float qz, float ri, float4 c, float e, float g, float kf,
+                                 float gf, float L2m, float L2p) {
+    const float ddx = qx - c.x, ddy = qy - c.y, ddz = qz - c.z;
+    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+    if (DIAG) {
+        if (d2 < L2m) ++a.nbr;
+        else if (d2 < L2p) a.unc = true;
+    }
+    pair_contact(a, ddx, ddy, ddz, d2, ri, c.w, e, g, kf, gf, L2m, L2p);
+}
+
 // ------------------------------------------------------------------ sweep
-// One thread per target agent, agents in storage (Morton) order.  The 27
-// neighbour boxes are visited as 9 rows of 3 consecutive boxes, each row a
-// contiguous range of the box-ordered payload.  All FP32 work is on
-// box-relative coordinates; every integer decision that FP32 cannot certify
-// sends the agent to the FP64 fix-up kernel instead.
+constexpr int kList = 32;  // per-thread list of candidates within reach (u16 LDS indices)
+constexpr int kChunk = 16;  // candidates tested between two list-room checks
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+    for (int off = 32; off > 0; off >>= 1) {
+        uint32_t o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Contact math of the listed candidates (phase 2), block-relative FP32
+// coordinates.  Wave-uniform loop with predication: no branches per entry.
+// Coincident or near-coincident centres, overlaps and forces within their
+// FP32 error bound of a decision threshold mark the target for FP64.
+__device__ inline void drain_list(Acc &a, const float4 *sp, const uint16_t *lst, uint32_t n, uint32_t self, float4 own,
+                                  float e, float g, float kf, float gf, float L2m, float L2p) {
+    const uint32_t nmax = wave_max_u32(n);
+    for (uint32_t k = 0; k < nmax; ++k) {
+        uint32_t q = lst[k * 256 + threadIdx.x];
+        q = q < (uint32_t)kStage ? q : 0u;
+        const bool valid = k < n && q != self;
+        const float4 c = sp[q];
+        const float ddx = valid ? own.x - c.x : 0.0f;
+        const float ddy = valid ? own.y - c.y : 0.0f;
+        const float ddz = valid ? own.z - c.z : 0.0f;
+        const float rj = valid ? c.w : 0.0f;
+        const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+        const float sr = own.w + rj;
+        const float sg = sr + g;
+        bool cand = valid && d2 < sg * sg;
+        const bool beyond = d2 >= L2m;  // only when the box length is below the largest diameter
+        bool unc = cand && beyond && d2 < L2p;
+        unc |= cand && d2 < g * g;  // (near-)coincident centres: direction left to FP64
+        cand = cand && !beyond && d2 >= g * g;
+        const float dist = __builtin_amdgcn_sqrtf(d2);
+        const float delta = sr - dist;
+        unc |= cand && delta <= e && delta >= -e;
+        bool contact = cand && delta > e;
+        const float rbar = own.w * rj * __builtin_amdgcn_rcpf(sr);
+        const float sq = __builtin_amdgcn_sqrtf(fmaxf(rbar * delta, 0.0f));
+        const float kd = kf * delta, gs = gf * sq;
+        const float fn = kd - gs;
+        const float ep = (kf + 0.5f * gs * __builtin_amdgcn_rcpf(delta)) * e + (kd + gs) * 0x1.0p-19f;
+        const bool bad = contact && (ep >= 0x1.0p-6f || fabsf(fn) <= ep);
+        unc |= bad;
+        contact = contact && !bad;
+        a.unc |= unc;
+        a.contacts += contact ? 1 : 0;
+        a.nz += contact ? 1 : 0;
+        const double f = contact ? (double)(fn * __builtin_amdgcn_rcpf(dist)) : 0.0;
+        a.ax += fixbits(fma(f, (double)ddx, kFixMagic));
+        a.ay += fixbits(fma(f, (double)ddy, kFixMagic));
+        a.az += fixbits(fma(f, (double)ddz, kFixMagic));
+        ++a.nfix;
+        a.eacc += contact ? (uint32_t)ceilf(ep * 0x1.0p26f) : 0u;
+    }
+}
+
 template <bool DIAG>
 __global__ void __launch_bounds__(256) k_sweep(Dev d) {
+    __shared__ float4 sp[kStage];            // staged payload, block-relative coordinates
+    __shared__ uint16_t lst[kList * 256];    // per-thread candidate lists, thread-interleaved
+    __shared__ uint32_t sbeg[kNb + 1];       // exclusive prefix of the staged box counts
+    __shared__ uint32_t gsrc[kNb];           // global slot start of every staged box
+    __shared__ uint32_t coff[kCore + 1];
+    __shared__ uint32_t scnt[kNb];
+    __shared__ uint32_t sh[4];
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    const int tpb = blockDim.x;
-    const int64_t per_tile = kTile;
-    // a tile of kTile agents is covered by kTile / blockDim.x passes
-    const int passes = (int)(per_tile / tpb) > 0 ? (int)(per_tile / tpb) : 1;
-    for (int64_t w = blockIdx.x; w < total * passes; w += gridDim.x) {
-        int64_t t = w / passes;
-        int part = (int)(w - t * passes);
-        int s = find_sim(d.tile_begin, d.n_sims, t);
+    const int64_t U = d.ctl->total_units;
+    const int tid = threadIdx.x;
+    // blocks are dealt to the 8 XCDs round-robin: give each XCD a contiguous
+    // Morton range of work units so that neighbouring blocks share its L2
+    const int xcd = blockIdx.x & 7;
+    const int64_t per_xcd = (int64_t)(gridDim.x >> 3);
+    const int64_t chunk = ceil_div(U, 8);
+    const int64_t u_end = (xcd + 1) * chunk < U ? (xcd + 1) * chunk : U;
+    for (int64_t u = xcd * chunk + (blockIdx.x >> 3); u < u_end; u += per_xcd) {
+        const int s = find_sim(d.wblk_begin, d.n_sims, u);
         const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + part * tpb + threadIdx.x;
-        if (loc >= S.n_start) continue;
-        int64_t i = S.a_off + loc;
-        uint8_t fl = d.flags[lp][i];
-        if (S.detect_static && (fl & kStatic)) {
-            skip_static<DIAG>(d, S, i, P, lp, fl);
-            continue;
+        int qx, qy, qz;
+        unpack_key(d.blist[S.b_off + (u - d.wblk_begin[s])], qx, qy, qz);
+        // table of the 6x6x6 staged boxes (x fastest)
+        uint32_t cnt = 0;
+        if (tid < kNb) {
+            const int lx = tid % kHalo, ly = (tid / kHalo) % kHalo, lz = tid / (kHalo * kHalo);
+            const int gx = qx * kBlk + lx - 1, gy = qy * kBlk + ly - 1, gz = qz * kBlk + lz - 1;
+            uint32_t src = 0;
+            if (gx >= 0 && gy >= 0 && gz >= 0 && gx < S.dims[0] && gy < S.dims[1] && gz < S.dims[2]) {
+                const uint32_t m = d.mrank[S.b_off + linear_box(gx, gy, gz, S.dims)];
+                src = d.box_start[S.sb_off + m];
+                cnt = d.box_start[S.sb_off + m + 1] - src;
+            }
+            gsrc[tid] = src;
+            scnt[tid] = cnt;
         }
-        const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
-        int bx, by, bz;
-        unpack_key(d.key[i], bx, by, bz);
-        const int nx = S.dims[0], ny = S.dims[1], nzd = S.dims[2];
+        uint32_t v[4] = {cnt, 0u, 0u, 0u};
+        uint32_t total;
+        const uint32_t pre = block_excl_scan_4(v, sh, total);
+        if (tid < kNb) sbeg[tid] = pre;
+        if (tid == 0) sbeg[kNb] = total;
+        __syncthreads();
+        if (tid < 64) {  // prefix of the target counts over the 64 core boxes (one wave)
+            const int lb = (tid % 4 + 1) + kHalo * ((tid / 4 % 4 + 1) + kHalo * (tid / 16 + 1));
+            const uint32_t cc = scnt[lb];
+            uint32_t x = cc;
+            for (int off = 1; off < 64; off <<= 1) {
+                uint32_t y = __shfl_up(x, off);
+                if (tid >= off) x += y;
+            }
+            coff[tid] = x - cc;
+            if (tid == 63) coff[64] = x;
+        }
         const float Lf = (float)S.L;
-        const float rxi = rel_coord(x, S.lo[0], S.L, bx);
-        const float ryi = rel_coord(y, S.lo[1], S.L, by);
-        const float rzi = rel_coord(z, S.lo[2], S.L, bz);
-        const float ri = (float)(0.5 * d.diam[lp][i]);
-        const uint32_t self = d.box_start[S.sb_off + linear_box(bx, by, bz, S.dims)] + d.rank[i];
-        const float e = S.e_delta;
-        const float g = 2.0f * e;
+        const bool staged = total <= (uint32_t)kStage;
+        if (staged) {
+            // box-relative -> relative to the centre of the 6x6x6 region (|x| < 3L)
+            for (uint32_t e = tid; e < total; e += blockDim.x) {
+                int lo = 0, hi = kNb;  // largest lb with sbeg[lb] <= e
+                while (hi - lo > 1) {
+                    int mid = (lo + hi) >> 1;
+                    if (sbeg[mid] <= e) lo = mid; else hi = mid;
+                }
+                float4 c = d.payload[gsrc[lo] + (e - sbeg[lo])];
+                const int lx = lo % kHalo, ly = (lo / kHalo) % kHalo, lz = lo / (kHalo * kHalo);
+                c.x += (float)(lx - 3) * Lf;
+                c.y += (float)(ly - 3) * Lf;
+                c.z += (float)(lz - 3) * Lf;
+                sp[e] = c;
+            }
+        }
+        __syncthreads();
+        const uint32_t nt = coff[64];
+        const float e = S.e_delta, g = 2.0f * e;
         const float kf = (float)S.k, gf = (float)S.gamma;
         const float L2 = (float)(S.L * S.L);
         const float G = (float)ldexp(S.L * S.L, -18);
         const float L2m = L2 - G, L2p = L2 + G;
-        long long ax = 0, ay = 0, az = 0;
-        uint32_t eacc = 0;
-        int contacts = 0, nzc = 0, nbr = 0, nfix = 0;
-        bool unc = false;
-        for (int oz = -1; oz <= 1; ++oz) {
-            int cz = bz + oz;
-            if (cz < 0 || cz >= nzd) continue;
-            for (int oy = -1; oy <= 1; ++oy) {
-                int cy = by + oy;
-                if (cy < 0 || cy >= ny) continue;
-                const int bx0 = bx > 0 ? bx - 1 : 0;
-                const int bx1 = bx < nx - 1 ? bx + 1 : nx - 1;
-                const int64_t rowlin = (int64_t)nx * ((int64_t)cy + (int64_t)ny * cz);
-                const uint32_t *bs = d.box_start + S.sb_off + rowlin;
-                const float qy = ryi - (float)oy * Lf;
-                const float qz = rzi - (float)oz * Lf;
-                uint32_t sb = bs[bx0];
-                for (int cx = bx0; cx <= bx1; ++cx) {
-                    const uint32_t se = bs[cx + 1];
-                    const float qx = rxi - (float)(cx - bx) * Lf;
-                    for (uint32_t slot = sb; slot < se; ++slot) {
-                        if (slot == self) continue;
-                        const float4 c = d.payload[slot];
-                        const float ddx = qx - c.x, ddy = qy - c.y, ddz = qz - c.z;
-                        const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                        if (DIAG) {
-                            if (d2 < L2m) ++nbr;
-                            else if (d2 < L2p) unc = true;
+        const float rmaxg = (float)S.rmax + g;
+        for (uint32_t t0 = 0; t0 < nt; t0 += blockDim.x) {
+            // all lanes run the loop body (wave-uniform inner loops); lanes
+            // without a target, and static targets, are predicated off
+            const uint32_t t = t0 + tid < nt ? t0 + tid : nt - 1;
+            bool act = t0 + tid < nt;
+            int c = 0, hi = kCore;  // core box of target t
+            while (hi - c > 1) {
+                int mid = (c + hi) >> 1;
+                if (coff[mid] <= t) c = mid; else hi = mid;
+            }
+            const int cx = c % 4, cy = c / 4 % 4, cz = c / 16;
+            const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
+            const uint32_t k = t - coff[c];
+            const uint32_t slot = gsrc[lb] + k;
+            const uint32_t self = staged ? sbeg[lb] + k : slot;
+            const int64_t i = d.sorted_idx[slot];
+            const int bx = qx * kBlk + cx, by = qy * kBlk + cy, bz = qz * kBlk + cz;
+            const int64_t lin = linear_box(bx, by, bz, S.dims);
+            const uint8_t fl = d.flags[lp][i];
+            if (act && S.detect_static && (fl & kStatic)) {
+                skip_static<DIAG>(d, i, P, lp, fl, lin);
+                act = false;
+            }
+            Acc a = {0, 0, 0, 0u, 0, 0, 0, 0, false};
+            if (staged) {
+                // phase 1: distance pre-test against the reach of the largest
+                // agent; survivors go to the thread's list; phase 2: contacts
+                const float4 own = sp[self];
+                const float R = own.w + rmaxg;
+                const float R2 = fminf(R * R, L2p);
+                uint32_t n = 0;
+                for (int r = 0; r < 9; ++r) {
+                    const int row = cx + kHalo * ((cy + r % 3) + kHalo * (cz + r / 3));  // boxes cx..cx+2
+                    const uint32_t b0 = sbeg[row];
+                    const uint32_t len = act ? sbeg[row + 3] - b0 : 0u;
+                    const uint32_t kmax = wave_max_u32(len);
+                    for (uint32_t k0 = 0; k0 < kmax; k0 += kChunk) {
+                        if (__ballot(n + kChunk > (uint32_t)kList)) {
+                            drain_list(a, sp, lst, n, self, own, e, g, kf, gf, L2m, L2p);
+                            n = 0;
                         }
-                        const float sr = ri + c.w;
-                        const float sg = sr + g;
-                        if (d2 < sg * sg) {
-                            if (d2 >= L2m) {  // only possible when box_len < largest diameter
-                                if (d2 < L2p) unc = true;
-                                continue;
+                        const uint32_t k1 = k0 + kChunk < kmax ? k0 + kChunk : kmax;
+                        for (uint32_t kk = k0; kk < k1; ++kk) {
+                            const bool in = kk < len;
+                            const uint32_t q = in ? b0 + kk : 0u;
+                            const float4 cc = sp[q];
+                            const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
+                            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                            if (DIAG) {
+                                const bool other = in && q != self;
+                                a.nbr += (other && d2 < L2m) ? 1 : 0;
+                                a.unc |= other && d2 >= L2m && d2 < L2p;
                             }
-                            const float dist = sqrtf(d2);
-                            const float delta = sr - dist;
-                            if (delta <= e) {
-                                if (delta >= -e) unc = true;
-                                continue;
-                            }
-                            ++contacts;
-                            const float rbar = ri * c.w / sr;
-                            const float sq = sqrtf(rbar * delta);
-                            const float fn = kf * delta - gf * sq;
-                            const float ep = (kf + gf * sq / (2.0f * delta)) * e + fabsf(fn) * 0x1.0p-19f;
-                            if (ep >= 0x1.0p-6f || fabsf(fn) <= ep) {
-                                unc = true;
-                                continue;
-                            }
-                            ++nzc;
-                            const double f = (double)(fn / dist);
-                            ax += fixbits(fma(f, (double)ddx, kFixMagic));
-                            ay += fixbits(fma(f, (double)ddy, kFixMagic));
-                            az += fixbits(fma(f, (double)ddz, kFixMagic));
-                            ++nfix;
-                            eacc += (uint32_t)ceilf(ep * 0x1.0p26f);
+                            lst[n * 256 + tid] = (uint16_t)q;
+                            n += (in && d2 < R2) ? 1u : 0u;
                         }
                     }
-                    sb = se;
+                }
+                drain_list(a, sp, lst, n, self, own, e, g, kf, gf, L2m, L2p);
+            } else if (act) {
+                const float4 own = d.payload[slot];
+                for (int oz = -1; oz <= 1; ++oz) {
+                    for (int oy = -1; oy <= 1; ++oy) {
+                        const int row = cx + kHalo * ((cy + 1 + oy) + kHalo * (cz + 1 + oz));
+                        const float qy2 = own.y - (float)oy * Lf;
+                        const float qz2 = own.z - (float)oz * Lf;
+                        for (int ox = -1; ox <= 1; ++ox) {
+                            const int lbb = row + ox + 1;
+                            const float qx2 = own.x - (float)ox * Lf;
+                            const uint32_t b0 = gsrc[lbb], nn = sbeg[lbb + 1] - sbeg[lbb];
+                            for (uint32_t q = b0; q < b0 + nn; ++q)
+                                if (q != self)
+                                    pair_fp32<DIAG>(a, qx2, qy2, qz2, own.w, d.payload[q], e, g, kf, gf, L2m, L2p);
+                        }
+                    }
                 }
             }
+            if (!act) continue;
+            bool unc = a.unc;
+            if (!unc) {
+                const unsigned long long mb = (unsigned long long)a.nfix * fixbits(kFixMagic);
+                const double fx = (double)(long long)(a.ax - mb) * kFixUnit;
+                const double fy = (double)(long long)(a.ay - mb) * kFixUnit;
+                const double fz = (double)(long long)(a.az - mb) * kFixUnit;
+                const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
+                const double ebound = (double)a.eacc * 0x1.0p-26 + 1e-9;
+                if (fabs(fnorm - S.adherence) <= ebound) {
+                    unc = true;
+                } else {
+                    const uint32_t m = d.mrank[S.b_off + lin];
+                    commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
+                                       fz, a.nz, a.nbr, a.contacts, m, lin);
+                }
+            }
+            if (unc) {
+                uint32_t q = atomicAdd(&d.ctl->n_fix, 1u);
+                d.fix_list[q] = (uint32_t)i;
+            }
         }
-        if (!unc) {
-            const long long mb = fixbits(kFixMagic);
-            const double fx = (double)(ax - (long long)nfix * mb) * kFixUnit;
-            const double fy = (double)(ay - (long long)nfix * mb) * kFixUnit;
-            const double fz = (double)(az - (long long)nfix * mb) * kFixUnit;
-            const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
-            const double ebound = (double)eacc * 0x1.0p-26 + 1e-9;
-            if (fabs(fnorm - S.adherence) <= ebound) unc = true;
-            else commit_agent<DIAG>(d, S, i, P, lp, fl, x, y, z, fx, fy, fz, nzc, nbr, contacts);
-        }
-        if (unc) {
-            uint32_t q = atomicAdd(&d.ctl->n_fix, 1u);
-            d.fix_list[q] = (uint32_t)i;
-        }
+        __syncthreads();  // the next unit reuses the LDS tables
     }
 }
 
 // ------------------------------------------------------------------ fixup
+// Order-independent sum of FP64 terms: every term is rounded to a multiple
+// of 2^-80 (round half up in magnitude) and added into a 128-bit two's
+// complement integer, so the result does not depend on the order in which
+// the neighbours are met.  Terms of magnitude 2^36 and above set `wide`
+// (the caller then falls back to a plain FP64 sum); with fewer than 2^11
+// terms the integer cannot overflow.
+struct Fix128 {
+    uint64_t lo = 0, hi = 0;
+    bool wide = false;
+    __device__ void add(double t) {
+        const uint64_t bits = (uint64_t)__double_as_longlong(t);
+        const int E = (int)((bits >> 52) & 0x7ff);
+        if (E == 0) return;  // zero or subnormal: below 2^-80
+        if (E >= 1023 + 36) {
+            wide = true;
+            return;
+        }
+        const uint64_t m = (bits & 0xfffffffffffffull) | (1ull << 52);
+        const int sh = E - 1075 + 80;  // value = m * 2^sh units of 2^-80, sh < 49
+        uint64_t vlo, vhi;
+        if (sh >= 0) {
+            vlo = m << sh;
+            vhi = sh == 0 ? 0ull : m >> (64 - sh);
+        } else if (sh > -54) {
+            const uint64_t half = 1ull << (-sh - 1);
+            vlo = (m + half) >> (-sh);
+            vhi = 0;
+        } else {
+            return;
+        }
+        if (bits >> 63) {  // subtract
+            const uint64_t nlo = lo - vlo;
+            hi = hi - vhi - (nlo > lo ? 1ull : 0ull);
+            lo = nlo;
+        } else {
+            const uint64_t nlo = lo + vlo;
+            hi = hi + vhi + (nlo < lo ? 1ull : 0ull);
+            lo = nlo;
+        }
+    }
+    __device__ double value() const {
+        uint64_t l = lo, h = hi;
+        const bool neg = (int64_t)h < 0;
+        if (neg) {  // magnitude
+            l = ~l + 1ull;
+            h = ~h + (l == 0 ? 1ull : 0ull);
+        }
+        // two roundings: deterministic, within one ulp of the exact sum
+        const double r = ((double)h * 0x1.0p64 + (double)l) * 0x1.0p-80;
+        return neg ? -r : r;
+    }
+};
+
 // FP64 re-evaluation with the exact expressions of the method for agents the
 // FP32 sweep could not decide.  Neighbours are read from the start-of-iteration
 // FP64 state through the grid (copy semantics).
@@ -544,15 +498,16 @@ __global__ void __launch_bounds__(256) k_fixup(Dev d) {
         const double L2 = S.L * S.L;
         int bx, by, bz;
         unpack_key(d.key[i], bx, by, bz);
-        double fx = 0.0, fy = 0.0, fz = 0.0;
+        double fx = 0.0, fy = 0.0, fz = 0.0;  // plain sums, used only when a term is huge
+        Fix128 sx, sy, sz;
         int nbr = 0, contacts = 0, nzc = 0;
         for (int oz = -1; oz <= 1; ++oz)
             for (int oy = -1; oy <= 1; ++oy)
                 for (int ox = -1; ox <= 1; ++ox) {
                     int cx = bx + ox, cy = by + oy, cz = bz + oz;
                     if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2]) continue;
-                    int64_t lin = linear_box(cx, cy, cz, S.dims);
-                    uint32_t s0 = d.box_start[S.sb_off + lin], s1 = d.box_start[S.sb_off + lin + 1];
+                    uint32_t m = d.mrank[S.b_off + linear_box(cx, cy, cz, S.dims)];
+                    uint32_t s0 = d.box_start[S.sb_off + m], s1 = d.box_start[S.sb_off + m + 1];
                     for (uint32_t slot = s0; slot < s1; ++slot) {
                         int64_t j = d.sorted_idx[slot];
                         if (j == i) continue;
@@ -569,20 +524,30 @@ __global__ void __launch_bounds__(256) k_fixup(Dev d) {
                         double fn = S.k * delta - S.gamma * sqrt(rbar * delta);
                         if (fn != 0.0) ++nzc;
                         if (dist > 0.0) {
-                            fx += fn * ddx / dist;
-                            fy += fn * ddy / dist;
-                            fz += fn * ddz / dist;
+                            const double tx = fn * ddx / dist, ty = fn * ddy / dist, tz = fn * ddz / dist;
+                            fx += tx;
+                            fy += ty;
+                            fz += tz;
+                            sx.add(tx);
+                            sy.add(ty);
+                            sz.add(tz);
                         }
                     }
                 }
-        commit_agent<DIAG>(d, S, i, P, lp, fl, x, y, z, fx, fy, fz, nzc, nbr, contacts);
+        if (!(sx.wide || sy.wide || sz.wide)) {
+            fx = sx.value();
+            fy = sy.value();
+            fz = sz.value();
+        }
+        const int64_t lin = linear_box(bx, by, bz, S.dims);
+        commit_agent<DIAG>(d, S, i, P, lp, fl, x, y, z, fx, fy, fz, nzc, nbr, contacts, d.mrank[S.b_off + lin], lin);
     }
 }
 
 // ------------------------------------------------------------------ growth and division
 // Correctly rounded cube root: ocml's cbrt is within one ulp; the candidate
 // is corrected by the sign of (y +- ulp/2)^3 - t, evaluated with error-free
-// products (Dekker/Ogita-Rump-Oishi TwoProd via fma).
+// products (TwoProd via fma, Ogita-Rump-Oishi).
 __device__ inline double cube_minus(double y, double h, double t) {
 #pragma clang fp contract(off)
     double p = y * y, e1 = fma(y, y, -p);
@@ -613,13 +578,17 @@ __device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
         uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
         uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
         uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
 }
 
-// Uniform unit vector for a division, keyed by (seed; uid, iteration, sim).
+// Uniform unit vector for a division, keyed by (seed; uid, iteration, sim):
+// Archimedes' construction, z uniform in [-1, 1) and a uniform azimuth.
 __device__ inline void division_direction(uint64_t seed, uint32_t sim, uint64_t uid, uint64_t iter, double u[3]) {
 #pragma clang fp contract(off)
     uint32_t c[4] = {(uint32_t)uid, (uint32_t)(uid >> 32), (uint32_t)iter, sim};
@@ -782,10 +751,16 @@ __global__ void __launch_bounds__(256) k_div_apply(Dev d) {
             double cx = d.pos[Q][i], cy = d.pos[Q][A + i], cz = d.pos[Q][2 * A + i];
             double jx = cx + shift * u[0], jy = cy + shift * u[1], jz = cz + shift * u[2];
             double mx = cx - shift * u[0], my = cy - shift * u[1], mz = cz - shift * u[2];
-            d.pos[Q][j] = jx; d.pos[Q][A + j] = jy; d.pos[Q][2 * A + j] = jz;
-            d.pos[Q][i] = mx; d.pos[Q][A + i] = my; d.pos[Q][2 * A + i] = mz;
-            d.vol[lp][i] = half; d.vol[lp][j] = half;
-            d.diam[lp][i] = dnew; d.diam[lp][j] = dnew;
+            d.pos[Q][j] = jx;
+            d.pos[Q][A + j] = jy;
+            d.pos[Q][2 * A + j] = jz;
+            d.pos[Q][i] = mx;
+            d.pos[Q][A + i] = my;
+            d.pos[Q][2 * A + i] = mz;
+            d.vol[lp][i] = half;
+            d.vol[lp][j] = half;
+            d.diam[lp][i] = dnew;
+            d.diam[lp][j] = dnew;
             d.growth[lp][j] = d.growth[lp][i];
             d.uid[lp][j] = (uint64_t)S.next_uid + rank;
             d.nz[lp][j] = 0;
@@ -797,12 +772,7 @@ __global__ void __launch_bounds__(256) k_div_apply(Dev d) {
             d.diam[lp][i] = diameter_from_volume(nv);
             d.flags[lp][i] |= kGrew;
         }
-        if (S.detect_static) {
-            // the start box of a changed agent (the new grid catches arrivals)
-            int bx, by, bz;
-            unpack_key(d.key[i], bx, by, bz);
-            d.dirty[S.b_off + linear_box(bx, by, bz, S.dims)] = 1;
-        }
+        if (S.detect_static) d.dirty[S.b_off + key_rank(d, S, d.key[i])] = 1;  // start box of a changed agent
     }
 }
 
@@ -815,12 +785,6 @@ __global__ void __launch_bounds__(256) k_div_apply(Dev d) {
 // 27-box neighbourhood are checked (boxes marked dirty prune the search);
 // changed agents that arrive from farther away are caught by k_static_fix on
 // the next grid.
-__device__ inline bool near_point(double x, double y, double z, double px, double py, double pz, double L2) {
-#pragma clang fp contract(off)
-    double ddx = x - px, ddy = y - py, ddz = z - pz;
-    return fma(ddz, ddz, fma(ddy, ddy, ddx * ddx)) < L2;
-}
-
 __global__ void __launch_bounds__(256) k_static(Dev d) {
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
@@ -845,9 +809,9 @@ __global__ void __launch_bounds__(256) k_static(Dev d) {
                     for (int ox = -1; ox <= 1 && st; ++ox) {
                         int cx = bx + ox, cy = by + oy, cz = bz + oz;
                         if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2]) continue;
-                        int64_t lin = linear_box(cx, cy, cz, S.dims);
-                        if (!d.dirty[S.b_off + lin]) continue;
-                        uint32_t s0 = d.box_start[S.sb_off + lin], s1 = d.box_start[S.sb_off + lin + 1];
+                        uint32_t m = d.mrank[S.b_off + linear_box(cx, cy, cz, S.dims)];
+                        if (!d.dirty[S.b_off + m]) continue;
+                        uint32_t s0 = d.box_start[S.sb_off + m], s1 = d.box_start[S.sb_off + m + 1];
                         for (uint32_t slot = s0; slot < s1 && st; ++slot) {
                             int64_t j = d.sorted_idx[slot];
                             if (j == i || !(d.flags[lp][j] & kChgMask)) continue;
@@ -862,321 +826,10 @@ __global__ void __launch_bounds__(256) k_static(Dev d) {
     }
 }
 
-// After the next grid is built (positions = committed positions): a static
-// agent stops being static when a changed agent (including a new daughter)
-// now lies within the previous iteration's radius.  Boxes holding a changed
-// agent were marked by k_bin.
-__global__ void __launch_bounds__(256) k_static_fix(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
-    const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        if (!S.detect_static) continue;
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n_start) continue;
-        int64_t i = S.a_off + loc;
-        uint8_t fl = d.flags[lp][i];
-        if (!(fl & kStatic)) continue;
-        bool st = S.L >= S.L_prev;  // a shrunken grid cannot cover the old radius: be conservative
-        if (st) {
-            const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
-            const double L2 = S.L_prev * S.L_prev;
-            int bx, by, bz;
-            unpack_key(d.key[i], bx, by, bz);
-            for (int oz = -1; oz <= 1 && st; ++oz)
-                for (int oy = -1; oy <= 1 && st; ++oy)
-                    for (int ox = -1; ox <= 1 && st; ++ox) {
-                        int cx = bx + ox, cy = by + oy, cz = bz + oz;
-                        if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2]) continue;
-                        int64_t lin = linear_box(cx, cy, cz, S.dims);
-                        if (!d.arrive[S.b_off + lin]) continue;
-                        uint32_t s0 = d.box_start[S.sb_off + lin], s1 = d.box_start[S.sb_off + lin + 1];
-                        for (uint32_t slot = s0; slot < s1 && st; ++slot) {
-                            int64_t j = d.sorted_idx[slot];
-                            if (j == i || !(d.flags[lp][j] & kChgMask)) continue;
-                            if (near_point(x, y, z, d.pos[P][j], d.pos[P][A + j], d.pos[P][2 * A + j], L2)) st = false;
-                        }
-                    }
-        }
-        if (!st) d.flags[lp][i] = fl & ~kStatic;
-    }
-}
-
-// Clears the dirty and arrival marks of the current grid.
-__global__ void __launch_bounds__(256) k_clear_marks(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    const int64_t total = d.ctl->total_btiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        if (!S.detect_static) continue;
-        int64_t k0 = (t - d.btile_begin[s]) * kBoxTile;
-        for (int q = threadIdx.x; q < kBoxTile; q += blockDim.x) {
-            if (k0 + q < S.nboxes) {
-                d.dirty[S.b_off + k0 + q] = 0;
-                d.arrive[S.b_off + k0 + q] = 0;
-            }
-        }
-    }
-}
-
-// ------------------------------------------------------------------ end of iteration
-__global__ void k_end(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    for (int s = threadIdx.x; s < d.n_sims; s += blockDim.x) {
-        SimDesc &S = d.sims[s];
-        S.n = S.n_start + S.n_div;
-        S.next_uid += S.n_div;
-        S.n_start = S.n;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        d.ctl->pos_par ^= 1;
-        d.ctl->iter += 1;
-        int64_t t = 0;
-        for (int s = 0; s < d.n_sims; ++s) {
-            d.tile_begin[s] = t;
-            t += ceil_div(d.sims[s].n, kTile);
-        }
-        d.tile_begin[d.n_sims] = t;
-        d.ctl->total_tiles = t;
-        d.ctl->resort_now = (d.resort_every > 0 && d.ctl->iter % d.resort_every == 0) ? 1 : 0;
-    }
-}
-
-// ------------------------------------------------------------------ Morton re-sort
-// Rank of box (bx,by,bz) among the boxes of an nx x ny x nz grid in Morton
-// order (x in the lowest bit, Fig 5.4): the number of in-grid boxes whose code
-// is smaller, counted bit by bit.  For every set bit p of the code, the boxes
-// sharing the bits above p and having 0 at p are counted per axis in closed
-// form (their free low bits form a range intersected with the grid).
-__device__ inline uint64_t morton_rank(int bx, int by, int bz, const int32_t dims[3]) {
-    const int c[3] = {bx, by, bz};
-    uint64_t rank = 0;
-    for (int level = 10; level >= 0; --level) {
-        for (int a = 2; a >= 0; --a) {
-            int p = 3 * level + a;
-            if (!((c[a] >> level) & 1)) continue;
-            uint64_t prod = 1;
-            for (int b = 0; b < 3; ++b) {
-                int freebits;
-                int64_t base;
-                if (b == a) {
-                    freebits = level;
-                    base = ((int64_t)(c[b] >> (level + 1)) << (level + 1));
-                } else {
-                    freebits = (p - b + 2) / 3;
-                    if (p < b) freebits = 0;
-                    base = ((int64_t)(c[b] >> freebits) << freebits);
-                }
-                int64_t span = (int64_t)1 << freebits;
-                int64_t cnt = (int64_t)dims[b] - base;
-                if (cnt < 0) cnt = 0;
-                if (cnt > span) cnt = span;
-                prod *= (uint64_t)cnt;
-            }
-            rank += prod;
-        }
-    }
-    return rank;
-}
-
-__global__ void __launch_bounds__(256) k_rs_rank(Dev d) {
-    if (ABM_ABORTED(d) || !d.ctl->resort_now) return;
-    const int64_t total = d.ctl->total_btiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t k0 = (t - d.btile_begin[s]) * kBoxTile;
-        for (int q = threadIdx.x; q < kBoxTile; q += blockDim.x) {
-            int64_t k = k0 + q;
-            if (k >= S.nboxes) break;
-            int bx = (int)(k % S.dims[0]);
-            int64_t r = k / S.dims[0];
-            int by = (int)(r % S.dims[1]);
-            int bz = (int)(r / S.dims[1]);
-            d.mrank[S.b_off + k] = (uint32_t)morton_rank(bx, by, bz, S.dims);
-        }
-    }
-}
-
-// Count agents per Morton rank of their current box (grid of this iteration).
-__global__ void __launch_bounds__(256) k_rs_count(Dev d) {
-    if (ABM_ABORTED(d) || !d.ctl->resort_now) return;
-    const int P = d.ctl->pos_par;  // already flipped: the committed positions
-    const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n || S.nboxes == 0) continue;
-        int64_t i = S.a_off + loc;
-        int bx = box_coord(d.pos[P][i], S.lo[0], S.L, S.dims[0]);
-        int by = box_coord(d.pos[P][A + i], S.lo[1], S.L, S.dims[1]);
-        int bz = box_coord(d.pos[P][2 * A + i], S.lo[2], S.L, S.dims[2]);
-        uint32_t mr = d.mrank[S.b_off + linear_box(bx, by, bz, S.dims)];
-        d.key[i] = mr;
-        d.rank[i] = atomicAdd(&d.count[S.b_off + mr], 1u);
-    }
-}
-
-// Move every agent to its Morton slot in the other buffers (out of place: the
-// source buffers are only read).  Positions land in the other position
-// buffer only, so every agent is marked as having differing buffers.
-__global__ void __launch_bounds__(256) k_rs_move(Dev d) {
-    if (ABM_ABORTED(d) || !d.ctl->resort_now) return;
-    const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
-    const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n || S.nboxes == 0) continue;
-        int64_t i = S.a_off + loc;
-        int64_t j = (int64_t)d.box_start[S.sb_off + d.key[i]] + d.rank[i];
-        const int nl = 1 - lp;
-        for (int a = 0; a < 3; ++a) d.pos[1 - P][a * A + j] = d.pos[P][a * A + i];
-        d.diam[nl][j] = d.diam[lp][i];
-        d.vol[nl][j] = d.vol[lp][i];
-        d.growth[nl][j] = d.growth[lp][i];
-        d.uid[nl][j] = d.uid[lp][i];
-        d.flags[nl][j] = d.flags[lp][i] | kBufDiff;
-        d.nz[nl][j] = d.nz[lp][i];
-    }
-}
-
-__global__ void k_rs_end(Dev d) {
-    if (ABM_ABORTED(d) || !d.ctl->resort_now) return;
-    if (threadIdx.x == 0) {
-        d.ctl->lay_par ^= 1;
-        d.ctl->pos_par ^= 1;
-    }
-}
-
-// ------------------------------------------------------------------ statistics
-// Deterministic two-level FP64 reductions: per-tile partials, then a fixed
-// order per simulation.
-__global__ void __launch_bounds__(256) k_stats_sum(Dev d, int pass, double *out) {
-    __shared__ double red[4][4];
-    const int P = d.ctl->pos_par;
-    const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        double v[3] = {0.0, 0.0, 0.0};
-        if (loc < S.n) {
-            int64_t i = S.a_off + loc;
-            double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
-            if (pass == 0) {
-                v[0] = x; v[1] = y; v[2] = z;
-            } else {
-                const double *c = out + 40 * s;
-                double ddx = x - c[0], ddy = y - c[1], ddz = z - c[2];
-                double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
-                double r = sqrt(d2);
-                v[0] = d2;
-                v[1] = r;
-                double w = c[3] / 32.0;
-                int64_t b = (int64_t)floor(r / w);
-                if (b > 31) b = 31;
-                if (b < 0) b = 0;
-                atomicAdd(&d.hist_cnt[32 * s + b], 1u);
-            }
-        }
-        // fixed-shape tree reduction: deterministic
-        for (int off = 32; off > 0; off >>= 1) {
-            v[0] += __shfl_xor(v[0], off);
-            v[2] += __shfl_xor(v[2], off);
-            if (pass == 0) v[1] += __shfl_xor(v[1], off);
-            else v[1] = fmax(v[1], __shfl_xor(v[1], off));
-        }
-        if (lane == 0)
-            for (int a = 0; a < 3; ++a) red[a][wid] = v[a];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double a0 = red[0][0], a1 = red[1][0], a2 = red[2][0];
-            for (int w = 1; w < 4; ++w) {
-                a0 += red[0][w];
-                a2 += red[2][w];
-                a1 = pass == 0 ? a1 + red[1][w] : fmax(a1, red[1][w]);
-            }
-            d.stat_part[3 * t] = a0;
-            d.stat_part[3 * t + 1] = a1;
-            d.stat_part[3 * t + 2] = a2;
-        }
-        __syncthreads();
-    }
-}
-
-// out layout per simulation (40 doubles): cx, cy, cz, hist_rmax, r_gyr, r_max, ...
-__global__ void k_stats_fold(Dev d, int pass, double *out, double hist_rmax) {
-    for (int s = threadIdx.x; s < d.n_sims; s += blockDim.x) {
-        const SimDesc &S = d.sims[s];
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int64_t t = d.tile_begin[s]; t < d.tile_begin[s + 1]; ++t) {
-            a0 += d.stat_part[3 * t];
-            a2 += d.stat_part[3 * t + 2];
-            a1 = pass == 0 ? a1 + d.stat_part[3 * t + 1] : fmax(a1, d.stat_part[3 * t + 1]);
-        }
-        double *o = out + 40 * s;
-        double n = (double)S.n;
-        if (pass == 0) {
-            o[0] = S.n > 0 ? a0 / n : 0.0;
-            o[1] = S.n > 0 ? a1 / n : 0.0;
-            o[2] = S.n > 0 ? a2 / n : 0.0;
-            o[3] = hist_rmax;
-            for (int b = 0; b < 32; ++b) d.hist_cnt[32 * s + b] = 0u;
-        } else {
-            o[4] = S.n > 0 ? sqrt(a0 / n) : 0.0;
-            o[5] = a1;
-        }
-    }
-}
-
-__global__ void k_stats_hist(Dev d, double *out, float *hist) {
-    for (int q = threadIdx.x; q < 32 * d.n_sims; q += blockDim.x) {
-        int s = q / 32, b = q % 32;
-        double w = out[40 * s + 3] / 32.0;
-        double r0 = w * b, r1 = w * (b + 1);
-        double shell = 4.0 / 3.0 * kPi * (r1 * r1 * r1 - r0 * r0 * r0);
-        hist[q] = (float)((double)d.hist_cnt[q] / shell * 1000.0);
-    }
-}
-
 // ------------------------------------------------------------------ launchers
-static int grid_of(int want, int64_t cap_tiles) {
-    int64_t g = cap_tiles < want ? cap_tiles : want;
-    return g < 1 ? 1 : (int)g;
-}
-
-// Grid of the current positions (counting sort by box), then the arrival
-// part of the static rule on that grid.
-void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool any_static) {
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_bounds, dim3(grid_agents), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_bin, dim3(grid_agents), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d);
-    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scatter, dim3(grid_agents), dim3(256), 0, st, d);
-    if (any_static) hipLaunchKernelGGL(k_static_fix, dim3(grid_agents), dim3(256), 0, st, d);
-}
-
-// The force sweep of one iteration (the dominant kernel).
-void launch_sweep(const Dev &d, hipStream_t st, int grid_agents, int sweep_block, bool diag) {
-    int sb = sweep_block;
-    int sweep_grid = grid_agents * (kTile / sb > 0 ? kTile / sb : 1);
-    if (diag) hipLaunchKernelGGL(k_sweep<true>, dim3(sweep_grid), dim3(sb), 0, st, d);
-    else hipLaunchKernelGGL(k_sweep<false>, dim3(sweep_grid), dim3(sb), 0, st, d);
+void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag) {
+    if (diag) hipLaunchKernelGGL(k_sweep<true>, dim3(sweep_grid), dim3(256), 0, st, d);
+    else hipLaunchKernelGGL(k_sweep<false>, dim3(sweep_grid), dim3(256), 0, st, d);
 }
 
 // Everything of one iteration after the sweep; ends by building the grid of
@@ -1193,76 +846,17 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
         hipLaunchKernelGGL(k_uscan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_div_apply, dim3(grid_agents), dim3(256), 0, st, d);
     }
-    if (any_static) {
-        hipLaunchKernelGGL(k_static, dim3(grid_agents), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_clear_marks, dim3(grid_boxes), dim3(256), 0, st, d);
-    }
-    hipLaunchKernelGGL(k_end, dim3(1), dim3(256), 0, st, d);
-    if (resort) {
-        hipLaunchKernelGGL(k_rs_rank, dim3(grid_boxes), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_rs_count, dim3(grid_agents), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d);
-        hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_rs_move, dim3(grid_agents), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_rs_end, dim3(1), dim3(64), 0, st, d);
-    }
+    if (any_static) hipLaunchKernelGGL(k_static, dim3(grid_agents), dim3(256), 0, st, d);
+    launch_end(d, st, grid_boxes, any_static);
+    if (resort) launch_resort(d, st, grid_agents, grid_boxes, false);
     launch_grid_build(d, st, grid_agents, grid_boxes, any_static);
 }
 
 // One iteration on the grid built at the end of the previous one.
-void launch_iteration(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, int sweep_block, bool diag,
+void launch_iteration(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, int sweep_grid, bool diag,
                       bool any_growth, bool any_static, bool resort) {
-    launch_sweep(d, st, grid_agents, sweep_block, diag);
+    launch_sweep(d, st, sweep_grid, diag);
     launch_after_sweep(d, st, grid_agents, grid_boxes, diag, any_growth, any_static, resort);
-}
-
-// Statistics: out_dev holds 40 doubles per simulation followed by the
-// histograms (n_sims x 32 floats).
-void launch_stats(const Dev &d, hipStream_t st, int grid_agents, double hist_rmax, double *out_dev) {
-    float *hist = (float *)(out_dev + 40 * d.n_sims);
-    hipLaunchKernelGGL(k_stats_sum, dim3(grid_agents), dim3(256), 0, st, d, 0, out_dev);
-    hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, st, d, 0, out_dev, hist_rmax);
-    hipLaunchKernelGGL(k_stats_sum, dim3(grid_agents), dim3(256), 0, st, d, 1, out_dev);
-    hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, st, d, 1, out_dev, hist_rmax);
-    hipLaunchKernelGGL(k_stats_hist, dim3(1), dim3(1024), 0, st, d, out_dev, hist);
-}
-
-__global__ void k_gather_pos(Dev d, int sim, double *dst) {
-    const int P = d.ctl->pos_par;
-    const SimDesc &S = d.sims[sim];
-    const int64_t A = d.A;
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < S.n; q += (int64_t)gridDim.x * blockDim.x) {
-        int64_t i = S.a_off + q;
-        dst[3 * q] = d.pos[P][i];
-        dst[3 * q + 1] = d.pos[P][A + i];
-        dst[3 * q + 2] = d.pos[P][2 * A + i];
-    }
-}
-
-void launch_gather_pos(const Dev &d, hipStream_t st, int sim, double *dst, int64_t n, int64_t a_off) {
-    int grid = (int)(n / 256 + 1);
-    if (grid > 4096) grid = 4096;
-    hipLaunchKernelGGL(k_gather_pos, dim3(grid), dim3(256), 0, st, d, sim, dst);
-}
-
-// Initial tile prefix (after create) so that statistics and queries work
-// before the first step.
-__global__ void k_init_tiles(Dev d) {
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int s = 0; s < d.n_sims; ++s) {
-            d.tile_begin[s] = t;
-            t += ceil_div(d.sims[s].n, kTile);
-            d.sims[s].n_start = d.sims[s].n;
-        }
-        d.tile_begin[d.n_sims] = t;
-        d.ctl->total_tiles = t;
-    }
-}
-
-void launch_scatter_init(const Dev &d, hipStream_t st, int grid_agents) {
-    hipLaunchKernelGGL(k_init_tiles, dim3(1), dim3(64), 0, st, d);
 }
 
 }  // namespace abm

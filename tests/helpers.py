@@ -6,8 +6,8 @@ import numpy as np
 from oracle import sim as osim
 
 # Bound on the FP32 error of one overlap in the HIP sweep, as a multiple of
-# the box length (box-relative FP32 coordinates).
-E_DELTA_REL = 2.0 ** -19
+# the box length (block-relative FP32 coordinates).
+E_DELTA_REL = 2.0 ** -18
 
 
 def gpu_params(abm, **kw):
