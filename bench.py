@@ -83,6 +83,19 @@ def cpu_baseline(args):
                       f"iterations after one untimed iteration, FP64, OpenMP over agents, {dt:.1f} s"}
 
 
+def copy_calibration(torch, steps):
+    """A plain copy of known size: the HBM byte counters of one such launch,
+    divided by the bytes it must move (2 GiB read, 2 GiB written), give the
+    scale factor for the counters of the other kernels."""
+    n = 2 ** 31 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": steps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +108,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-agents", type=int, default=1_000_000)
     ap.add_argument("--cpu-sample-iters", type=int, default=5)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 2 GiB (reference kernel for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -102,6 +117,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        copy_calibration(torch, args.steps)
+        return
     sys.path.insert(0, ROOT)
     from paper_2503_10796_amd import abm, inputs
 

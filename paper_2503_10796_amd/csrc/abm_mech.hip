@@ -28,7 +28,8 @@ constexpr double kFixUnit = 0x1.0p-40;
 constexpr int kHalo = kBlk + 2;              // 6
 constexpr int kNb = kHalo * kHalo * kHalo;   // 216 staged boxes
 constexpr int kCore = kBlk * kBlk * kBlk;    // 64 target boxes
-constexpr int kStage = 2048;                 // staged agents (32 KB of float4)
+constexpr int kStage = 1024;                 // staged agents (16 KB of float4), a power of two
+static_assert((kStage & (kStage - 1)) == 0, "staged indices are wrapped with a mask");
 
 __device__ inline unsigned long long fixbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
@@ -117,52 +118,92 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
     }
 }
 
-// Per-target accumulator of the FP32 sweep.
-struct Acc {
-    unsigned long long ax, ay, az;  // force components in 2^-40 units, plus nfix * magic bits (mod 2^64)
-    uint32_t eacc;         // error bound in 2^-26 units (rounded up per pair)
-    int contacts, nz, nbr, nfix;
-    bool unc;              // an integer outcome is not decidable in FP32
+// ------------------------------------------------------------------ sweep
+// Per work unit (an aligned 4x4x4 block of boxes):
+//   table    start and count of the 6x6x6 staged boxes (block scan)
+//   stage    FP32 payload of the region into LDS, relative to its centre
+//   setup    per target: static skip (Sec 5.5) or nine tasks, one per row of
+//            three boxes (x-1..x+1) of its 27-box neighbourhood; the tasks
+//            are counting-sorted by row length, so the 64 lanes of a wave
+//            hold rows of about equal length and run equal trip counts
+//   sweep    each lane tests its row against the pair's contact reach plus
+//            the guard band; survivors go to a per-wave LDS queue, which is
+//            drained 64 pairs at a time through the contact math (Eq 4.1-4.2)
+//            with exact fixed-point LDS atomics into per-target accumulators
+//   commit   per target: threshold, displacement, write-back (or FP64 path)
+// Units whose region does not fit in LDS take a slower global-memory path.
+constexpr int kMaxT = 320;      // targets per unit on the LDS path
+constexpr int kBuckets = 64;    // task lengths 1..63, longer rows share the last bucket
+constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 16 | staged index)
+constexpr uint32_t kUncBit = 0x80000000u;
+constexpr uint16_t kNoTarget = 0xffff;
+
+template <bool DIAG>
+struct SweepLds {
+    float4 sp[kStage];                      // staged payload, block-relative coordinates
+    unsigned long long acc[3][kMaxT];       // force sums, 2^-40 units (two's complement)
+    uint32_t acnt[kMaxT];                   // contacts, plus kUncBit
+    uint32_t aeacc[kMaxT];                  // FP32 error bound of the sum, 2^-26 units
+    uint32_t anbr[DIAG ? kMaxT : 1];        // neighbours within the box length
+    uint32_t sbeg[kNb + 1];                 // exclusive prefix of the staged box counts
+    uint32_t gsrc[kNb];                     // global slot start of every staged box
+    uint32_t coff[kCore + 1];               // prefix of the target counts of the core boxes
+    uint32_t scnt[kNb];
+    uint32_t bcnt[kBuckets], boff[kBuckets];
+    uint32_t queue[4][kQueue];
+    uint32_t sh[4];
+    uint32_t ntask;
+    uint16_t task[9 * kMaxT];               // target << 4 | row, sorted by row length (longest first)
+    uint32_t trow[kMaxT];                   // per row r, bits 3r..3r+2: row used, left box, right box
+    uint16_t tself[kMaxT];                  // staged index of each target (kNoTarget: static)
+    uint8_t tbox[kMaxT];                    // core box of each target
 };
 
-// Contact part of one pair: (ddx,ddy,ddz) = target minus candidate, d2 its
-// squared length, ri/rj the radii.  Decides contact (delta > 0) and non-zero
-// force, accumulates the force in fixed point and its error bound; marks the
-// target undecidable when FP32 cannot certify an integer outcome.
-__device__ inline void pair_contact(Acc &a, float ddx, float ddy, float ddz, float d2, float ri, float rj, float e,
-                                    float g, float kf, float gf, float L2m, float L2p) {
+// Per-target accumulator of the global-memory path.
+struct Acc {
+    unsigned long long ax, ay, az;  // force components in 2^-40 units, plus nfix * magic bits (mod 2^64)
+    uint32_t eacc;                  // error bound in 2^-26 units (rounded up per pair)
+    int contacts, nz, nbr, nfix;
+    bool unc;                       // an integer outcome is not decidable in FP32
+};
+
+// Contact math of one pair in FP32 (target minus candidate = (ddx,ddy,ddz),
+// squared length d2, radii ri, rj).  Decides contact (overlap > 0) and
+// non-zero force and returns the force factor F_N / dist; marks the pair
+// undecidable (unc) when FP32 cannot certify an integer outcome: coincident
+// centres, a distance at the box length, an overlap or a force within its
+// error bound of zero.  ep: error bound of F_N.
+struct PairOut {
+    bool contact, unc;
+    float f, ep;
+};
+__device__ inline PairOut pair_math(float ddx, float ddy, float ddz, float d2, float ri, float rj, float e, float g,
+                                    float kf, float gf, float L2m, float L2p, bool valid) {
+    PairOut o;
     const float sr = ri + rj;
-    const float sg = sr + g;
-    if (!(d2 < sg * sg)) return;
-    if (d2 >= L2m) {  // only possible when the box length is below the largest diameter
-        if (d2 < L2p) a.unc = true;
-        return;
-    }
-    const float dist = sqrtf(d2);
+    const float sg = (ri + g) + rj;  // the same rounding as the reach test of the sweep
+    bool cand = valid && d2 < sg * sg;
+    const bool beyond = d2 >= L2m;  // only when the box length is below the largest diameter
+    bool unc = cand && beyond && d2 < L2p;
+    unc |= cand && d2 < g * g;  // (near-)coincident centres: direction left to FP64
+    cand = cand && !beyond && d2 >= g * g;
+    const float dist = __builtin_amdgcn_sqrtf(d2);
     const float delta = sr - dist;
-    if (delta <= e) {
-        if (delta >= -e) a.unc = true;
-        return;
-    }
-    ++a.contacts;
+    unc |= cand && delta <= e && delta >= -e;
+    bool contact = cand && delta > e;
     const float rbar = ri * rj * __builtin_amdgcn_rcpf(sr);
-    const float sq = sqrtf(rbar * delta);
+    const float sq = __builtin_amdgcn_sqrtf(fmaxf(rbar * delta, 0.0f));
     const float kd = kf * delta, gs = gf * sq;
     const float fn = kd - gs;
     // bound on |fn error|: conditioning of Eq 4.1 times the overlap error,
     // plus FP32 rounding relative to the magnitudes of both terms
     const float ep = (kf + 0.5f * gs * __builtin_amdgcn_rcpf(delta)) * e + (kd + gs) * 0x1.0p-19f;
-    if (ep >= 0x1.0p-6f || fabsf(fn) <= ep) {
-        a.unc = true;
-        return;
-    }
-    ++a.nz;
-    const double f = (double)(fn * __builtin_amdgcn_rcpf(dist));
-    a.ax += fixbits(fma(f, (double)ddx, kFixMagic));
-    a.ay += fixbits(fma(f, (double)ddy, kFixMagic));
-    a.az += fixbits(fma(f, (double)ddz, kFixMagic));
-    ++a.nfix;
-    a.eacc += (uint32_t)ceilf(ep * 0x1.0p26f);
+    const bool bad = contact && (ep >= 0x1.0p-6f || fabsf(fn) <= ep);
+    o.unc = unc || bad;
+    o.contact = contact && !bad;
+    o.f = fn * __builtin_amdgcn_rcpf(dist);
+    o.ep = ep;
+    return o;
 }
 
 // One candidate pair in FP32 box-relative coordinates (global-memory path).
@@ -176,83 +217,155 @@ __device__ inline void pair_fp32(Acc &a, float qx, float qy, float qz, float ri,
         if (d2 < L2m) ++a.nbr;
         else if (d2 < L2p) a.unc = true;
     }
-    pair_contact(a, ddx, ddy, ddz, d2, ri, c.w, e, g, kf, gf, L2m, L2p);
-}
-
-// ------------------------------------------------------------------ sweep
-constexpr int kList = 32;  // per-thread list of candidates within reach (u16 LDS indices)
-constexpr int kChunk = 16;  // candidates tested between two list-room checks
-
-__device__ inline uint32_t wave_max_u32(uint32_t v) {
-    for (int off = 32; off > 0; off >>= 1) {
-        uint32_t o = __shfl_xor(v, off);
-        v = o > v ? o : v;
-    }
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-// Contact math of the listed candidates (phase 2), block-relative FP32
-// coordinates.  Wave-uniform loop with predication: no branches per entry.
-// Coincident or near-coincident centres, overlaps and forces within their
-// FP32 error bound of a decision threshold mark the target for FP64.
-__device__ inline void drain_list(Acc &a, const float4 *sp, const uint16_t *lst, uint32_t n, uint32_t self, float4 own,
-                                  float e, float g, float kf, float gf, float L2m, float L2p) {
-    const uint32_t nmax = wave_max_u32(n);
-    for (uint32_t k = 0; k < nmax; ++k) {
-        uint32_t q = lst[k * 256 + threadIdx.x];
-        q = q < (uint32_t)kStage ? q : 0u;
-        const bool valid = k < n && q != self;
-        const float4 c = sp[q];
-        const float ddx = valid ? own.x - c.x : 0.0f;
-        const float ddy = valid ? own.y - c.y : 0.0f;
-        const float ddz = valid ? own.z - c.z : 0.0f;
-        const float rj = valid ? c.w : 0.0f;
-        const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-        const float sr = own.w + rj;
-        const float sg = sr + g;
-        bool cand = valid && d2 < sg * sg;
-        const bool beyond = d2 >= L2m;  // only when the box length is below the largest diameter
-        bool unc = cand && beyond && d2 < L2p;
-        unc |= cand && d2 < g * g;  // (near-)coincident centres: direction left to FP64
-        cand = cand && !beyond && d2 >= g * g;
-        const float dist = __builtin_amdgcn_sqrtf(d2);
-        const float delta = sr - dist;
-        unc |= cand && delta <= e && delta >= -e;
-        bool contact = cand && delta > e;
-        const float rbar = own.w * rj * __builtin_amdgcn_rcpf(sr);
-        const float sq = __builtin_amdgcn_sqrtf(fmaxf(rbar * delta, 0.0f));
-        const float kd = kf * delta, gs = gf * sq;
-        const float fn = kd - gs;
-        const float ep = (kf + 0.5f * gs * __builtin_amdgcn_rcpf(delta)) * e + (kd + gs) * 0x1.0p-19f;
-        const bool bad = contact && (ep >= 0x1.0p-6f || fabsf(fn) <= ep);
-        unc |= bad;
-        contact = contact && !bad;
-        a.unc |= unc;
-        a.contacts += contact ? 1 : 0;
-        a.nz += contact ? 1 : 0;
-        const double f = contact ? (double)(fn * __builtin_amdgcn_rcpf(dist)) : 0.0;
+    const PairOut o = pair_math(ddx, ddy, ddz, d2, ri, c.w, e, g, kf, gf, L2m, L2p, true);
+    a.unc |= o.unc;
+    if (o.contact) {
+        ++a.contacts;
+        ++a.nz;
+        const double f = (double)o.f;
         a.ax += fixbits(fma(f, (double)ddx, kFixMagic));
         a.ay += fixbits(fma(f, (double)ddy, kFixMagic));
         a.az += fixbits(fma(f, (double)ddz, kFixMagic));
         ++a.nfix;
-        a.eacc += contact ? (uint32_t)ceilf(ep * 0x1.0p26f) : 0u;
+        a.eacc += (uint32_t)ceilf(o.ep * 0x1.0p26f);
+    }
+}
+
+// Drains `cnt` (<= 64) queued pairs of this wave (lane l takes entry l).
+template <bool DIAG>
+__device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32_t cnt, float e, float g, float kf,
+                                   float gf, float L2m, float L2p) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t ent = qw[lane];
+    const uint32_t t = lane < cnt ? ent >> 16 : 0u;
+    const uint32_t q = lane < cnt ? ent & 0xffffu : 0u;
+    const uint32_t self = L.tself[t];
+    const bool valid = lane < cnt && q != self && self != kNoTarget;
+    const float4 own = L.sp[valid ? self : 0u];
+    const float4 c = L.sp[q];
+    const float ddx = own.x - c.x, ddy = own.y - c.y, ddz = own.z - c.z;
+    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+    const PairOut o = pair_math(ddx, ddy, ddz, d2, own.w, c.w, e, g, kf, gf, L2m, L2p, valid);
+    if (o.contact) {
+        const double f = (double)o.f;
+        const unsigned long long mb = fixbits(kFixMagic);
+        atomicAdd(&L.acc[0][t], fixbits(fma(f, (double)ddx, kFixMagic)) - mb);
+        atomicAdd(&L.acc[1][t], fixbits(fma(f, (double)ddy, kFixMagic)) - mb);
+        atomicAdd(&L.acc[2][t], fixbits(fma(f, (double)ddz, kFixMagic)) - mb);
+        atomicAdd(&L.acnt[t], 1u);
+        atomicAdd(&L.aeacc[t], (uint32_t)ceilf(o.ep * 0x1.0p26f));
+    }
+    if (o.unc) atomicOr(&L.acnt[t], kUncBit);
+}
+
+__device__ inline void core_box_coords(int c, int &cx, int &cy, int &cz) {
+    cx = c & 3;
+    cy = (c >> 2) & 3;
+    cz = c >> 4;
+}
+// Staged row (boxes x-1..x+1 around core box (cx,cy,cz)) of task row r.
+__device__ inline int task_row(int cx, int cy, int cz, int r) {
+    return cx + kHalo * ((cy + r % 3) + kHalo * (cz + r / 3));
+}
+
+// Rows of a target's 27-box neighbourhood that can hold a pair within reach
+// (bits 3r..3r+2 per row r: row used, its left box, its right box).  `reach`
+// bounds the pair's contact distance plus the guard band, with a margin for
+// the FP32 block-relative coordinates: a box whose distance from the target
+// exceeds it cannot hold a pair that the sweep keeps.  With DIAG every box is
+// visited (all neighbours within the box length are counted).
+template <bool DIAG>
+__device__ inline uint32_t row_mask(float4 own, int cx, int cy, int cz, float Lf, float reach_add) {
+    if (DIAG) return 0x7ffffffu;
+    const float reach = own.w + reach_add;
+    const float r2 = reach * reach;
+    // distances to the faces of the target box (local box c+1 spans [(c-2)L, (c-1)L))
+    const float fx0 = own.x - (float)(cx - 2) * Lf, fx1 = Lf - fx0;
+    const float fy0 = own.y - (float)(cy - 2) * Lf, fy1 = Lf - fy0;
+    const float fz0 = own.z - (float)(cz - 2) * Lf, fz1 = Lf - fz0;
+    uint32_t m = 0;
+    for (int r = 0; r < 9; ++r) {
+        const int dy = r % 3 - 1, dz = r / 3 - 1;
+        const float gy = dy < 0 ? fy0 : (dy > 0 ? fy1 : 0.0f);
+        const float gz = dz < 0 ? fz0 : (dz > 0 ? fz1 : 0.0f);
+        const float rem = r2 - gy * gy - gz * gz;
+        if (rem > 0.0f) {
+            const uint32_t b = 1u | (fx0 * fx0 < rem ? 2u : 0u) | (fx1 * fx1 < rem ? 4u : 0u);
+            m |= b << (3 * r);
+        }
+    }
+    return m;
+}
+
+// Global-memory path of one unit (region larger than the LDS stage, or more
+// targets than kMaxT): one thread per target over its 27 boxes.
+template <bool DIAG>
+__device__ void sweep_unit_global(const Dev &d, const SimDesc &S, SweepLds<DIAG> &L, int P, int lp, int qx, int qy,
+                                  int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
+    const int64_t A = d.A;
+    const uint32_t nt = L.coff[kCore];
+    const float Lf = (float)S.L;
+    for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
+        int c = 0, hi = kCore;
+        while (hi - c > 1) {
+            int mid = (c + hi) >> 1;
+            if (L.coff[mid] <= t) c = mid; else hi = mid;
+        }
+        int cx, cy, cz;
+        core_box_coords(c, cx, cy, cz);
+        const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
+        const uint32_t slot = L.gsrc[lb] + (t - L.coff[c]);
+        const int64_t i = d.sorted_idx[slot];
+        const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
+        const uint8_t fl = d.flags[lp][i];
+        if (S.detect_static && (fl & kStatic)) {
+            skip_static<DIAG>(d, i, P, lp, fl, lin);
+            continue;
+        }
+        Acc a = {0, 0, 0, 0u, 0, 0, 0, 0, false};
+        const float4 own = d.payload[slot];
+        for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy) {
+                const int row = cx + kHalo * ((cy + 1 + oy) + kHalo * (cz + 1 + oz));
+                const float qy2 = own.y - (float)oy * Lf;
+                const float qz2 = own.z - (float)oz * Lf;
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int lbb = row + ox + 1;
+                    const float qx2 = own.x - (float)ox * Lf;
+                    const uint32_t b0 = L.gsrc[lbb], nn = L.sbeg[lbb + 1] - L.sbeg[lbb];
+                    for (uint32_t q = b0; q < b0 + nn; ++q)
+                        if (q != slot) pair_fp32<DIAG>(a, qx2, qy2, qz2, own.w, d.payload[q], e, g, kf, gf, L2m, L2p);
+                }
+            }
+        bool unc = a.unc;
+        if (!unc) {
+            const unsigned long long mb = (unsigned long long)a.nfix * fixbits(kFixMagic);
+            const double fx = (double)(long long)(a.ax - mb) * kFixUnit;
+            const double fy = (double)(long long)(a.ay - mb) * kFixUnit;
+            const double fz = (double)(long long)(a.az - mb) * kFixUnit;
+            const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
+            const double ebound = (double)a.eacc * 0x1.0p-26 + 1e-9;
+            if (fabs(fnorm - S.adherence) <= ebound) {
+                unc = true;
+            } else {
+                const uint32_t m = d.mrank[S.b_off + lin];
+                commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy, fz,
+                                   a.nz, a.nbr, a.contacts, m, lin);
+            }
+        }
+        if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
     }
 }
 
 template <bool DIAG>
 __global__ void __launch_bounds__(256) k_sweep(Dev d) {
-    __shared__ float4 sp[kStage];            // staged payload, block-relative coordinates
-    __shared__ uint16_t lst[kList * 256];    // per-thread candidate lists, thread-interleaved
-    __shared__ uint32_t sbeg[kNb + 1];       // exclusive prefix of the staged box counts
-    __shared__ uint32_t gsrc[kNb];           // global slot start of every staged box
-    __shared__ uint32_t coff[kCore + 1];
-    __shared__ uint32_t scnt[kNb];
-    __shared__ uint32_t sh[4];
+    __shared__ SweepLds<DIAG> L;
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
     const int64_t U = d.ctl->total_units;
     const int tid = threadIdx.x;
+    const uint32_t lane = tid & 63, w = tid >> 6;
     // blocks are dealt to the 8 XCDs round-robin: give each XCD a contiguous
     // Morton range of work units so that neighbouring blocks share its L2
     const int xcd = blockIdx.x & 7;
@@ -264,7 +377,7 @@ __global__ void __launch_bounds__(256) k_sweep(Dev d) {
         const SimDesc &S = d.sims[s];
         int qx, qy, qz;
         unpack_key(d.blist[S.b_off + (u - d.wblk_begin[s])], qx, qy, qz);
-        // table of the 6x6x6 staged boxes (x fastest)
+        // ---- table of the 6x6x6 staged boxes (x fastest)
         uint32_t cnt = 0;
         if (tid < kNb) {
             const int lx = tid % kHalo, ly = (tid / kHalo) % kHalo, lz = tid / (kHalo * kHalo);
@@ -275,152 +388,231 @@ __global__ void __launch_bounds__(256) k_sweep(Dev d) {
                 src = d.box_start[S.sb_off + m];
                 cnt = d.box_start[S.sb_off + m + 1] - src;
             }
-            gsrc[tid] = src;
-            scnt[tid] = cnt;
+            L.gsrc[tid] = src;
+            L.scnt[tid] = cnt;
         }
         uint32_t v[4] = {cnt, 0u, 0u, 0u};
         uint32_t total;
-        const uint32_t pre = block_excl_scan_4(v, sh, total);
-        if (tid < kNb) sbeg[tid] = pre;
-        if (tid == 0) sbeg[kNb] = total;
+        const uint32_t pre = block_excl_scan_4(v, L.sh, total);
+        if (tid < kNb) L.sbeg[tid] = pre;
+        if (tid == 0) L.sbeg[kNb] = total;
         __syncthreads();
         if (tid < 64) {  // prefix of the target counts over the 64 core boxes (one wave)
             const int lb = (tid % 4 + 1) + kHalo * ((tid / 4 % 4 + 1) + kHalo * (tid / 16 + 1));
-            const uint32_t cc = scnt[lb];
+            const uint32_t cc = L.scnt[lb];
             uint32_t x = cc;
             for (int off = 1; off < 64; off <<= 1) {
                 uint32_t y = __shfl_up(x, off);
                 if (tid >= off) x += y;
             }
-            coff[tid] = x - cc;
-            if (tid == 63) coff[64] = x;
+            L.coff[tid] = x - cc;
+            if (tid == 63) L.coff[64] = x;
+            L.bcnt[tid] = 0;
         }
         const float Lf = (float)S.L;
         const bool staged = total <= (uint32_t)kStage;
         if (staged) {
             // box-relative -> relative to the centre of the 6x6x6 region (|x| < 3L)
-            for (uint32_t e = tid; e < total; e += blockDim.x) {
-                int lo = 0, hi = kNb;  // largest lb with sbeg[lb] <= e
+            for (uint32_t k = tid; k < total; k += blockDim.x) {
+                int lo = 0, hi = kNb;  // largest lb with sbeg[lb] <= k
                 while (hi - lo > 1) {
                     int mid = (lo + hi) >> 1;
-                    if (sbeg[mid] <= e) lo = mid; else hi = mid;
+                    if (L.sbeg[mid] <= k) lo = mid; else hi = mid;
                 }
-                float4 c = d.payload[gsrc[lo] + (e - sbeg[lo])];
+                float4 c = d.payload[L.gsrc[lo] + (k - L.sbeg[lo])];
                 const int lx = lo % kHalo, ly = (lo / kHalo) % kHalo, lz = lo / (kHalo * kHalo);
                 c.x += (float)(lx - 3) * Lf;
                 c.y += (float)(ly - 3) * Lf;
                 c.z += (float)(lz - 3) * Lf;
-                sp[e] = c;
+                L.sp[k] = c;
             }
         }
         __syncthreads();
-        const uint32_t nt = coff[64];
+        const uint32_t nt = L.coff[kCore];
         const float e = S.e_delta, g = 2.0f * e;
         const float kf = (float)S.k, gf = (float)S.gamma;
         const float L2 = (float)(S.L * S.L);
         const float G = (float)ldexp(S.L * S.L, -18);
         const float L2m = L2 - G, L2p = L2 + G;
-        const float rmaxg = (float)S.rmax + g;
-        for (uint32_t t0 = 0; t0 < nt; t0 += blockDim.x) {
-            // all lanes run the loop body (wave-uniform inner loops); lanes
-            // without a target, and static targets, are predicated off
-            const uint32_t t = t0 + tid < nt ? t0 + tid : nt - 1;
-            bool act = t0 + tid < nt;
-            int c = 0, hi = kCore;  // core box of target t
+        // largest reach beyond the target radius: largest radius, guard band
+        // and a margin of 2^-10 L for the block-relative FP32 coordinates
+        const float reach_add = (float)S.rmax + g + (float)ldexp(S.L, -10);
+        if (!staged || nt > (uint32_t)kMaxT) {
+            sweep_unit_global<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            __syncthreads();  // the next unit reuses the LDS tables
+            continue;
+        }
+        // ---- setup: static skip, accumulators, task counts per row length
+        for (uint32_t t = tid; t < nt; t += blockDim.x) {
+            int c = 0, hi = kCore;
             while (hi - c > 1) {
                 int mid = (c + hi) >> 1;
-                if (coff[mid] <= t) c = mid; else hi = mid;
+                if (L.coff[mid] <= t) c = mid; else hi = mid;
             }
-            const int cx = c % 4, cy = c / 4 % 4, cz = c / 16;
+            int cx, cy, cz;
+            core_box_coords(c, cx, cy, cz);
             const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
-            const uint32_t k = t - coff[c];
-            const uint32_t slot = gsrc[lb] + k;
-            const uint32_t self = staged ? sbeg[lb] + k : slot;
-            const int64_t i = d.sorted_idx[slot];
-            const int bx = qx * kBlk + cx, by = qy * kBlk + cy, bz = qz * kBlk + cz;
-            const int64_t lin = linear_box(bx, by, bz, S.dims);
-            const uint8_t fl = d.flags[lp][i];
-            if (act && S.detect_static && (fl & kStatic)) {
-                skip_static<DIAG>(d, i, P, lp, fl, lin);
-                act = false;
+            const uint32_t k = t - L.coff[c];
+            bool stat = false;
+            if (S.detect_static) {
+                const int64_t i = d.sorted_idx[L.gsrc[lb] + k];
+                const uint8_t fl = d.flags[lp][i];
+                if (fl & kStatic) {
+                    skip_static<DIAG>(d, i, P, lp, fl,
+                                      linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims));
+                    stat = true;
+                }
             }
-            Acc a = {0, 0, 0, 0u, 0, 0, 0, 0, false};
-            if (staged) {
-                // phase 1: distance pre-test against the reach of the largest
-                // agent; survivors go to the thread's list; phase 2: contacts
-                const float4 own = sp[self];
-                const float R = own.w + rmaxg;
-                const float R2 = fminf(R * R, L2p);
-                uint32_t n = 0;
+            const uint32_t self = L.sbeg[lb] + k;
+            L.tself[t] = stat ? kNoTarget : (uint16_t)self;
+            L.tbox[t] = (uint8_t)c;
+            L.acc[0][t] = 0;
+            L.acc[1][t] = 0;
+            L.acc[2][t] = 0;
+            L.acnt[t] = 0;
+            L.aeacc[t] = 0;
+            if (DIAG) L.anbr[t] = 0;
+            if (!stat) {
+                const uint32_t rows = row_mask<DIAG>(L.sp[self], cx, cy, cz, Lf, reach_add);
+                L.trow[t] = rows;
                 for (int r = 0; r < 9; ++r) {
-                    const int row = cx + kHalo * ((cy + r % 3) + kHalo * (cz + r / 3));  // boxes cx..cx+2
-                    const uint32_t b0 = sbeg[row];
-                    const uint32_t len = act ? sbeg[row + 3] - b0 : 0u;
-                    const uint32_t kmax = wave_max_u32(len);
-                    for (uint32_t k0 = 0; k0 < kmax; k0 += kChunk) {
-                        if (__ballot(n + kChunk > (uint32_t)kList)) {
-                            drain_list(a, sp, lst, n, self, own, e, g, kf, gf, L2m, L2p);
-                            n = 0;
-                        }
-                        const uint32_t k1 = k0 + kChunk < kmax ? k0 + kChunk : kmax;
-                        for (uint32_t kk = k0; kk < k1; ++kk) {
-                            const bool in = kk < len;
-                            const uint32_t q = in ? b0 + kk : 0u;
-                            const float4 cc = sp[q];
-                            const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
-                            const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                            if (DIAG) {
-                                const bool other = in && q != self;
-                                a.nbr += (other && d2 < L2m) ? 1 : 0;
-                                a.unc |= other && d2 >= L2m && d2 < L2p;
-                            }
-                            lst[n * 256 + tid] = (uint16_t)q;
-                            n += (in && d2 < R2) ? 1u : 0u;
-                        }
-                    }
-                }
-                drain_list(a, sp, lst, n, self, own, e, g, kf, gf, L2m, L2p);
-            } else if (act) {
-                const float4 own = d.payload[slot];
-                for (int oz = -1; oz <= 1; ++oz) {
-                    for (int oy = -1; oy <= 1; ++oy) {
-                        const int row = cx + kHalo * ((cy + 1 + oy) + kHalo * (cz + 1 + oz));
-                        const float qy2 = own.y - (float)oy * Lf;
-                        const float qz2 = own.z - (float)oz * Lf;
-                        for (int ox = -1; ox <= 1; ++ox) {
-                            const int lbb = row + ox + 1;
-                            const float qx2 = own.x - (float)ox * Lf;
-                            const uint32_t b0 = gsrc[lbb], nn = sbeg[lbb + 1] - sbeg[lbb];
-                            for (uint32_t q = b0; q < b0 + nn; ++q)
-                                if (q != self)
-                                    pair_fp32<DIAG>(a, qx2, qy2, qz2, own.w, d.payload[q], e, g, kf, gf, L2m, L2p);
-                        }
-                    }
+                    const uint32_t rb = (rows >> (3 * r)) & 7u;
+                    if (!rb) continue;
+                    const int row = task_row(cx, cy, cz, r);
+                    const uint32_t len = L.sbeg[row + ((rb & 4u) ? 3 : 2)] - L.sbeg[row + ((rb & 2u) ? 0 : 1)];
+                    if (len) atomicAdd(&L.bcnt[len < kBuckets ? len : kBuckets - 1], 1u);
                 }
             }
-            if (!act) continue;
-            bool unc = a.unc;
+        }
+        __syncthreads();
+        if (tid < 64) {  // bucket offsets, longest rows first (one wave)
+            const uint32_t b = kBuckets - 1 - tid;
+            const uint32_t cc = L.bcnt[b];
+            uint32_t x = cc;
+            for (int off = 1; off < 64; off <<= 1) {
+                uint32_t y = __shfl_up(x, off);
+                if (tid >= off) x += y;
+            }
+            L.boff[b] = x - cc;
+            if (tid == 63) L.ntask = x;
+        }
+        __syncthreads();
+        for (uint32_t t = tid; t < nt; t += blockDim.x) {
+            if (L.tself[t] == kNoTarget) continue;
+            int cx, cy, cz;
+            core_box_coords(L.tbox[t], cx, cy, cz);
+            const uint32_t rows = L.trow[t];
+            for (int r = 0; r < 9; ++r) {
+                const uint32_t rb = (rows >> (3 * r)) & 7u;
+                if (!rb) continue;
+                const int row = task_row(cx, cy, cz, r);
+                const uint32_t len = L.sbeg[row + ((rb & 4u) ? 3 : 2)] - L.sbeg[row + ((rb & 2u) ? 0 : 1)];
+                if (len) {
+                    const uint32_t p = atomicAdd(&L.boff[len < kBuckets ? len : kBuckets - 1], 1u);
+                    L.task[p] = (uint16_t)((t << 4) | (uint32_t)r);
+                }
+            }
+        }
+        __syncthreads();
+        // ---- sweep: chunks of 64 tasks per wave, survivors through the queue
+        {
+            uint32_t *qw = L.queue[w];
+            uint32_t qn = 0;  // wave-uniform queue fill
+            const uint32_t ntask = L.ntask;
+            for (uint32_t c0 = w * 64; c0 < ntask; c0 += 256) {
+                const uint32_t j = c0 + lane;
+                const bool tv = j < ntask;
+                const uint32_t tk = L.task[tv ? j : c0];
+                const uint32_t t = tk >> 4, r = tk & 15u;
+                int cx, cy, cz;
+                core_box_coords(L.tbox[t], cx, cy, cz);
+                const int row = task_row(cx, cy, cz, (int)r);
+                const uint32_t rb = (L.trow[t] >> (3 * r)) & 7u;
+                const uint32_t b0 = L.sbeg[row + ((rb & 2u) ? 0 : 1)];
+                const uint32_t len = tv ? L.sbeg[row + ((rb & 4u) ? 3 : 2)] - b0 : 0u;
+                const uint32_t self = L.tself[t];
+                const float4 own = L.sp[self];
+                const float owg = own.w + g;
+                const uint32_t tq = (t << 16) + b0;
+                uint32_t nb = 0;
+                bool un = false;
+                // candidates b0, b0+1, ...: lanes past their row end read
+                // wrapped indices and are masked; the next one is prefetched
+                uint32_t q = b0 & (kStage - 1);
+                float4 cc = L.sp[q];
+                for (uint32_t kk = 0;; ++kk) {
+                    const bool in = kk < len;
+                    if (!__builtin_amdgcn_ballot_w64(in)) break;
+                    const uint32_t qn1 = (q + 1) & (kStage - 1);
+                    const float4 cn = L.sp[qn1];
+                    const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
+                    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                    const float sg = owg + cc.w;
+                    const bool sv = in && d2 < sg * sg;
+                    if (DIAG) {
+                        const bool other = in && q != self;
+                        nb += (other && d2 < L2m) ? 1u : 0u;
+                        un |= other && d2 >= L2m && d2 < L2p;
+                    }
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(sv);
+                    if (m) {
+                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        if (sv) qw[qn + below] = tq + kk;
+                        qn += (uint32_t)__popcll(m);
+                        if (qn >= 64) {
+                            __builtin_amdgcn_wave_barrier();
+                            drain_queue<DIAG>(L, qw, 64u, e, g, kf, gf, L2m, L2p);
+                            __builtin_amdgcn_wave_barrier();
+                            qn -= 64;
+                            if (lane < qn) qw[lane] = qw[64 + lane];
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+                    cc = cn;
+                    q = qn1;
+                }
+                if (DIAG && tv) {
+                    atomicAdd(&L.anbr[t], nb);
+                    if (un) atomicOr(&L.acnt[t], kUncBit);
+                }
+            }
+            if (qn) {
+                __builtin_amdgcn_wave_barrier();
+                drain_queue<DIAG>(L, qw, qn, e, g, kf, gf, L2m, L2p);
+            }
+        }
+        __syncthreads();
+        // ---- commit
+        for (uint32_t t = tid; t < nt; t += blockDim.x) {
+            if (L.tself[t] == kNoTarget) continue;
+            const int c = L.tbox[t];
+            int cx, cy, cz;
+            core_box_coords(c, cx, cy, cz);
+            const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
+            const int64_t i = d.sorted_idx[L.gsrc[lb] + (t - L.coff[c])];
+            const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
+            const uint32_t ac = L.acnt[t];
+            bool unc = (ac & kUncBit) != 0;
             if (!unc) {
-                const unsigned long long mb = (unsigned long long)a.nfix * fixbits(kFixMagic);
-                const double fx = (double)(long long)(a.ax - mb) * kFixUnit;
-                const double fy = (double)(long long)(a.ay - mb) * kFixUnit;
-                const double fz = (double)(long long)(a.az - mb) * kFixUnit;
+                const double fx = (double)(long long)L.acc[0][t] * kFixUnit;
+                const double fy = (double)(long long)L.acc[1][t] * kFixUnit;
+                const double fz = (double)(long long)L.acc[2][t] * kFixUnit;
                 const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
-                const double ebound = (double)a.eacc * 0x1.0p-26 + 1e-9;
+                const double ebound = (double)L.aeacc[t] * 0x1.0p-26 + 1e-9;
                 if (fabs(fnorm - S.adherence) <= ebound) {
                     unc = true;
                 } else {
+                    const int nzc = (int)(ac & ~kUncBit);
+                    const uint8_t fl = d.flags[lp][i];
                     const uint32_t m = d.mrank[S.b_off + lin];
                     commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
-                                       fz, a.nz, a.nbr, a.contacts, m, lin);
+                                       fz, nzc, DIAG ? (int)L.anbr[t] : 0, nzc, m, lin);
                 }
             }
-            if (unc) {
-                uint32_t q = atomicAdd(&d.ctl->n_fix, 1u);
-                d.fix_list[q] = (uint32_t)i;
-            }
+            if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
         }
-        __syncthreads();  // the next unit reuses the LDS tables
+        __syncthreads();  // the next unit reuses the LDS
     }
 }
 

@@ -95,3 +95,25 @@ def compare_single_step(abm, b, o, sim=0, L=15.0, check_static=True):
         out["static_mismatch"] = int(np.count_nonzero(g_st != o_st))
         assert out["static_mismatch"] == 0, out
     return out
+
+
+def compare_positions_single_step(abm, b, o, start_pos, sim=0, L=15.0):
+    """Production (non-diagnostic) step against the oracle stepped once from
+    the same state: the same agents move, and every new position is within
+    dt/m times the force tolerance of the oracle's."""
+    n = o.n
+    g_uid = b.query(abm.UID, sim)
+    order_g = np.argsort(g_uid, kind="stable")
+    order_o = np.argsort(o.uid[:n], kind="stable")
+    assert np.array_equal(g_uid[order_g], o.uid[:n][order_o]), "agent sets differ"
+    pg = b.query(abm.POS, sim)[order_g]
+    po = o.pos()[order_o]
+    p0 = start_pos[order_o]
+    old = o.is_new[:n][order_o] == 0
+    moved_g = np.any(pg[old] != p0[old], axis=1)
+    moved_o = np.any(po[old] != p0[old], axis=1)
+    assert np.array_equal(moved_g, moved_o), "move decisions differ"
+    tol = (o.params.dt / o.params.mass) * force_tolerance(o, L)[order_o][old] + 1e-12
+    err = np.linalg.norm(pg[old] - po[old], axis=1)
+    assert np.all(err <= tol + 1e-13 * np.abs(po[old]).max(axis=1)), float((err / tol).max())
+    return {"pos_max_abs_err": float(err.max()) if err.size else 0.0, "moved": int(moved_o.sum())}

@@ -41,6 +41,29 @@ def test_c0_every_iteration_matches_oracle_single_step(abm, detect_static, workl
         st = H.gpu_state(abm, b)
 
 
+@pytest.mark.parametrize("detect_static,workload", [(False, "c0"), (True, "relaxed_lattice"), (False, "dense")])
+def test_production_path_single_step_matches_oracle(abm, detect_static, workload):
+    """The launch configuration of the benchmark (no diagnostics: row culling
+    and reach tests active) against the oracle, one iteration at a time."""
+    if workload == "c0":
+        pos, diam = c0()
+    elif workload == "relaxed_lattice":
+        pos, diam = inputs.relaxed_lattice(16, seed=2)
+    else:  # twice the density of the uniform workload: more contacts per agent
+        pos, diam = inputs.plain(4096, 127.0, seed=9)
+    gp = H.gpu_params(abm, detect_static=detect_static)
+    b = abm.Population(gp, pos, diam, capacity=4096, box_capacity=1 << 16)
+    op = H.oracle_params(detect_static=detect_static)
+    st = H.gpu_state(abm, b)
+    for it in range(6):
+        o = H.oracle_from_state(st, op, iteration=it)
+        b.step(1)
+        o.step(1)
+        res = H.compare_positions_single_step(abm, b, o, st["pos"])
+        print(f"iter {it}: {res}", flush=True)
+        st = H.gpu_state(abm, b)
+
+
 def test_c0_trajectory_error_and_determinism(abm):
     pos, diam = c0()
     gp = H.gpu_params(abm)
