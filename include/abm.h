@@ -100,7 +100,10 @@ typedef struct abm_batch abm_pop; /* a population is a batch of one simulation *
 /* ------------------------------------------------------------------------- */
 
 /* Workspace bytes for n_sims simulations with these agent and grid-box
- * capacities (arrays of n_sims).  Returns 0 for invalid sizes. */
+ * capacities (arrays of n_sims).  The grid of a simulation needs 64 box
+ * slots per aligned 4x4x4 block of boxes that it touches, i.e.
+ * 64 * ceil(dx/4) * ceil(dy/4) * ceil(dz/4) for dx x dy x dz boxes; a larger
+ * grid fails the step with ABM_ERR_CAPACITY.  Returns 0 for invalid sizes. */
 size_t abm_batch_workspace_bytes(int n_sims, const int64_t *capacity, const int64_t *box_capacity);
 
 /* Create a batch.  per_sim: n_sims parameter sets.  n0: initial agents per
@@ -132,6 +135,12 @@ int abm_batch_step(abm_batch *b, int n_iter);
 
 /* Current agent counts (n_sims entries, host). */
 int abm_batch_num_agents(abm_batch *b, int64_t *n_out);
+
+/* Number of agents (whole batch) whose force, contact and move decisions the
+ * last iteration took on the FP64 path because the FP32 sweep could not
+ * certify them (guard bands around the decision thresholds, Eq 4.1-4.2 and
+ * the adherence rule of Sec 5.5).  A statistic; *n_out is host memory. */
+int abm_batch_fp64_agents(abm_batch *b, int64_t *n_out);
 
 /* Copy one field of simulation `sim` into dst (capacity `cap` elements of the
  * field's type); *n_out receives the number of agents. */

@@ -63,6 +63,7 @@ def lib():
         L.abm_batch_restore.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int]
         L.abm_batch_step.argtypes = [_vp, ctypes.c_int]
         L.abm_batch_num_agents.argtypes = [_vp, _i64p]
+        L.abm_batch_fp64_agents.argtypes = [_vp, _i64p]
         L.abm_batch_query.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64, _i64p]
         L.abm_batch_grid.argtypes = [_vp, ctypes.c_int, _vp, _vp, _vp]
         L.abm_batch_stats.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
@@ -167,6 +168,12 @@ class Batch:
         out = np.zeros(self.n_sims, dtype=np.int64)
         check(lib().abm_batch_num_agents(self.h, out.ctypes.data_as(_i64p)))
         return out
+
+    def fp64_agents(self):
+        """Agents decided on the FP64 path in the last iteration (whole batch)."""
+        out = np.zeros(1, dtype=np.int64)
+        check(lib().abm_batch_fp64_agents(self.h, out.ctypes.data_as(_i64p)))
+        return int(out[0])
 
     def query(self, field, sim=0):
         dt, width = _FIELD_TYPES[field]

@@ -55,7 +55,7 @@ struct Layout {
     size_t sims, ctl, tile_begin, btile_begin, utile_begin, a_begin, wblk_begin, bnd, blist;
     size_t pos[2], diam[2], vol[2], growth[2], uid[2], flags[2], nz[2];
     size_t stage8, key, rank, payload, sorted_idx, nbr, contacts, force, disp, boxid;
-    size_t count, box_start, mrank, dirty, arrive, tile_sum, tile_off, fix_list, divflag, divrank;
+    size_t count, box_start, brank, dirty, arrive, tile_sum, tile_off, fix_list, divflag, divrank;
     size_t stat_part, hist_cnt, stat_out;
     size_t total;
 };
@@ -106,7 +106,7 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
     L.boxid = c.take<int64_t>(A);
     L.count = c.take<uint32_t>(B);
     L.box_start = c.take<uint32_t>(SB);
-    L.mrank = c.take<uint32_t>(B);
+    L.brank = c.take<uint32_t>(B);
     L.blist = c.take<uint32_t>(B);
     L.dirty = c.take<uint8_t>(B);
     L.arrive = c.take<uint8_t>(B);
@@ -323,7 +323,7 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     d.boxid = (int64_t *)(w + L.boxid);
     d.count = (uint32_t *)(w + L.count);
     d.box_start = (uint32_t *)(w + L.box_start);
-    d.mrank = (uint32_t *)(w + L.mrank);
+    d.brank = (uint32_t *)(w + L.brank);
     d.blist = (uint32_t *)(w + L.blist);
     d.dirty = (uint8_t *)(w + L.dirty);
     d.arrive = (uint8_t *)(w + L.arrive);
@@ -612,6 +612,16 @@ extern "C" int abm_batch_num_agents(abm_batch *b, int64_t *n_out) {
     int rc = read_sims(b, sims);
     if (rc) return rc;
     for (int s = 0; s < b->n_sims; ++s) n_out[s] = sims[s].n;
+    return ABM_OK;
+}
+
+extern "C" int abm_batch_fp64_agents(abm_batch *b, int64_t *n_out) {
+    g_err.clear();
+    if (!b || !n_out) return fail(ABM_ERR_ARG, "null argument");
+    Ctl c;
+    int rc = read_ctl(b, c);
+    if (rc) return rc;
+    *n_out = c.n_fp64_last;
     return ABM_OK;
 }
 

@@ -68,18 +68,61 @@ __device__ inline uint32_t morton_rank(int bx, int by, int bz, const int32_t dim
     return (uint32_t)rank;
 }
 
-// Morton rank of the box holding (x, y, z) in the current grid of S.
+// Box slot of box (bx,by,bz): boxes are ordered by the Morton rank of their
+// aligned 4x4x4 block, then by the Morton code of the box within the block
+// (two bits per axis, x lowest).  For aligned power-of-two blocks this is the
+// Morton order of the boxes; edge blocks that stick out of the grid keep
+// their unused slots empty.  The block ranks form a small table (one entry
+// per block), so no per-box table is read.
+static_assert(kBlk == 4, "box slots interleave two bits per axis within a block");
+__device__ inline uint32_t local_morton(int bx, int by, int bz) {
+    return (uint32_t)((bx & 1) | ((by & 1) << 1) | ((bz & 1) << 2) | ((bx & 2) << 2) | ((by & 2) << 3) |
+                      ((bz & 2) << 4));
+}
+__device__ inline uint32_t box_rank(const Dev &d, const SimDesc &S, int bx, int by, int bz) {
+    const int64_t blk =
+        (int64_t)(bx >> 2) + (int64_t)S.bdims[0] * ((int64_t)(by >> 2) + (int64_t)S.bdims[1] * (int64_t)(bz >> 2));
+    return d.brank[S.b_off + blk] * 64u + local_morton(bx, by, bz);
+}
+
+// Box slot of the box holding (x, y, z) in the current grid of S.
 __device__ inline uint32_t box_rank_of(const Dev &d, const SimDesc &S, double x, double y, double z) {
     int bx = box_coord(x, S.lo[0], S.L, S.dims[0]);
     int by = box_coord(y, S.lo[1], S.L, S.dims[1]);
     int bz = box_coord(z, S.lo[2], S.L, S.dims[2]);
-    return d.mrank[S.b_off + linear_box(bx, by, bz, S.dims)];
+    return box_rank(d, S, bx, by, bz);
 }
 
 __device__ inline uint32_t key_rank(const Dev &d, const SimDesc &S, uint32_t key) {
     int bx, by, bz;
     unpack_key(key, bx, by, bz);
-    return d.mrank[S.b_off + linear_box(bx, by, bz, S.dims)];
+    return box_rank(d, S, bx, by, bz);
+}
+
+// Atomic counting in which runs of equal keys in consecutive lanes of a wave
+// share one atomic add of the run length at base[key]; returns this lane's
+// position among the adds to its counter.  Same-address atomics of one
+// instruction serialize, and agents in Morton order arrive in such runs.
+// Every lane of the wave must call this; lanes with valid == false take no
+// position and must be the last lanes of the wave.
+__device__ inline uint32_t run_atomic_add(uint32_t *base, uint32_t key, bool valid) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t kp = __shfl_up(key, 1);
+    const bool head = valid && (lane == 0 || kp != key);
+    const uint64_t hm = __ballot(head);
+    const uint64_t vm = __ballot(valid);
+    const uint64_t upto = (2ull << lane) - 1;  // lanes 0..lane (all lanes for lane 63)
+    const uint64_t below = hm & upto;
+    const int start = below ? 63 - __clzll(below) : 0;
+    uint32_t r = 0;
+    if (head) {
+        const uint64_t after = hm & ~upto;
+        const int next = after ? __ffsll((long long)after) - 1 : 64;
+        const int last = 63 - __clzll(vm);
+        const int end = next < last + 1 ? next : last + 1;
+        r = atomicAdd(&base[key], (uint32_t)(end - lane));
+    }
+    return __shfl(r, start) + (uint32_t)(lane - start);
 }
 
 // Squared distance below L^2 with the neighbour predicate's exact expression.

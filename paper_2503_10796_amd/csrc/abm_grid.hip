@@ -5,7 +5,7 @@
 //   begin    per-simulation counters and agent-tile prefix
 //   bounds   open boundary: min/max of positions and largest diameter (Sec 4.4.11)
 //   grid     box length, dims; Morton tables are rebuilt when the dims change
-//   mrank    linear box id -> Morton rank; Morton list of aligned 4^3 blocks
+//   brank    linear block id -> Morton rank of the block; Morton list of blocks
 //   bin      per-box counts with arrival rank (slot order = Morton order of boxes)
 //   scan_*   per-box exclusive scan -> slot start of every box
 //   scatter  box-ordered FP32 payload (box-relative centre, radius) + agent index
@@ -41,6 +41,7 @@ __global__ void k_begin(Dev d) {
         }
         d.tile_begin[d.n_sims] = t;
         d.ctl->total_tiles = t;
+        d.ctl->n_fp64_last = d.ctl->n_fix;
         d.ctl->n_fix = 0;
     }
 }
@@ -133,7 +134,7 @@ __global__ void k_grid(Dev d) {
         }
         double L = S.box_len > 0.0 ? S.box_len : dec_double(e[6]);
         S.L = L;
-        int64_t nb = 1, nbl = 1;
+        int64_t nbl = 1;
         bool bad = !(L > 0.0);
         for (int a = 0; a < 3; ++a) {
             S.lo[a] = dec_double(e[a]);
@@ -145,9 +146,10 @@ __global__ void k_grid(Dev d) {
                 q = 1.0;
             }
             S.dims[a] = (int32_t)q;
-            nb *= (int64_t)q;
-            nbl *= ceil_div((int64_t)q, kBlk);
+            S.bdims[a] = (int32_t)ceil_div((int64_t)q, kBlk);
+            nbl *= (int64_t)S.bdims[a];
         }
+        int64_t nb = nbl * kBlk * kBlk * kBlk;  // box slots
         if (bad || nb > S.box_cap) {
             S.err |= kErrGrid;
             atomicOr(&d.ctl->err, kErrGrid);
@@ -179,30 +181,26 @@ __global__ void k_grid(Dev d) {
     }
 }
 
-// Morton rank of every box and the Morton-ordered list of aligned 4^3 blocks;
+// Morton rank of every aligned 4^3 block and the Morton-ordered block list;
 // only for simulations whose grid dims changed.
-__global__ void __launch_bounds__(256) k_mrank(Dev d) {
+__global__ void __launch_bounds__(256) k_brank(Dev d) {
     if (ABM_ABORTED(d)) return;
     const int64_t total = d.ctl->total_btiles;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         int s = find_sim(d.btile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
         if (!S.remap) continue;
-        const int32_t bdims[3] = {(int32_t)ceil_div(S.dims[0], kBlk), (int32_t)ceil_div(S.dims[1], kBlk),
-                                  (int32_t)ceil_div(S.dims[2], kBlk)};
         int64_t k0 = (t - d.btile_begin[s]) * kBoxTile;
         for (int q = threadIdx.x; q < kBoxTile; q += blockDim.x) {
             int64_t k = k0 + q;
-            if (k >= S.nboxes) break;
-            int bx = (int)(k % S.dims[0]);
-            int64_t r = k / S.dims[0];
-            int by = (int)(r % S.dims[1]);
-            int bz = (int)(r / S.dims[1]);
-            d.mrank[S.b_off + k] = morton_rank(bx, by, bz, S.dims);
-            if (bx % kBlk == 0 && by % kBlk == 0 && bz % kBlk == 0) {
-                int qx = bx / kBlk, qy = by / kBlk, qz = bz / kBlk;
-                d.blist[S.b_off + morton_rank(qx, qy, qz, bdims)] = pack_key(qx, qy, qz);
-            }
+            if (k >= S.nblocks) break;
+            int qx = (int)(k % S.bdims[0]);
+            int64_t r = k / S.bdims[0];
+            int qy = (int)(r % S.bdims[1]);
+            int qz = (int)(r / S.bdims[1]);
+            const uint32_t m = morton_rank(qx, qy, qz, S.bdims);
+            d.brank[S.b_off + k] = m;
+            d.blist[S.b_off + m] = pack_key(qx, qy, qz);
         }
     }
 }
@@ -224,16 +222,22 @@ __global__ void __launch_bounds__(256) k_bin(Dev d) {
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         int s = find_sim(d.tile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n_start) continue;
-        int64_t i = S.a_off + loc;
-        const double L = S.L;
-        int bx = box_coord(d.pos[P][i], S.lo[0], L, S.dims[0]);
-        int by = box_coord(d.pos[P][A + i], S.lo[1], L, S.dims[1]);
-        int bz = box_coord(d.pos[P][2 * A + i], S.lo[2], L, S.dims[2]);
-        uint32_t m = d.mrank[S.b_off + linear_box(bx, by, bz, S.dims)];
+        const int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
+        const bool valid = loc < S.n_start;  // the invalid lanes are the last of the tile
+        const int64_t i = S.a_off + (valid ? loc : 0);
+        uint32_t m = 0;
+        int bx = 0, by = 0, bz = 0;
+        if (valid) {
+            const double L = S.L;
+            bx = box_coord(d.pos[P][i], S.lo[0], L, S.dims[0]);
+            by = box_coord(d.pos[P][A + i], S.lo[1], L, S.dims[1]);
+            bz = box_coord(d.pos[P][2 * A + i], S.lo[2], L, S.dims[2]);
+            m = box_rank(d, S, bx, by, bz);
+        }
+        const uint32_t r = run_atomic_add(d.count + S.b_off, m, valid);
+        if (!valid) continue;
         d.key[i] = pack_key(bx, by, bz);
-        d.rank[i] = atomicAdd(&d.count[S.b_off + m], 1u);
+        d.rank[i] = r;
         if (S.detect_static && (d.flags[lp][i] & kChgMask)) d.arrive[S.b_off + m] = 1;
     }
 }
@@ -330,7 +334,7 @@ __global__ void __launch_bounds__(256) k_scatter(Dev d) {
         int64_t i = S.a_off + loc;
         int bx, by, bz;
         unpack_key(d.key[i], bx, by, bz);
-        uint32_t m = d.mrank[S.b_off + linear_box(bx, by, bz, S.dims)];
+        uint32_t m = box_rank(d, S, bx, by, bz);
         uint32_t slot = d.box_start[S.sb_off + m] + d.rank[i];
         float4 p;
         p.x = rel_coord(d.pos[P][i], S.lo[0], S.L, bx);
@@ -372,7 +376,7 @@ __global__ void __launch_bounds__(256) k_static_fix(Dev d) {
                     for (int ox = -1; ox <= 1 && st; ++ox) {
                         int cx = bx + ox, cy = by + oy, cz = bz + oz;
                         if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2]) continue;
-                        uint32_t m = d.mrank[S.b_off + linear_box(cx, cy, cz, S.dims)];
+                        uint32_t m = box_rank(d, S, cx, cy, cz);
                         if (!d.arrive[S.b_off + m]) continue;
                         uint32_t s0 = d.box_start[S.sb_off + m], s1 = d.box_start[S.sb_off + m + 1];
                         for (uint32_t slot = s0; slot < s1 && st; ++slot) {
@@ -445,12 +449,15 @@ __global__ void __launch_bounds__(256) k_rs_count(Dev d) {
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         int s = find_sim(d.tile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n || S.nboxes == 0) continue;
-        int64_t i = S.a_off + loc;
-        uint32_t m = box_rank_of(d, S, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i]);
+        if (S.nboxes == 0) continue;  // uniform over the block
+        const int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
+        const bool valid = loc < S.n;  // the invalid lanes are the last of the tile
+        const int64_t i = S.a_off + (valid ? loc : 0);
+        const uint32_t m = valid ? box_rank_of(d, S, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i]) : 0u;
+        const uint32_t r = run_atomic_add(d.count + S.b_off, m, valid);
+        if (!valid) continue;
         d.key[i] = m;
-        d.rank[i] = atomicAdd(&d.count[S.b_off + m], 1u);
+        d.rank[i] = r;
     }
 }
 
@@ -614,7 +621,7 @@ void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_b
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_bounds, dim3(grid_agents), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_mrank, dim3(grid_boxes), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_brank, dim3(grid_boxes), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_grid_done, dim3(1), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_bin, dim3(grid_agents), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);

@@ -32,7 +32,7 @@ constexpr int kErrCapacity = 1, kErrNonfinite = 2, kErrGrid = 4;
 struct alignas(256) SimDesc {
     // set at creation
     int64_t a_off, cap;      // agent range
-    int64_t b_off, box_cap;  // count/dirty/mrank range
+    int64_t b_off, box_cap;  // box-slot range (count, dirty, arrive) and block tables (brank, blist)
     int64_t sb_off;          // box_start range: box_cap + 1 entries
     double dt, k, gamma, adherence, mass, max_disp, box_len, div_vol, shift_frac;
     int32_t detect_static, resort_every;
@@ -44,8 +44,9 @@ struct alignas(256) SimDesc {
     double L_prev;  // box length of the previous grid (static rule radius)
     int32_t dims[3];
     int32_t err;
-    int64_t nboxes;
-    int32_t dims_prev[3];  // dims of the Morton-rank tables
+    int64_t nboxes;        // box slots in use: 64 per aligned 4x4x4 block (edge blocks padded)
+    int32_t bdims[3];      // blocks per axis, ceil(dims / 4)
+    int32_t dims_prev[3];  // dims of the block-rank tables
     int32_t remap;         // the tables must be rebuilt for new dims
     int64_t nblocks;       // aligned 4x4x4 box blocks (sweep work units)
     double rmax;           // largest agent radius at the start of the iteration
@@ -54,7 +55,7 @@ struct alignas(256) SimDesc {
 };
 
 constexpr int kBndSlots = 64;  // spread of the bounds atomics (slots per simulation)
-constexpr int kBlk = 4;        // sweep work unit: kBlk^3 boxes, staged with a one-box halo
+constexpr int kBlk = 4;        // aligned blocks of kBlk^3 boxes: box order and sweep work unit
 
 struct alignas(256) Ctl {
     int64_t iter;
@@ -62,7 +63,7 @@ struct alignas(256) Ctl {
     int32_t err;
     int32_t abort;
     uint32_t n_fix;
-    uint32_t n_unc_pairs;  // statistics: agents sent to the FP64 path
+    uint32_t n_fp64_last;  // agents the FP64 path decided in the last iteration
     int64_t total_tiles, total_btiles, total_utiles, total_units;
     int32_t resort_now;
     int32_t any_growth;
@@ -92,8 +93,8 @@ struct Dev {
     int32_t *nbr, *contacts;
     double *force, *disp;  // 3*A interleaved
     int64_t *boxid;
-    uint32_t *count, *box_start;  // indexed by Morton rank of the box
-    uint32_t *mrank;              // linear box id -> Morton rank
+    uint32_t *count, *box_start;  // indexed by the Morton rank of the box (box slot)
+    uint32_t *brank;              // linear block id -> Morton rank of the block
     uint8_t *dirty;   // boxes holding the start position of a changed agent
     uint8_t *arrive;  // boxes of the new grid holding a changed agent
     uint32_t *tile_sum, *tile_off;

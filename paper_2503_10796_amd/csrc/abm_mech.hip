@@ -135,14 +135,16 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
 constexpr int kMaxT = 320;      // targets per unit on the LDS path
 constexpr int kBuckets = 64;    // task lengths 1..63, longer rows share the last bucket
 constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 16 | staged index)
-constexpr uint32_t kUncBit = 0x80000000u;
+constexpr uint32_t kUncBit = 0x80000000u;  // acnt: the target needs the FP64 path
+constexpr uint32_t kNzUncOne = 0x10000u;   // acnt bits 16..30: contacts whose force may be zero
 constexpr uint16_t kNoTarget = 0xffff;
 
 template <bool DIAG>
 struct SweepLds {
     float4 sp[kStage];                      // staged payload, block-relative coordinates
     unsigned long long acc[3][kMaxT];       // force sums, 2^-40 units (two's complement)
-    uint32_t acnt[kMaxT];                   // contacts, plus kUncBit
+    uint32_t acnt[kMaxT];                   // contacts with a certain non-zero force (bits 0..15),
+                                            // contacts whose force may be zero (16..30), kUncBit
     uint32_t aeacc[kMaxT];                  // FP32 error bound of the sum, 2^-26 units
     uint32_t anbr[DIAG ? kMaxT : 1];        // neighbours within the box length
     uint32_t sbeg[kNb + 1];                 // exclusive prefix of the staged box counts
@@ -164,6 +166,7 @@ struct Acc {
     unsigned long long ax, ay, az;  // force components in 2^-40 units, plus nfix * magic bits (mod 2^64)
     uint32_t eacc;                  // error bound in 2^-26 units (rounded up per pair)
     int contacts, nz, nbr, nfix;
+    int nz_unc;                     // contacts whose force may be zero
     bool unc;                       // an integer outcome is not decidable in FP32
 };
 
@@ -175,6 +178,7 @@ struct Acc {
 // error bound of zero.  ep: error bound of F_N.
 struct PairOut {
     bool contact, unc;
+    bool nz_unc;  // a contact whose force cannot be told from zero in FP32
     float f, ep;
 };
 __device__ inline PairOut pair_math(float ddx, float ddy, float ddz, float d2, float ri, float rj, float e, float g,
@@ -198,9 +202,12 @@ __device__ inline PairOut pair_math(float ddx, float ddy, float ddz, float d2, f
     // bound on |fn error|: conditioning of Eq 4.1 times the overlap error,
     // plus FP32 rounding relative to the magnitudes of both terms
     const float ep = (kf + 0.5f * gs * __builtin_amdgcn_rcpf(delta)) * e + (kd + gs) * 0x1.0p-19f;
-    const bool bad = contact && (ep >= 0x1.0p-6f || fabsf(fn) <= ep);
-    o.unc = unc || bad;
-    o.contact = contact && !bad;
+    // a force within its bound of zero is a tiny, bounded term of the sum;
+    // only the non-zero-force count is then uncertain (see commit)
+    const bool big = contact && ep >= 0x1.0p-6f;
+    o.nz_unc = contact && !big && fabsf(fn) <= ep;
+    o.unc = unc || big;
+    o.contact = contact && !big;
     o.f = fn * __builtin_amdgcn_rcpf(dist);
     o.ep = ep;
     return o;
@@ -218,10 +225,10 @@ __device__ inline void pair_fp32(Acc &a, float qx, float qy, float qz, float ri,
         else if (d2 < L2p) a.unc = true;
     }
     const PairOut o = pair_math(ddx, ddy, ddz, d2, ri, c.w, e, g, kf, gf, L2m, L2p, true);
-    a.unc |= o.unc;
+    a.unc |= o.unc || (DIAG && o.nz_unc);
     if (o.contact) {
         ++a.contacts;
-        ++a.nz;
+        if (o.nz_unc) ++a.nz_unc; else ++a.nz;
         const double f = (double)o.f;
         a.ax += fixbits(fma(f, (double)ddx, kFixMagic));
         a.ay += fixbits(fma(f, (double)ddy, kFixMagic));
@@ -229,6 +236,16 @@ __device__ inline void pair_fp32(Acc &a, float qx, float qy, float qz, float ri,
         ++a.nfix;
         a.eacc += (uint32_t)ceilf(o.ep * 0x1.0p26f);
     }
+}
+
+// The non-zero-force count of a target: nz_min contacts with a certain
+// non-zero force and nz_unc whose FP32 force cannot be told from zero.  The
+// count feeds only the static rule (at most one non-zero force, Sec 5.5);
+// where that test cannot flip, the uncertain contacts count as non-zero (an
+// FP64 force of exactly zero would need the two terms of Eq 4.1 to round to
+// the same double).  Otherwise the target takes the FP64 path.
+__device__ inline bool nz_decided(const SimDesc &S, int nz_min, int nz_unc) {
+    return !S.detect_static || nz_unc == 0 || nz_min >= 2 || nz_min + nz_unc <= 1;
 }
 
 // Drains `cnt` (<= 64) queued pairs of this wave (lane l takes entry l).
@@ -252,10 +269,10 @@ __device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32
         atomicAdd(&L.acc[0][t], fixbits(fma(f, (double)ddx, kFixMagic)) - mb);
         atomicAdd(&L.acc[1][t], fixbits(fma(f, (double)ddy, kFixMagic)) - mb);
         atomicAdd(&L.acc[2][t], fixbits(fma(f, (double)ddz, kFixMagic)) - mb);
-        atomicAdd(&L.acnt[t], 1u);
+        atomicAdd(&L.acnt[t], o.nz_unc ? kNzUncOne : 1u);
         atomicAdd(&L.aeacc[t], (uint32_t)ceilf(o.ep * 0x1.0p26f));
     }
-    if (o.unc) atomicOr(&L.acnt[t], kUncBit);
+    if (o.unc || (DIAG && o.nz_unc)) atomicOr(&L.acnt[t], kUncBit);
 }
 
 __device__ inline void core_box_coords(int c, int &cx, int &cy, int &cz) {
@@ -322,7 +339,7 @@ __device__ void sweep_unit_global(const Dev &d, const SimDesc &S, SweepLds<DIAG>
             skip_static<DIAG>(d, i, P, lp, fl, lin);
             continue;
         }
-        Acc a = {0, 0, 0, 0u, 0, 0, 0, 0, false};
+        Acc a = {0, 0, 0, 0u, 0, 0, 0, 0, 0, false};
         const float4 own = d.payload[slot];
         for (int oz = -1; oz <= 1; ++oz)
             for (int oy = -1; oy <= 1; ++oy) {
@@ -337,7 +354,7 @@ __device__ void sweep_unit_global(const Dev &d, const SimDesc &S, SweepLds<DIAG>
                         if (q != slot) pair_fp32<DIAG>(a, qx2, qy2, qz2, own.w, d.payload[q], e, g, kf, gf, L2m, L2p);
                 }
             }
-        bool unc = a.unc;
+        bool unc = a.unc || !nz_decided(S, a.nz, a.nz_unc);
         if (!unc) {
             const unsigned long long mb = (unsigned long long)a.nfix * fixbits(kFixMagic);
             const double fx = (double)(long long)(a.ax - mb) * kFixUnit;
@@ -348,9 +365,9 @@ __device__ void sweep_unit_global(const Dev &d, const SimDesc &S, SweepLds<DIAG>
             if (fabs(fnorm - S.adherence) <= ebound) {
                 unc = true;
             } else {
-                const uint32_t m = d.mrank[S.b_off + lin];
+                const uint32_t m = box_rank(d, S, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz);
                 commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy, fz,
-                                   a.nz, a.nbr, a.contacts, m, lin);
+                                   a.nz + a.nz_unc, a.nbr, a.contacts, m, lin);
             }
         }
         if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
@@ -384,7 +401,7 @@ __global__ void __launch_bounds__(256) k_sweep(Dev d) {
             const int gx = qx * kBlk + lx - 1, gy = qy * kBlk + ly - 1, gz = qz * kBlk + lz - 1;
             uint32_t src = 0;
             if (gx >= 0 && gy >= 0 && gz >= 0 && gx < S.dims[0] && gy < S.dims[1] && gz < S.dims[2]) {
-                const uint32_t m = d.mrank[S.b_off + linear_box(gx, gy, gz, S.dims)];
+                const uint32_t m = box_rank(d, S, gx, gy, gz);
                 src = d.box_start[S.sb_off + m];
                 cnt = d.box_start[S.sb_off + m + 1] - src;
             }
@@ -593,7 +610,8 @@ __global__ void __launch_bounds__(256) k_sweep(Dev d) {
             const int64_t i = d.sorted_idx[L.gsrc[lb] + (t - L.coff[c])];
             const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
             const uint32_t ac = L.acnt[t];
-            bool unc = (ac & kUncBit) != 0;
+            const int nz_min = (int)(ac & 0xffffu), nz_unc = (int)((ac >> 16) & 0x7fffu);
+            bool unc = (ac & kUncBit) != 0 || !nz_decided(S, nz_min, nz_unc);
             if (!unc) {
                 const double fx = (double)(long long)L.acc[0][t] * kFixUnit;
                 const double fy = (double)(long long)L.acc[1][t] * kFixUnit;
@@ -603,9 +621,9 @@ __global__ void __launch_bounds__(256) k_sweep(Dev d) {
                 if (fabs(fnorm - S.adherence) <= ebound) {
                     unc = true;
                 } else {
-                    const int nzc = (int)(ac & ~kUncBit);
+                    const int nzc = nz_min + nz_unc;
                     const uint8_t fl = d.flags[lp][i];
-                    const uint32_t m = d.mrank[S.b_off + lin];
+                    const uint32_t m = box_rank(d, S, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz);
                     commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
                                        fz, nzc, DIAG ? (int)L.anbr[t] : 0, nzc, m, lin);
                 }
@@ -673,66 +691,122 @@ struct Fix128 {
 // FP64 re-evaluation with the exact expressions of the method for agents the
 // FP32 sweep could not decide.  Neighbours are read from the start-of-iteration
 // FP64 state through the grid (copy semantics).
+// 128-bit sum over the lanes of a wave (two's complement, exact).
+__device__ inline void wave_sum128(uint64_t &lo, uint64_t &hi) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t olo = __shfl_xor(lo, off), ohi = __shfl_xor(hi, off);
+        const uint64_t nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1ull : 0ull);
+        lo = nlo;
+    }
+}
+__device__ inline int wave_sum_i32(int v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__device__ inline double wave_sum_f64(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// One wave per agent on the FP64 path: lane b < 27 reads the slot range of
+// neighbour box b, the candidates of all 27 boxes are dealt to the lanes,
+// and the exact per-lane sums are added over the wave.
 template <bool DIAG>
 __global__ void __launch_bounds__(256) k_fixup(Dev d) {
 #pragma clang fp contract(off)
+    __shared__ uint32_t bst[4][27], bpre[4][28];
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
     const uint32_t nf = d.ctl->n_fix;
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nf; q += gridDim.x * blockDim.x) {
+    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (uint32_t q = blockIdx.x * 4 + w; q < nf; q += gridDim.x * 4) {
         const int64_t i = d.fix_list[q];
         const int s = find_sim(d.a_begin, d.n_sims, i);
         const SimDesc &S = d.sims[s];
-        const uint8_t fl = d.flags[lp][i];
         const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
         const double ri = 0.5 * d.diam[lp][i];
         const double L2 = S.L * S.L;
         int bx, by, bz;
         unpack_key(d.key[i], bx, by, bz);
+        uint32_t cnt = 0, st = 0;
+        if (lane < 27) {
+            const int cx = bx + (int)(lane % 3) - 1, cy = by + (int)(lane / 3 % 3) - 1, cz = bz + (int)(lane / 9) - 1;
+            if (cx >= 0 && cy >= 0 && cz >= 0 && cx < S.dims[0] && cy < S.dims[1] && cz < S.dims[2]) {
+                const uint32_t m = box_rank(d, S, cx, cy, cz);
+                st = d.box_start[S.sb_off + m];
+                cnt = d.box_start[S.sb_off + m + 1] - st;
+            }
+        }
+        uint32_t pre = cnt;  // inclusive scan over the lanes
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = __shfl_up(pre, off);
+            if (lane >= (uint32_t)off) pre += o;
+        }
+        const uint32_t total = __shfl(pre, 63);
+        if (lane < 27) {
+            bst[w][lane] = st;
+            bpre[w][lane] = pre - cnt;
+        }
+        if (lane == 27) bpre[w][27] = total;
+        __builtin_amdgcn_wave_barrier();
         double fx = 0.0, fy = 0.0, fz = 0.0;  // plain sums, used only when a term is huge
         Fix128 sx, sy, sz;
         int nbr = 0, contacts = 0, nzc = 0;
-        for (int oz = -1; oz <= 1; ++oz)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int ox = -1; ox <= 1; ++ox) {
-                    int cx = bx + ox, cy = by + oy, cz = bz + oz;
-                    if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2]) continue;
-                    uint32_t m = d.mrank[S.b_off + linear_box(cx, cy, cz, S.dims)];
-                    uint32_t s0 = d.box_start[S.sb_off + m], s1 = d.box_start[S.sb_off + m + 1];
-                    for (uint32_t slot = s0; slot < s1; ++slot) {
-                        int64_t j = d.sorted_idx[slot];
-                        if (j == i) continue;
-                        double ddx = x - d.pos[P][j], ddy = y - d.pos[P][A + j], ddz = z - d.pos[P][2 * A + j];
-                        double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
-                        if (!(d2 < L2)) continue;
-                        ++nbr;
-                        double rj = 0.5 * d.diam[lp][j];
-                        double dist = sqrt(d2);
-                        double delta = ri + rj - dist;
-                        if (!(delta > 0.0)) continue;
-                        ++contacts;
-                        double rbar = ri * rj / (ri + rj);
-                        double fn = S.k * delta - S.gamma * sqrt(rbar * delta);
-                        if (fn != 0.0) ++nzc;
-                        if (dist > 0.0) {
-                            const double tx = fn * ddx / dist, ty = fn * ddy / dist, tz = fn * ddz / dist;
-                            fx += tx;
-                            fy += ty;
-                            fz += tz;
-                            sx.add(tx);
-                            sy.add(ty);
-                            sz.add(tz);
-                        }
-                    }
-                }
-        if (!(sx.wide || sy.wide || sz.wide)) {
+        for (uint32_t c = lane; c < total; c += 64) {
+            int lo = 0, hi = 27;  // box of candidate c: the largest b with bpre[b] <= c
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (bpre[w][mid] <= c) lo = mid; else hi = mid;
+            }
+            const int64_t j = d.sorted_idx[bst[w][lo] + (c - bpre[w][lo])];
+            if (j == i) continue;
+            const double ddx = x - d.pos[P][j], ddy = y - d.pos[P][A + j], ddz = z - d.pos[P][2 * A + j];
+            const double d2 = fma(ddz, ddz, fma(ddy, ddy, ddx * ddx));
+            if (!(d2 < L2)) continue;
+            ++nbr;
+            const double rj = 0.5 * d.diam[lp][j];
+            const double dist = sqrt(d2);
+            const double delta = ri + rj - dist;
+            if (!(delta > 0.0)) continue;
+            ++contacts;
+            const double rbar = ri * rj / (ri + rj);
+            const double fn = S.k * delta - S.gamma * sqrt(rbar * delta);
+            if (fn != 0.0) ++nzc;
+            if (dist > 0.0) {
+                const double tx = fn * ddx / dist, ty = fn * ddy / dist, tz = fn * ddz / dist;
+                fx += tx;
+                fy += ty;
+                fz += tz;
+                sx.add(tx);
+                sy.add(ty);
+                sz.add(tz);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();  // the box tables are rewritten for the next agent
+        nbr = wave_sum_i32(nbr);
+        contacts = wave_sum_i32(contacts);
+        nzc = wave_sum_i32(nzc);
+        const bool wide = __builtin_amdgcn_ballot_w64(sx.wide || sy.wide || sz.wide) != 0;
+        if (wide) {
+            fx = wave_sum_f64(fx);
+            fy = wave_sum_f64(fy);
+            fz = wave_sum_f64(fz);
+        } else {
+            wave_sum128(sx.lo, sx.hi);
+            wave_sum128(sy.lo, sy.hi);
+            wave_sum128(sz.lo, sz.hi);
             fx = sx.value();
             fy = sy.value();
             fz = sz.value();
         }
-        const int64_t lin = linear_box(bx, by, bz, S.dims);
-        commit_agent<DIAG>(d, S, i, P, lp, fl, x, y, z, fx, fy, fz, nzc, nbr, contacts, d.mrank[S.b_off + lin], lin);
+        if (lane == 0) {
+            const uint8_t fl = d.flags[lp][i];
+            const int64_t lin = linear_box(bx, by, bz, S.dims);
+            commit_agent<DIAG>(d, S, i, P, lp, fl, x, y, z, fx, fy, fz, nzc, nbr, contacts, box_rank(d, S, bx, by, bz),
+                               lin);
+        }
     }
 }
 
@@ -1001,7 +1075,7 @@ __global__ void __launch_bounds__(256) k_static(Dev d) {
                     for (int ox = -1; ox <= 1 && st; ++ox) {
                         int cx = bx + ox, cy = by + oy, cz = bz + oz;
                         if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2]) continue;
-                        uint32_t m = d.mrank[S.b_off + linear_box(cx, cy, cz, S.dims)];
+                        uint32_t m = box_rank(d, S, cx, cy, cz);
                         if (!d.dirty[S.b_off + m]) continue;
                         uint32_t s0 = d.box_start[S.sb_off + m], s1 = d.box_start[S.sb_off + m + 1];
                         for (uint32_t slot = s0; slot < s1 && st; ++slot) {
@@ -1028,8 +1102,9 @@ void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag) {
 // the committed state.
 void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool diag, bool any_growth,
                         bool any_static, bool resort) {
-    if (diag) hipLaunchKernelGGL(k_fixup<true>, dim3(256), dim3(256), 0, st, d);
-    else hipLaunchKernelGGL(k_fixup<false>, dim3(256), dim3(256), 0, st, d);
+    // one wave per agent on the FP64 path (16384 waves, grid-stride beyond)
+    if (diag) hipLaunchKernelGGL(k_fixup<true>, dim3(4096), dim3(256), 0, st, d);
+    else hipLaunchKernelGGL(k_fixup<false>, dim3(4096), dim3(256), 0, st, d);
     if (any_growth) {
         hipLaunchKernelGGL(k_div_mark, dim3(grid_agents), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_div_check, dim3(1), dim3(256), 0, st, d);
