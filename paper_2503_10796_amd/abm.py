@@ -82,6 +82,20 @@ def lib():
         L.abm_pop_query.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64, _i64p]
         L.abm_pop_stats.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
         L.abm_pop_destroy.argtypes = [_vp]
+        _ip = ctypes.POINTER(ctypes.c_int)
+        _fp = ctypes.POINTER(ctypes.c_float)
+        L.abm_mlp_workspace_bytes.restype = ctypes.c_size_t
+        L.abm_mlp_workspace_bytes.argtypes = [_ip, ctypes.c_int, ctypes.c_int]
+        L.abm_mlp_create.argtypes = [_ip, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _vp, ctypes.c_size_t, _vp,
+                                     ctypes.POINTER(_vp)]
+        L.abm_mlp_train_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _fp]
+        L.abm_mlp_grads.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, _fp]
+        L.abm_mlp_infer.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+        L.abm_mlp_get_params.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.abm_mlp_set_params.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.abm_mlp_num_params.restype = ctypes.c_size_t
+        L.abm_mlp_num_params.argtypes = [_vp]
+        L.abm_mlp_destroy.argtypes = [_vp]
         _lib = L
     return _lib
 
@@ -272,3 +286,73 @@ class Population(Batch):
         check(lib().abm_pop_query(self.h, int(field), out.ctypes.data_as(ctypes.c_void_p), 0, max(n, 1),
                                   ctypes.byref(got)))
         return out[: got.value]
+
+
+class Mlp:
+    """Surrogate MLP on the GPU (BF16 matrix-core GEMMs, FP32 master weights).
+
+    Inputs and outputs are CUDA float32 tensors; parameters use the layout of
+    the C ABI (per layer W [out, in] row-major, then b)."""
+
+    def __init__(self, dims=(35, 256, 256, 256, 32), max_batch=4096, seed=0, stream=None):
+        torch = _torch()
+        L = lib()
+        self.dims = tuple(int(d) for d in dims)
+        self.max_batch = int(max_batch)
+        d = (ctypes.c_int * len(self.dims))(*self.dims)
+        nbytes = L.abm_mlp_workspace_bytes(d, len(self.dims), self.max_batch)
+        if nbytes == 0:
+            raise AbmError(ERR_ARG, "invalid MLP dims or batch")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self._stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        check(L.abm_mlp_create(d, len(self.dims), self.max_batch, int(seed), ctypes.c_void_p(self.workspace.data_ptr()),
+                               nbytes + 256, self._stream, ctypes.byref(h)))
+        self.h = h
+        self.n_params = int(L.abm_mlp_num_params(h))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.abm_mlp_destroy(h)
+            self.h = None
+
+    @staticmethod
+    def _dev(t):
+        torch = _torch()
+        t = t if hasattr(t, "data_ptr") else torch.as_tensor(np.asarray(t, dtype=np.float32))
+        return t.to(device="cuda", dtype=torch.float32).contiguous()
+
+    def train_step(self, x, y, lr=1e-3, want_loss=True):
+        x, y = self._dev(x), self._dev(y)
+        loss = ctypes.c_float()
+        check(lib().abm_mlp_train_step(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                       x.shape[0], float(lr), ctypes.byref(loss) if want_loss else None))
+        return float(loss.value) if want_loss else None
+
+    def grads(self, x, y):
+        torch = _torch()
+        x, y = self._dev(x), self._dev(y)
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = ctypes.c_float()
+        check(lib().abm_mlp_grads(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.shape[0],
+                                  ctypes.c_void_p(g.data_ptr()), ctypes.byref(loss)))
+        return float(loss.value), g
+
+    def infer(self, x, out=None):
+        torch = _torch()
+        x = self._dev(x)
+        y = out if out is not None else torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device="cuda")
+        check(lib().abm_mlp_infer(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.shape[0]))
+        return y
+
+    def get_params(self):
+        torch = _torch()
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        check(lib().abm_mlp_get_params(self.h, ctypes.c_void_p(p.data_ptr()), self.n_params))
+        return p
+
+    def set_params(self, theta):
+        p = self._dev(theta)
+        check(lib().abm_mlp_set_params(self.h, ctypes.c_void_p(p.data_ptr()), p.numel()))
+        _torch().cuda.current_stream().synchronize()

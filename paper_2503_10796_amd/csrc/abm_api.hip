@@ -20,6 +20,14 @@ using namespace abm;
 
 static thread_local std::string g_err;
 
+namespace abm {
+void clear_error() { g_err.clear(); }
+int set_error(int code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+}  // namespace abm
+
 static int fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;

@@ -125,6 +125,22 @@ __device__ inline uint32_t run_atomic_add(uint32_t *base, uint32_t key, bool val
     return __shfl(r, start) + (uint32_t)(lane - start);
 }
 
+// Philox4x32-10 (Salmon et al., SC 2011): ten rounds on the counter c with
+// key (k0, k1); c is replaced by the output block.
+__device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
 // Squared distance below L^2 with the neighbour predicate's exact expression.
 __device__ inline bool near_point(double x, double y, double z, double px, double py, double pz, double L2) {
 #pragma clang fp contract(off)

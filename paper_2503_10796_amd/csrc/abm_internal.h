@@ -158,6 +158,10 @@ __device__ inline float rel_coord(double v, double lo, double L, int b) {
     return (float)(v - origin);
 }
 
+// Error message of the last failed call on this thread (abm_last_error).
+void clear_error();
+int set_error(int code, const char *msg);
+
 // Host-side launch helpers implemented in the .hip files.
 void launch_iteration(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, int sweep_grid, bool diag,
                       bool any_growth, bool any_static, bool resort);

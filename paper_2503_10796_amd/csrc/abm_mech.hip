@@ -838,21 +838,6 @@ __device__ inline double cbrt_cr(double t) {
 
 __device__ inline double diameter_from_volume(double v) { return cbrt_cr((6.0 * v) / kPi); }
 
-// Philox4x32-10 (Salmon et al., SC'11).
-__device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    for (int r = 0; r < 10; ++r) {
-        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
 // Uniform unit vector for a division, keyed by (seed; uid, iteration, sim):
 // Archimedes' construction, z uniform in [-1, 1) and a uniform azimuth.
 __device__ inline void division_direction(uint64_t seed, uint32_t sim, uint64_t uid, uint64_t iter, double u[3]) {
