@@ -96,13 +96,129 @@ def copy_calibration(torch, steps):
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": steps}), flush=True)
 
 
+def bench_sweep(args):
+    """Batched parameter sweep (one graph launch per iteration for all
+    simulations) against the per-simulation path on the same simulations."""
+    import numpy as np
+    import torch
+    from paper_2503_10796_amd import sweep
+    cfg = sweep.SweepConfig(args.sims, seed=4, iters=args.sweep_iters)
+    t_gen = time.perf_counter()
+    counts = np.array([cfg.counts(s, *cfg.state(s)[2:4]) for s in range(cfg.n_sims)])
+    updates = float(counts[:, :cfg.iters].sum())
+    log(f"[bench] sweep inputs and exact agent counts in {time.perf_counter() - t_gen:.1f} s; "
+        f"{int(counts[:, 0].sum())} agents at the start, {int(counts[:, -1].sum())} at the end")
+    _, t_batch, n_end, grid = sweep.run_batched(cfg, record=False, tune=True, log=log)
+    assert np.array_equal(n_end, counts[:, -1].astype(np.int64)), "agent counts differ from the lineage count"
+    secs = sweep.run_per_sim(cfg, list(range(cfg.n_sims)))
+    t_single = float(secs.sum())
+    log(f"[bench] per-simulation path: {t_single:.3f} s for {cfg.n_sims} simulations")
+    out = {
+        "metric": "batched parameter sweep: agent updates/s, speedup over the per-simulation path",
+        "value": updates / t_batch, "unit": "agent updates/s", "n_gpus": 1, "steps": cfg.iters, "warmup": 1,
+        "ms_per_step": t_batch / cfg.iters * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"tumour-spheroid sweep: {cfg.n_sims} simulations, Latin hypercube seed 4 over growth "
+                               f"scale [0.5,1.5], division diameter [6,18] um, adherence [0.9,2.7]; initial counts "
+                               f"log-uniform [1e3,5e4]; {cfg.iters} iterations",
+                   "agents_start": int(counts[:, 0].sum()), "agents_end": int(counts[:, -1].sum()),
+                   "sweep_workgroups": grid},
+        "batched_s": t_batch, "per_simulation_s": t_single, "speedup_vs_per_simulation": t_single / t_batch,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_surrogate(args):
+    """Surrogate screening: train on windows of a batched sweep, judge on the
+    simulated histograms of held-out parameter sets, time the screening."""
+    import numpy as np
+    import torch
+    from paper_2503_10796_amd import sweep, surrogate
+    cfg = sweep.SweepConfig(args.sims, seed=4, iters=args.sweep_iters)
+    hist, t_train_sim, _, _ = sweep.run_batched(cfg, record=True, tune=False, log=log)
+    x, y = surrogate.windows(cfg, hist, 20000, seed=6, t_max=cfg.iters - surrogate.HORIZON)
+    model, t_train = surrogate.train(x, y, steps=args.train_steps, log=log)
+    log(f"[bench] trained {args.train_steps} steps in {t_train:.2f} s")
+    held = sweep.SweepConfig(2 * args.sims, seed=5, iters=cfg.iters)
+    parts = []
+    for half in range(2):
+        sims = list(range(half * args.sims, (half + 1) * args.sims))
+        h, _, _, _ = sweep.run_batched(held, record=True, tune=False, log=log, sims=sims)
+        parts.append(h)
+    hh = np.concatenate(parts, axis=1)
+    times = list(range(0, cfg.iters - surrogate.HORIZON + 1, 50))
+    xe, ye, h0 = surrogate.eval_windows(held, hh, times)
+    pred = model.predict(xe)
+    W = surrogate.linear_fit(x, y)
+    pred_lin = surrogate.to_hist(xe, surrogate.linear_predict(W, xe))
+    j_mlp, j_pers, j_lin = (surrogate.judge(p, ye, h0) for p in (pred, h0, pred_lin))
+    log(f"[bench] held-out relative L2 error: surrogate {j_mlp}, persistence {j_pers}, linear {j_lin}")
+    rg_true = surrogate.r_gyr_from_hist(ye)
+    rg_err = np.abs(surrogate.r_gyr_from_hist(pred) - rg_true) / np.maximum(rg_true, 1e-30)
+    rg_err_p = np.abs(surrogate.r_gyr_from_hist(h0) - rg_true) / np.maximum(rg_true, 1e-30)
+    # screening: 50 iterations for all held-out sets, batched and per simulation, vs one inference
+    t_b = 0.0
+    for half in range(2):
+        sims = list(range(half * args.sims, (half + 1) * args.sims))
+        _, tb, _, _ = sweep.run_batched(held, record=False, tune=False, sims=sims, iters=surrogate.HORIZON)
+        t_b += tb
+    n_ps = min(64, held.n_sims)
+    t_ps = float(sweep.run_per_sim(held, list(range(n_ps)), iters=surrogate.HORIZON).sum()) * held.n_sims / n_ps
+    # screening cost of the surrogate: one network call on standardised inputs already on the GPU
+    x_screen = torch.as_tensor(((xe[:held.n_sims] - model.xm) / model.xs).astype(np.float32), device="cuda")
+    x_big = torch.as_tensor(((np.resize(xe, (4096, xe.shape[1])) - model.xm) / model.xs).astype(np.float32),
+                            device="cuda")
+    net = model.model
+    for xx in (x_screen, x_big):
+        net.infer(xx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 20
+    for _ in range(reps):
+        net.infer(x_screen)
+    torch.cuda.synchronize()
+    t_inf = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.infer(x_big)
+    torch.cuda.synchronize()
+    t_inf_big = (time.perf_counter() - t0) / reps
+    flops = 2.0 * sum(surrogate.DIMS[i] * surrogate.DIMS[i + 1] for i in range(len(surrogate.DIMS) - 1)) * 4096
+    out = {
+        "metric": "surrogate screening speedup over the batched simulation at the stated error",
+        "value": t_b / t_inf, "unit": "x", "n_gpus": 1, "steps": args.train_steps, "warmup": 0,
+        "ms_per_step": t_train / args.train_steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (fp32 accumulate)", "data": "synthetic",
+        "config": {"workload": f"MLP 35-256-256-256-32 on 20000 windows of a {cfg.n_sims}-simulation sweep "
+                               f"(seed 4); judged on {held.n_sims} held-out sets (seed 5) at t = {times}, "
+                               f"horizon {surrogate.HORIZON} iterations"},
+        "error_rel_l2": {"surrogate": j_mlp, "persistence": j_pers, "linear": j_lin,
+                         "r_gyr_rel_median": float(np.median(rg_err)),
+                         "r_gyr_rel_median_persistence": float(np.median(rg_err_p))},
+        "gain_vs_persistence": {"mean": j_pers["mean"] / j_mlp["mean"],
+                                "median_changing": j_pers["median_changing"] / j_mlp["median_changing"],
+                                "median": j_pers["median"] / j_mlp["median"]},
+        "gain_vs_linear": {"mean": j_lin["mean"] / j_mlp["mean"], "median": j_lin["median"] / j_mlp["median"]},
+        "screen_s": {"batched_sim": t_b, "per_simulation_sim": t_ps, "surrogate_infer": t_inf},
+        "speedup_vs_per_simulation": t_ps / t_inf,
+        "inference_4096": {"ms": t_inf_big * 1e3, "tflops": flops / t_inf_big / 1e12},
+        "training_s": t_train,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--agents", type=int, default=100_000_000)
-    ap.add_argument("--workload", choices=["uniform", "relaxed"], default="uniform")
+    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate"], default="uniform",
+                    help="uniform / relaxed: mechanics at scale (the headline line); sweep: batched parameter "
+                         "sweep vs the per-simulation path; surrogate: screening speedup and error")
+    ap.add_argument("--sims", type=int, default=256, help="sweep: simulations")
+    ap.add_argument("--sweep-iters", type=int, default=300, help="sweep: iterations per simulation")
+    ap.add_argument("--train-steps", type=int, default=3000, help="surrogate: Adam steps")
     ap.add_argument("--resort-every", type=int, default=10)
     ap.add_argument("--sweep-grid", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -121,6 +237,12 @@ def main():
         copy_calibration(torch, args.steps)
         return
     sys.path.insert(0, ROOT)
+    if args.workload == "sweep":
+        bench_sweep(args)
+        return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
+        return
     from paper_2503_10796_amd import abm, inputs
 
     abm.lib()

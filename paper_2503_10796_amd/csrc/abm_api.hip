@@ -553,6 +553,23 @@ static bool any_diag(const abm_batch *b) {
     return false;
 }
 
+// Every iteration ends by building the grid of its result, and the iteration
+// graph relies on it.  The first step (and a step after an error) builds it
+// first, and puts agents into Morton order when re-sorting is on; so does the
+// tuner before it replays iterations.
+static int ensure_grid(abm_batch *b) {
+    if (b->grid_valid) return ABM_OK;
+    b->d.resort_every = b->resort_every;
+    launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);
+    if (b->resort_every > 0) {
+        launch_resort(b->d, b->stream, b->grid_agents, b->grid_boxes, true);
+        launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);
+    }
+    HIPCHK(hipGetLastError());
+    b->grid_valid = true;
+    return ABM_OK;
+}
+
 extern "C" int abm_batch_step(abm_batch *b, int n_iter) {
     g_err.clear();
     if (!b || n_iter < 0) return fail(ABM_ERR_ARG, "bad handle or iteration count");
@@ -561,19 +578,8 @@ extern "C" int abm_batch_step(abm_batch *b, int n_iter) {
     int rc = b->timing ? capture(b, 1, diag) : capture(b, 0, diag);
     if (!rc && b->timing) rc = capture(b, 2, diag);
     if (rc) return rc;
-    if (!b->grid_valid) {
-        // every iteration ends by building the grid of its result; the first
-        // step (and a step after an error) builds it first, and puts agents
-        // into Morton order when re-sorting is on
-        b->d.resort_every = b->resort_every;
-        launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);
-        if (b->resort_every > 0) {
-            launch_resort(b->d, b->stream, b->grid_agents, b->grid_boxes, true);
-            launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);
-        }
-        HIPCHK(hipGetLastError());
-        b->grid_valid = true;
-    }
+    rc = ensure_grid(b);
+    if (rc) return rc;
     if (b->timing) {
         while ((int)b->ev.size() < 2 * n_iter) {
             hipEvent_t e;
@@ -759,6 +765,8 @@ extern "C" int abm_batch_set_sweep_grid(abm_batch *b, int workgroups) {
 extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out) {
     g_err.clear();
     if (!b || n_trial_iters < 1) return fail(ABM_ERR_ARG, "bad arguments");
+    int rc0 = ensure_grid(b);  // the trials replay iterations, which need the grid
+    if (rc0) return rc0;
     // snapshot of the whole workspace so that trials leave the batch unchanged
     void *snap = nullptr;
     size_t bytes = b->L.total - 256;

@@ -501,6 +501,7 @@ __global__ void k_rs_end(Dev d) {
 // order per simulation.
 __global__ void __launch_bounds__(256) k_stats_sum(Dev d, int pass, double *out) {
     __shared__ double red[3][4];
+    __shared__ uint32_t hb[32];  // this tile's histogram counts
     const int P = d.ctl->pos_par;
     const int64_t A = d.A;
     const int64_t total = d.ctl->total_tiles;
@@ -510,6 +511,8 @@ __global__ void __launch_bounds__(256) k_stats_sum(Dev d, int pass, double *out)
         const SimDesc &S = d.sims[s];
         int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
         double v[3] = {0.0, 0.0, 0.0};
+        if (pass == 1 && threadIdx.x < 32) hb[threadIdx.x] = 0u;
+        __syncthreads();
         if (loc < S.n) {
             int64_t i = S.a_off + loc;
             double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
@@ -528,7 +531,7 @@ __global__ void __launch_bounds__(256) k_stats_sum(Dev d, int pass, double *out)
                 int64_t b = (int64_t)floor(r / w);
                 if (b > 31) b = 31;
                 if (b < 0) b = 0;
-                atomicAdd(&d.hist_cnt[32 * s + b], 1u);
+                atomicAdd(&hb[b], 1u);
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
@@ -551,31 +554,49 @@ __global__ void __launch_bounds__(256) k_stats_sum(Dev d, int pass, double *out)
             d.stat_part[3 * t + 1] = a1;
             d.stat_part[3 * t + 2] = a2;
         }
+        if (pass == 1 && threadIdx.x < 32 && hb[threadIdx.x]) atomicAdd(&d.hist_cnt[32 * s + threadIdx.x], hb[threadIdx.x]);
         __syncthreads();
     }
 }
 
-// out per simulation (40 doubles): centroid x, y, z, histogram radius, r_gyr, r_max
-__global__ void k_stats_fold(Dev d, int pass, double *out, double hist_rmax) {
-    for (int s = threadIdx.x; s < d.n_sims; s += blockDim.x) {
-        const SimDesc &S = d.sims[s];
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int64_t t = d.tile_begin[s]; t < d.tile_begin[s + 1]; ++t) {
-            a0 += d.stat_part[3 * t];
-            a2 += d.stat_part[3 * t + 2];
-            a1 = pass == 0 ? a1 + d.stat_part[3 * t + 1] : fmax(a1, d.stat_part[3 * t + 1]);
+// out per simulation (40 doubles): centroid x, y, z, histogram radius, r_gyr, r_max.
+// One block per simulation: each thread folds a fixed set of tiles, then a
+// fixed-order tree over the threads.
+__global__ void __launch_bounds__(256) k_stats_fold(Dev d, int pass, double *out, double hist_rmax) {
+    __shared__ double red[3][256];
+    const int s = blockIdx.x;
+    const SimDesc &S = d.sims[s];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t t = d.tile_begin[s] + threadIdx.x; t < d.tile_begin[s + 1]; t += blockDim.x) {
+        a0 += d.stat_part[3 * t];
+        a2 += d.stat_part[3 * t + 2];
+        a1 = pass == 0 ? a1 + d.stat_part[3 * t + 1] : fmax(a1, d.stat_part[3 * t + 1]);
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    red[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[2][threadIdx.x] += red[2][threadIdx.x + h];
+            red[1][threadIdx.x] = pass == 0 ? red[1][threadIdx.x] + red[1][threadIdx.x + h]
+                                            : fmax(red[1][threadIdx.x], red[1][threadIdx.x + h]);
         }
+        __syncthreads();
+    }
+    if (threadIdx.x < 32 && pass == 0) d.hist_cnt[32 * s + threadIdx.x] = 0u;
+    if (threadIdx.x == 0) {
         double *o = out + 40 * s;
-        double n = (double)S.n;
+        const double n = (double)S.n;
         if (pass == 0) {
-            o[0] = S.n > 0 ? a0 / n : 0.0;
-            o[1] = S.n > 0 ? a1 / n : 0.0;
-            o[2] = S.n > 0 ? a2 / n : 0.0;
+            o[0] = S.n > 0 ? red[0][0] / n : 0.0;
+            o[1] = S.n > 0 ? red[1][0] / n : 0.0;
+            o[2] = S.n > 0 ? red[2][0] / n : 0.0;
             o[3] = hist_rmax;
-            for (int b = 0; b < 32; ++b) d.hist_cnt[32 * s + b] = 0u;
         } else {
-            o[4] = S.n > 0 ? sqrt(a0 / n) : 0.0;
-            o[5] = a1;
+            o[4] = S.n > 0 ? sqrt(red[0][0] / n) : 0.0;
+            o[5] = red[1][0];
         }
     }
 }
@@ -651,9 +672,9 @@ void launch_end(const Dev &d, hipStream_t st, int grid_boxes, bool any_static) {
 void launch_stats(const Dev &d, hipStream_t st, int grid_agents, double hist_rmax, double *out_dev) {
     float *hist = (float *)(out_dev + 40 * d.n_sims);
     hipLaunchKernelGGL(k_stats_sum, dim3(grid_agents), dim3(256), 0, st, d, 0, out_dev);
-    hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, st, d, 0, out_dev, hist_rmax);
+    hipLaunchKernelGGL(k_stats_fold, dim3(d.n_sims), dim3(256), 0, st, d, 0, out_dev, hist_rmax);
     hipLaunchKernelGGL(k_stats_sum, dim3(grid_agents), dim3(256), 0, st, d, 1, out_dev);
-    hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(256), 0, st, d, 1, out_dev, hist_rmax);
+    hipLaunchKernelGGL(k_stats_fold, dim3(d.n_sims), dim3(256), 0, st, d, 1, out_dev, hist_rmax);
     hipLaunchKernelGGL(k_stats_hist, dim3(1), dim3(1024), 0, st, d, out_dev, hist);
 }
 

@@ -30,6 +30,7 @@ constexpr int kNb = kHalo * kHalo * kHalo;   // 216 staged boxes
 constexpr int kCore = kBlk * kBlk * kBlk;    // 64 target boxes
 constexpr int kStage = 1024;                 // staged agents (16 KB of float4), a power of two
 static_assert((kStage & (kStage - 1)) == 0, "staged indices are wrapped with a mask");
+static_assert(kStage >= 4 * 64, "the dense path uses 64 staged entries per wave of a 256-thread block");
 
 __device__ inline unsigned long long fixbits(double v) { return (unsigned long long)__double_as_longlong(v); }
 
@@ -131,7 +132,8 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
 //            drained 64 pairs at a time through the contact math (Eq 4.1-4.2)
 //            with exact fixed-point LDS atomics into per-target accumulators
 //   commit   per target: threshold, displacement, write-back (or FP64 path)
-// Units whose region does not fit in LDS take a slower global-memory path.
+// Units whose region does not fit in LDS (dense packings) take a box-wise
+// path that reads the payload from global memory.
 constexpr int kMaxT = 320;      // targets per unit on the LDS path
 constexpr int kBuckets = 64;    // task lengths 1..63, longer rows share the last bucket
 constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 16 | staged index)
@@ -314,63 +316,108 @@ __device__ inline uint32_t row_mask(float4 own, int cx, int cy, int cz, float Lf
     return m;
 }
 
-// Global-memory path of one unit (region larger than the LDS stage, or more
-// targets than kMaxT): one thread per target over its 27 boxes.
+// Exact sum of the accumulators of the lanes lane ^ off for off = g, 2g, ..., 32
+// (the streams of one target, see sweep_unit_dense).
+__device__ inline void acc_reduce_streams(Acc &a, int g) {
+    for (int off = g; off < 64; off <<= 1) {
+        a.ax += __shfl_xor(a.ax, off);
+        a.ay += __shfl_xor(a.ay, off);
+        a.az += __shfl_xor(a.az, off);
+        a.eacc += __shfl_xor(a.eacc, off);
+        a.contacts += __shfl_xor(a.contacts, off);
+        a.nz += __shfl_xor(a.nz, off);
+        a.nbr += __shfl_xor(a.nbr, off);
+        a.nfix += __shfl_xor(a.nfix, off);
+        a.nz_unc += __shfl_xor(a.nz_unc, off);
+        a.unc = (__shfl_xor((int)a.unc, off) | (int)a.unc) != 0;
+    }
+}
+
+// Dense units (region larger than the LDS stage, or more targets than kMaxT):
+// each wave takes one core box at a time.  All targets of a box share its
+// 27-box candidate set, so the lanes hold (target, stream) pairs, g targets
+// by 64 / g streams, and walk the candidates in wave-uniform loops with the
+// streams interleaved; the exact fixed-point sums of a target's streams are
+// then added across lanes.  Payload is read from global memory in coalesced
+// chunks of 64 candidates staged in the wave's slice of the LDS stage.
 template <bool DIAG>
-__device__ void sweep_unit_global(const Dev &d, const SimDesc &S, SweepLds<DIAG> &L, int P, int lp, int qx, int qy,
-                                  int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
+__device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> &L, int P, int lp, int qx, int qy,
+                                 int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
     const int64_t A = d.A;
-    const uint32_t nt = L.coff[kCore];
     const float Lf = (float)S.L;
-    for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
-        int c = 0, hi = kCore;
-        while (hi - c > 1) {
-            int mid = (c + hi) >> 1;
-            if (L.coff[mid] <= t) c = mid; else hi = mid;
-        }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float4 *buf = L.sp + 64 * w;  // the LDS stage is free on this path: 64 candidates per wave
+    for (int c = w; c < kCore; c += blockDim.x >> 6) {
         int cx, cy, cz;
         core_box_coords(c, cx, cy, cz);
         const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
-        const uint32_t slot = L.gsrc[lb] + (t - L.coff[c]);
-        const int64_t i = d.sorted_idx[slot];
+        const uint32_t cnt = L.scnt[lb];
+        if (cnt == 0) continue;
         const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
-        const uint8_t fl = d.flags[lp][i];
-        if (S.detect_static && (fl & kStatic)) {
-            skip_static<DIAG>(d, i, P, lp, fl, lin);
-            continue;
-        }
-        Acc a = {0, 0, 0, 0u, 0, 0, 0, 0, 0, false};
-        const float4 own = d.payload[slot];
-        for (int oz = -1; oz <= 1; ++oz)
-            for (int oy = -1; oy <= 1; ++oy) {
-                const int row = cx + kHalo * ((cy + 1 + oy) + kHalo * (cz + 1 + oz));
-                const float qy2 = own.y - (float)oy * Lf;
-                const float qz2 = own.z - (float)oz * Lf;
-                for (int ox = -1; ox <= 1; ++ox) {
-                    const int lbb = row + ox + 1;
-                    const float qx2 = own.x - (float)ox * Lf;
-                    const uint32_t b0 = L.gsrc[lbb], nn = L.sbeg[lbb + 1] - L.sbeg[lbb];
-                    for (uint32_t q = b0; q < b0 + nn; ++q)
-                        if (q != slot) pair_fp32<DIAG>(a, qx2, qy2, qz2, own.w, d.payload[q], e, g, kf, gf, L2m, L2p);
+        for (uint32_t p0 = 0; p0 < cnt;) {
+            // gsz targets in this pass (a power of two >= the remaining ones, at
+            // most 64), 64 / gsz streams each
+            int gsz = 1;
+            while (gsz < 64 && (uint32_t)gsz < cnt - p0) gsz <<= 1;
+            const int nstream = 64 / gsz;
+            const int tl = lane & (gsz - 1), sid = lane / gsz;
+            const uint32_t k = p0 + (uint32_t)tl;
+            const bool tv = k < cnt;
+            const uint32_t slot = L.gsrc[lb] + (tv ? k : 0u);
+            const int64_t i = d.sorted_idx[slot];
+            const uint8_t fl = d.flags[lp][i];
+            const bool stat = tv && S.detect_static && (fl & kStatic);
+            const bool act = tv && !stat;
+            if (stat && sid == 0) skip_static<DIAG>(d, i, P, lp, fl, lin);
+            Acc a = {0, 0, 0, 0u, 0, 0, 0, 0, 0, false};
+            const float4 own = d.payload[slot];
+            for (int oz = -1; oz <= 1; ++oz)
+                for (int oy = -1; oy <= 1; ++oy) {
+                    const int row = cx + kHalo * ((cy + 1 + oy) + kHalo * (cz + 1 + oz));
+                    const float qy2 = own.y - (float)oy * Lf;
+                    const float qz2 = own.z - (float)oz * Lf;
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const int lbb = row + ox + 1;
+                        const float qx2 = own.x - (float)ox * Lf;
+                        const uint32_t b0 = L.gsrc[lbb], nn = L.scnt[lbb];
+                        // the box's candidates 64 at a time: one coalesced load
+                        // per chunk into this wave's LDS slice, then broadcast reads
+                        for (uint32_t c0 = 0; c0 < nn; c0 += 64) {
+                            const uint32_t mc = nn - c0 < 64u ? nn - c0 : 64u;
+                            __builtin_amdgcn_wave_barrier();
+                            if ((uint32_t)lane < mc) buf[lane] = d.payload[b0 + c0 + (uint32_t)lane];
+                            __builtin_amdgcn_wave_barrier();
+                            for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
+                                const uint32_t j = j0 + (uint32_t)sid;
+                                const bool in = j < mc && act;
+                                const float4 cc = buf[j < mc ? j : 0u];
+                                if (in && b0 + c0 + j != slot)
+                                    pair_fp32<DIAG>(a, qx2, qy2, qz2, own.w, cc, e, g, kf, gf, L2m, L2p);
+                            }
+                        }
+                    }
+                }
+            acc_reduce_streams(a, gsz);
+            p0 += (uint32_t)gsz;
+            if (!act || sid != 0) continue;
+            bool unc = a.unc || !nz_decided(S, a.nz, a.nz_unc);
+            if (!unc) {
+                const unsigned long long mb = (unsigned long long)a.nfix * fixbits(kFixMagic);
+                const double fx = (double)(long long)(a.ax - mb) * kFixUnit;
+                const double fy = (double)(long long)(a.ay - mb) * kFixUnit;
+                const double fz = (double)(long long)(a.az - mb) * kFixUnit;
+                const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
+                const double ebound = (double)a.eacc * 0x1.0p-26 + 1e-9;
+                if (fabs(fnorm - S.adherence) <= ebound) {
+                    unc = true;
+                } else {
+                    const uint32_t m = box_rank(d, S, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz);
+                    commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
+                                       fz, a.nz + a.nz_unc, a.nbr, a.contacts, m, lin);
                 }
             }
-        bool unc = a.unc || !nz_decided(S, a.nz, a.nz_unc);
-        if (!unc) {
-            const unsigned long long mb = (unsigned long long)a.nfix * fixbits(kFixMagic);
-            const double fx = (double)(long long)(a.ax - mb) * kFixUnit;
-            const double fy = (double)(long long)(a.ay - mb) * kFixUnit;
-            const double fz = (double)(long long)(a.az - mb) * kFixUnit;
-            const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
-            const double ebound = (double)a.eacc * 0x1.0p-26 + 1e-9;
-            if (fabs(fnorm - S.adherence) <= ebound) {
-                unc = true;
-            } else {
-                const uint32_t m = box_rank(d, S, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz);
-                commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy, fz,
-                                   a.nz + a.nz_unc, a.nbr, a.contacts, m, lin);
-            }
+            if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
         }
-        if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
     }
 }
 
@@ -455,7 +502,7 @@ __global__ void __launch_bounds__(256) k_sweep(Dev d) {
         // and a margin of 2^-10 L for the block-relative FP32 coordinates
         const float reach_add = (float)S.rmax + g + (float)ldexp(S.L, -10);
         if (!staged || nt > (uint32_t)kMaxT) {
-            sweep_unit_global<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
         }
