@@ -83,6 +83,41 @@ def cpu_baseline(args):
                       f"iterations after one untimed iteration, FP64, OpenMP over agents, {dt:.1f} s"}
 
 
+def _counter_per_dispatch(path, kernel_substr, counter):
+    """Mean over dispatches of a kernel of one counter (summed over its
+    hardware instances) from a rocprofv3 csv counter file."""
+    import csv
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter:
+            per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+    return sum(per.values()) / len(per), len(per)
+
+
+def pmc_summary(args):
+    """HBM bytes of one force-sweep launch from the byte counters, each scaled
+    by what the same counter reads for a plain copy of known size."""
+    fetch, write, cfetch, cwrite = args.pmc_summary
+    f_kib, nf = _counter_per_dispatch(fetch, "k_sweep", "FETCH_SIZE")
+    w_kib, nw = _counter_per_dispatch(write, "k_sweep", "WRITE_SIZE")
+    cf_kib, _ = _counter_per_dispatch(cfetch, "copyBuffer", "FETCH_SIZE")
+    cw_kib, _ = _counter_per_dispatch(cwrite, "copyBuffer", "WRITE_SIZE")
+    copy_bytes = 2 ** 31
+    f_scale = copy_bytes / (cf_kib * 1024.0)
+    w_scale = copy_bytes / (cw_kib * 1024.0)
+    read_b = f_kib * 1024.0 * f_scale
+    write_b = w_kib * 1024.0 * w_scale
+    out = {"kernel": "k_sweep", "workload": args.workload, "agents": args.agents,
+           "kernel_source_sha256_16": kernel_source_hash(),
+           "fetch_kib_per_launch": f_kib, "write_kib_per_launch": w_kib, "dispatches": [nf, nw],
+           "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib, "fetch_scale": f_scale, "write_scale": w_scale,
+           "hbm_read_bytes_per_launch": read_b, "hbm_write_bytes_per_launch": write_b,
+           "hbm_bytes_per_launch": read_b + write_b}
+    with open(PMC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(torch, steps):
     """A plain copy of known size: the HBM byte counters of one such launch,
     divided by the bytes it must move (2 GiB read, 2 GiB written), give the
@@ -222,11 +257,17 @@ def main():
     ap.add_argument("--resort-every", type=int, default=10)
     ap.add_argument("--sweep-grid", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-agents", type=int, default=1_000_000)
-    ap.add_argument("--cpu-sample-iters", type=int, default=5)
+    ap.add_argument("--cpu-sample-agents", type=int, default=4_000_000)
+    ap.add_argument("--cpu-sample-iters", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB (reference kernel for the HBM byte counters)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the HBM bytes per force-sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counter "
+                         "files (this workload, then the copy calibration) into " + os.path.relpath(PMC_FILE, ROOT))
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)

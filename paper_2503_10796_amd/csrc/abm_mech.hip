@@ -422,7 +422,7 @@ __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> 
 }
 
 template <bool DIAG>
-__global__ void __launch_bounds__(256) k_sweep(Dev d) {
+__global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: at most 128 VGPRs
     __shared__ SweepLds<DIAG> L;
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
