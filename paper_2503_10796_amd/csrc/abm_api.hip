@@ -63,7 +63,7 @@ struct Layout {
     size_t sims, ctl, tile_begin, btile_begin, utile_begin, a_begin, wblk_begin, bnd, blist;
     size_t pos[2], diam[2], vol[2], growth[2], uid[2], flags[2], nz[2];
     size_t stage8, key, rank, payload, sorted_idx, nbr, contacts, force, disp, boxid;
-    size_t count, box_start, brank, dirty, arrive, tile_sum, tile_off, fix_list, divflag, divrank;
+    size_t count, box_start, brank, dirty, arrive, dirty_blk, arrive_blk, active_blk, near_blk, tile_sum, tile_off, fix_list, divflag, divrank;
     size_t stat_part, hist_cnt, stat_out;
     size_t total;
 };
@@ -118,6 +118,10 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
     L.blist = c.take<uint32_t>(B);
     L.dirty = c.take<uint8_t>(B);
     L.arrive = c.take<uint8_t>(B);
+    L.dirty_blk = c.take<uint8_t>(B);
+    L.arrive_blk = c.take<uint8_t>(B);
+    L.active_blk = c.take<uint8_t>(B);
+    L.near_blk = c.take<uint8_t>(B);
     L.tile_sum = c.take<uint32_t>(ST);
     L.tile_off = c.take<uint32_t>(ST);
     L.fix_list = c.take<uint32_t>(A);
@@ -335,6 +339,10 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     d.blist = (uint32_t *)(w + L.blist);
     d.dirty = (uint8_t *)(w + L.dirty);
     d.arrive = (uint8_t *)(w + L.arrive);
+    d.dirty_blk = (uint8_t *)(w + L.dirty_blk);
+    d.arrive_blk = (uint8_t *)(w + L.arrive_blk);
+    d.active_blk = (uint8_t *)(w + L.active_blk);
+    d.near_blk = (uint8_t *)(w + L.near_blk);
     d.tile_sum = (uint32_t *)(w + L.tile_sum);
     d.tile_off = (uint32_t *)(w + L.tile_off);
     d.fix_list = (uint32_t *)(w + L.fix_list);
@@ -360,6 +368,9 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     HIPCHK_C(hipMemsetAsync(d.flags[1], 0, A, st));
     HIPCHK_C(hipMemsetAsync(d.nz[0], 0, A, st));
     HIPCHK_C(hipMemsetAsync(d.arrive, 0, B, st));
+    HIPCHK_C(hipMemsetAsync(d.dirty_blk, 0, B, st));
+    HIPCHK_C(hipMemsetAsync(d.arrive_blk, 0, B, st));
+    HIPCHK_C(hipMemsetAsync(d.active_blk, 0, B, st));
     HIPCHK_C(hipMemsetAsync(d.growth[0], 0, sizeof(double) * A, st));
     HIPCHK_C(hipMemsetAsync(d.hist_cnt, 0, sizeof(unsigned) * 32 * n_sims, st));
 
@@ -542,6 +553,9 @@ static int clear_abort(abm_batch *b) {
     for (auto &S : sims) B += S.box_cap;
     HIPCHK(hipMemsetAsync(b->d.dirty, 0, B, b->stream));
     HIPCHK(hipMemsetAsync(b->d.arrive, 0, B, b->stream));
+    HIPCHK(hipMemsetAsync(b->d.dirty_blk, 0, B, b->stream));
+    HIPCHK(hipMemsetAsync(b->d.arrive_blk, 0, B, b->stream));
+    HIPCHK(hipMemsetAsync(b->d.active_blk, 0, B, b->stream));
     HIPCHK(hipMemsetAsync(b->d.count, 0, sizeof(uint32_t) * B, b->stream));
     HIPCHK(hipStreamSynchronize(b->stream));
     return ABM_OK;
@@ -562,7 +576,7 @@ static int ensure_grid(abm_batch *b) {
     b->d.resort_every = b->resort_every;
     launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);
     if (b->resort_every > 0) {
-        launch_resort(b->d, b->stream, b->grid_agents, b->grid_boxes, true);
+        launch_resort(b->d, b->stream, b->grid_agents, b->grid_boxes, true, b->any_static);
         launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);
     }
     HIPCHK(hipGetLastError());

@@ -99,6 +99,12 @@ __device__ inline uint32_t key_rank(const Dev &d, const SimDesc &S, uint32_t key
     return box_rank(d, S, bx, by, bz);
 }
 
+// Box marks of the static rule, kept per box slot and per aligned block.
+__device__ inline void mark_box(uint8_t *box_marks, uint8_t *blk_marks, const SimDesc &S, uint32_t m) {
+    box_marks[S.b_off + m] = 1;
+    blk_marks[S.b_off + (m >> 6)] = 1;
+}
+
 // Atomic counting in which runs of equal keys in consecutive lanes of a wave
 // share one atomic add of the run length at base[key]; returns this lane's
 // position among the adds to its counter.  Same-address atomics of one

@@ -238,7 +238,12 @@ __global__ void __launch_bounds__(256) k_bin(Dev d) {
         if (!valid) continue;
         d.key[i] = pack_key(bx, by, bz);
         d.rank[i] = r;
-        if (S.detect_static && (d.flags[lp][i] & kChgMask)) d.arrive[S.b_off + m] = 1;
+        if (S.detect_static) {
+            const uint8_t fl = d.flags[lp][i];
+            if (fl & kChgMask) mark_box(d.arrive, d.arrive_blk, S, m);
+            // the next sweep visits the block unless its agents are static and settled
+            if (!(fl & kStatic) || (fl & (kBufDiff | kChgMask))) d.active_blk[S.b_off + (m >> 6)] = 1;
+        }
     }
 }
 
@@ -366,11 +371,11 @@ __global__ void __launch_bounds__(256) k_static_fix(Dev d) {
         uint8_t fl = d.flags[lp][i];
         if (!(fl & kStatic)) continue;
         bool st = S.L >= S.L_prev;  // a shrunken grid cannot cover the old radius: be conservative
-        if (st) {
+        int bx, by, bz;
+        unpack_key(d.key[i], bx, by, bz);
+        if (st && d.near_blk[S.b_off + (box_rank(d, S, bx, by, bz) >> 6)]) {
             const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
             const double L2 = S.L_prev * S.L_prev;
-            int bx, by, bz;
-            unpack_key(d.key[i], bx, by, bz);
             for (int oz = -1; oz <= 1 && st; ++oz)
                 for (int oy = -1; oy <= 1 && st; ++oy)
                     for (int ox = -1; ox <= 1 && st; ++ox) {
@@ -386,25 +391,70 @@ __global__ void __launch_bounds__(256) k_static_fix(Dev d) {
                         }
                     }
         }
-        if (!st) d.flags[lp][i] = fl & ~kStatic;
+        if (!st) {
+            d.flags[lp][i] = fl & ~kStatic;
+            d.active_blk[S.b_off + (box_rank(d, S, bx, by, bz) >> 6)] = 1;
+        }
     }
 }
 
-// Clears the dirty and arrival marks of the current grid.
+// near_blk[b] = any dirty (or arrival) mark in block b or its 26 neighbours:
+// a static agent whose block is not near a mark has no changed agent within
+// one box of it.  One thread per block (block tiles of 16 blocks).
+__global__ void __launch_bounds__(256) k_near_marks(Dev d, int arrivals) {
+    if (ABM_ABORTED(d)) return;
+    const int64_t total = d.ctl->total_btiles;
+    const uint8_t *marks = arrivals ? d.arrive_blk : d.dirty_blk;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int s = find_sim(d.btile_begin, d.n_sims, t);
+        const SimDesc &S = d.sims[s];
+        if (!S.detect_static || threadIdx.x >= kBoxTile / 64) continue;
+        const int64_t blk = (t - d.btile_begin[s]) * (kBoxTile / 64) + threadIdx.x;
+        if (blk >= S.nblocks) continue;
+        int qx, qy, qz;
+        unpack_key(d.blist[S.b_off + blk], qx, qy, qz);
+        uint8_t any = 0;
+        for (int oz = -1; oz <= 1; ++oz)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int ox = -1; ox <= 1; ++ox) {
+                    const int cx = qx + ox, cy = qy + oy, cz = qz + oz;
+                    if (cx < 0 || cy < 0 || cz < 0 || cx >= S.bdims[0] || cy >= S.bdims[1] || cz >= S.bdims[2]) continue;
+                    const int64_t lin = (int64_t)cx + (int64_t)S.bdims[0] * ((int64_t)cy + (int64_t)S.bdims[1] * cz);
+                    any |= marks[S.b_off + d.brank[S.b_off + lin]];
+                }
+        d.near_blk[S.b_off + blk] = any;
+    }
+}
+
+// Clears the dirty and arrival marks of the current grid: the 64 box marks
+// of every marked block, then the block marks (a box tile holds 16 blocks).
 __global__ void __launch_bounds__(256) k_clear_marks(Dev d) {
     if (ABM_ABORTED(d)) return;
     const int64_t total = d.ctl->total_btiles;
+    const int q = threadIdx.x >> 4, e = threadIdx.x & 15;  // block of the tile, 16 threads per block
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         int s = find_sim(d.btile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
         if (!S.detect_static) continue;
-        int64_t k0 = (t - d.btile_begin[s]) * kBoxTile;
-        for (int q = threadIdx.x; q < kBoxTile; q += blockDim.x) {
-            if (k0 + q < S.nboxes) {
-                d.dirty[S.b_off + k0 + q] = 0;
-                d.arrive[S.b_off + k0 + q] = 0;
-            }
+        const int64_t blk = (t - d.btile_begin[s]) * (kBoxTile / 64) + q;
+        if (blk >= S.nblocks) continue;
+        const int64_t bi = S.b_off + blk;
+        if (!d.dirty_blk[bi] && !d.arrive_blk[bi]) continue;
+        for (int k = e; k < 64; k += 16) {
+            d.dirty[S.b_off + blk * 64 + k] = 0;
+            d.arrive[S.b_off + blk * 64 + k] = 0;
         }
+    }
+    __syncthreads();
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int s = find_sim(d.btile_begin, d.n_sims, t);
+        const SimDesc &S = d.sims[s];
+        if (!S.detect_static || e != 0) continue;
+        const int64_t blk = (t - d.btile_begin[s]) * (kBoxTile / 64) + q;
+        if (blk >= S.nblocks) continue;
+        d.dirty_blk[S.b_off + blk] = 0;
+        d.arrive_blk[S.b_off + blk] = 0;
+        d.active_blk[S.b_off + blk] = 0;
     }
 }
 
@@ -484,6 +534,28 @@ __global__ void __launch_bounds__(256) k_rs_move(Dev d) {
         d.uid[nl][j] = d.uid[lp][i];
         d.flags[nl][j] = d.flags[lp][i] | kBufDiff;
         d.nz[nl][j] = d.nz[lp][i];
+    }
+}
+
+// After a re-sort of a simulation with static detection, both position
+// buffers receive the new arrangement, so that static agents need no
+// visit to settle differing buffers (runs before the parities flip).
+__global__ void __launch_bounds__(256) k_rs_sync(Dev d) {
+    if (ABM_ABORTED(d) || !d.ctl->resort_now) return;
+    const int P = d.ctl->pos_par, lp = d.ctl->lay_par;  // buffers of the old arrangement
+    const int64_t A = d.A;
+    const int64_t total = d.ctl->total_tiles;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int s = find_sim(d.tile_begin, d.n_sims, t);
+        const SimDesc &S = d.sims[s];
+        if (!S.detect_static || S.nboxes == 0) continue;
+        const int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
+        if (loc >= S.n) continue;
+        const int64_t i = S.a_off + loc;
+        d.pos[P][i] = d.pos[1 - P][i];
+        d.pos[P][A + i] = d.pos[1 - P][A + i];
+        d.pos[P][2 * A + i] = d.pos[1 - P][2 * A + i];
+        d.flags[1 - lp][i] &= (uint8_t)~kBufDiff;
     }
 }
 
@@ -649,17 +721,25 @@ void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_b
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_scatter, dim3(grid_agents), dim3(256), 0, st, d);
-    if (any_static) hipLaunchKernelGGL(k_static_fix, dim3(grid_agents), dim3(256), 0, st, d);
+    if (any_static) {
+        launch_near_marks(d, st, grid_boxes, true);
+        hipLaunchKernelGGL(k_static_fix, dim3(grid_agents), dim3(256), 0, st, d);
+    }
 }
 
-void launch_resort(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool force) {
+void launch_resort(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool force, bool any_static) {
     if (force) hipLaunchKernelGGL(k_force_resort, dim3(1), dim3(64), 0, st, d);
     hipLaunchKernelGGL(k_rs_count, dim3(grid_agents), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_rs_move, dim3(grid_agents), dim3(256), 0, st, d);
+    if (any_static) hipLaunchKernelGGL(k_rs_sync, dim3(grid_agents), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_rs_end, dim3(1), dim3(64), 0, st, d);
+}
+
+void launch_near_marks(const Dev &d, hipStream_t st, int grid_boxes, bool arrivals) {
+    hipLaunchKernelGGL(k_near_marks, dim3(grid_boxes), dim3(256), 0, st, d, arrivals ? 1 : 0);
 }
 
 void launch_end(const Dev &d, hipStream_t st, int grid_boxes, bool any_static) {

@@ -97,6 +97,9 @@ struct Dev {
     uint32_t *brank;              // linear block id -> Morton rank of the block
     uint8_t *dirty;   // boxes holding the start position of a changed agent
     uint8_t *arrive;  // boxes of the new grid holding a changed agent
+    uint8_t *dirty_blk, *arrive_blk;  // the same marks per aligned 4x4x4 block (index: box slot / 64)
+    uint8_t *active_blk;  // blocks of the current grid holding an agent the next sweep must visit
+    uint8_t *near_blk;    // a dirty (or arrival) mark in the block or one of its 26 neighbours
     uint32_t *tile_sum, *tile_off;
     uint32_t *fix_list;
     uint32_t *divflag, *divrank;
@@ -169,8 +172,9 @@ void launch_grid_build(const Dev &d, hipStream_t s, int grid_agents, int grid_bo
 void launch_sweep(const Dev &d, hipStream_t s, int sweep_grid, bool diag);
 void launch_after_sweep(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool diag, bool any_growth,
                         bool any_static, bool resort);
-void launch_resort(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool force);
+void launch_resort(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool force, bool any_static);
 void launch_end(const Dev &d, hipStream_t s, int grid_boxes, bool any_static);
+void launch_near_marks(const Dev &d, hipStream_t s, int grid_boxes, bool arrivals);
 void launch_stats(const Dev &d, hipStream_t s, int grid_agents, double hist_rmax, double *out_dev);
 void launch_gather_pos(const Dev &d, hipStream_t s, int sim, double *dst, int64_t n, int64_t a_off);
 void launch_scatter_init(const Dev &d, hipStream_t s, int grid_agents);

@@ -75,7 +75,7 @@ __device__ inline void commit_agent(const Dev &d, const SimDesc &S, int64_t i, i
         d.pos[1 - P][A + i] = y + dy;
         d.pos[1 - P][2 * A + i] = z + dz;
         d.flags[lp][i] = fl | kBufDiff | kMoved;
-        if (S.detect_static) d.dirty[S.b_off + m] = 1;  // start box of a changed agent
+        if (S.detect_static) mark_box(d.dirty, d.dirty_blk, S, m);  // start box of a changed agent
     } else {
         if (fl & kBufDiff) {
             d.pos[1 - P][i] = x;
@@ -439,6 +439,10 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
     for (int64_t u = xcd * chunk + (blockIdx.x >> 3); u < u_end; u += per_xcd) {
         const int s = find_sim(d.wblk_begin, d.n_sims, u);
         const SimDesc &S = d.sims[s];
+        // with static detection, a block whose agents are all static and
+        // settled needs no visit (marked while binning the grid); the
+        // diagnostic mode visits every block to write its per-agent fields
+        if (!DIAG && S.detect_static && !d.active_blk[S.b_off + (u - d.wblk_begin[s])]) continue;
         int qx, qy, qz;
         unpack_key(d.blist[S.b_off + (u - d.wblk_begin[s])], qx, qy, qz);
         // ---- table of the 6x6x6 staged boxes (x fastest)
@@ -473,25 +477,8 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             if (tid == 63) L.coff[64] = x;
             L.bcnt[tid] = 0;
         }
-        const float Lf = (float)S.L;
-        const bool staged = total <= (uint32_t)kStage;
-        if (staged) {
-            // box-relative -> relative to the centre of the 6x6x6 region (|x| < 3L)
-            for (uint32_t k = tid; k < total; k += blockDim.x) {
-                int lo = 0, hi = kNb;  // largest lb with sbeg[lb] <= k
-                while (hi - lo > 1) {
-                    int mid = (lo + hi) >> 1;
-                    if (L.sbeg[mid] <= k) lo = mid; else hi = mid;
-                }
-                float4 c = d.payload[L.gsrc[lo] + (k - L.sbeg[lo])];
-                const int lx = lo % kHalo, ly = (lo / kHalo) % kHalo, lz = lo / (kHalo * kHalo);
-                c.x += (float)(lx - 3) * Lf;
-                c.y += (float)(ly - 3) * Lf;
-                c.z += (float)(lz - 3) * Lf;
-                L.sp[k] = c;
-            }
-        }
         __syncthreads();
+        const float Lf = (float)S.L;
         const uint32_t nt = L.coff[kCore];
         const float e = S.e_delta, g = 2.0f * e;
         const float kf = (float)S.k, gf = (float)S.gamma;
@@ -501,12 +488,14 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
         // largest reach beyond the target radius: largest radius, guard band
         // and a margin of 2^-10 L for the block-relative FP32 coordinates
         const float reach_add = (float)S.rmax + g + (float)ldexp(S.L, -10);
-        if (!staged || nt > (uint32_t)kMaxT) {
+        const bool lds_path = total <= (uint32_t)kStage && nt <= (uint32_t)kMaxT;
+        if (!lds_path) {
             sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
         }
-        // ---- setup: static skip, accumulators, task counts per row length
+        // ---- targets: static skip (Sec 5.5), staged index, core box, zero accumulators
+        int active = 0;
         for (uint32_t t = tid; t < nt; t += blockDim.x) {
             int c = 0, hi = kCore;
             while (hi - c > 1) {
@@ -527,8 +516,8 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                     stat = true;
                 }
             }
-            const uint32_t self = L.sbeg[lb] + k;
-            L.tself[t] = stat ? kNoTarget : (uint16_t)self;
+            active |= stat ? 0 : 1;
+            L.tself[t] = stat ? kNoTarget : (uint16_t)(L.sbeg[lb] + k);
             L.tbox[t] = (uint8_t)c;
             L.acc[0][t] = 0;
             L.acc[1][t] = 0;
@@ -536,16 +525,37 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             L.acnt[t] = 0;
             L.aeacc[t] = 0;
             if (DIAG) L.anbr[t] = 0;
-            if (!stat) {
-                const uint32_t rows = row_mask<DIAG>(L.sp[self], cx, cy, cz, Lf, reach_add);
-                L.trow[t] = rows;
-                for (int r = 0; r < 9; ++r) {
-                    const uint32_t rb = (rows >> (3 * r)) & 7u;
-                    if (!rb) continue;
-                    const int row = task_row(cx, cy, cz, r);
-                    const uint32_t len = L.sbeg[row + ((rb & 4u) ? 3 : 2)] - L.sbeg[row + ((rb & 2u) ? 0 : 1)];
-                    if (len) atomicAdd(&L.bcnt[len < kBuckets ? len : kBuckets - 1], 1u);
-                }
+        }
+        if (!__syncthreads_or(active)) continue;  // every target static: nothing to stage or sweep
+        // ---- stage: box-relative -> relative to the centre of the 6x6x6 region (|x| < 3L)
+        for (uint32_t k = tid; k < total; k += blockDim.x) {
+            int lo = 0, hi = kNb;  // largest lb with sbeg[lb] <= k
+            while (hi - lo > 1) {
+                int mid = (lo + hi) >> 1;
+                if (L.sbeg[mid] <= k) lo = mid; else hi = mid;
+            }
+            float4 c = d.payload[L.gsrc[lo] + (k - L.sbeg[lo])];
+            const int lx = lo % kHalo, ly = (lo / kHalo) % kHalo, lz = lo / (kHalo * kHalo);
+            c.x += (float)(lx - 3) * Lf;
+            c.y += (float)(ly - 3) * Lf;
+            c.z += (float)(lz - 3) * Lf;
+            L.sp[k] = c;
+        }
+        __syncthreads();
+        // ---- setup: rows within reach of every active target, task counts per row length
+        for (uint32_t t = tid; t < nt; t += blockDim.x) {
+            const uint32_t self = L.tself[t];
+            if (self == kNoTarget) continue;
+            int cx, cy, cz;
+            core_box_coords(L.tbox[t], cx, cy, cz);
+            const uint32_t rows = row_mask<DIAG>(L.sp[self], cx, cy, cz, Lf, reach_add);
+            L.trow[t] = rows;
+            for (int r = 0; r < 9; ++r) {
+                const uint32_t rb = (rows >> (3 * r)) & 7u;
+                if (!rb) continue;
+                const int row = task_row(cx, cy, cz, r);
+                const uint32_t len = L.sbeg[row + ((rb & 4u) ? 3 : 2)] - L.sbeg[row + ((rb & 2u) ? 0 : 1)];
+                if (len) atomicAdd(&L.bcnt[len < kBuckets ? len : kBuckets - 1], 1u);
             }
         }
         __syncthreads();
@@ -1070,7 +1080,7 @@ __global__ void __launch_bounds__(256) k_div_apply(Dev d) {
             d.diam[lp][i] = diameter_from_volume(nv);
             d.flags[lp][i] |= kGrew;
         }
-        if (S.detect_static) d.dirty[S.b_off + key_rank(d, S, d.key[i])] = 1;  // start box of a changed agent
+        if (S.detect_static) mark_box(d.dirty, d.dirty_blk, S, key_rank(d, S, d.key[i]));  // start box of a changed agent
     }
 }
 
@@ -1097,11 +1107,11 @@ __global__ void __launch_bounds__(256) k_static(Dev d) {
         int64_t i = S.a_off + loc;
         uint8_t fl = d.flags[lp][i];
         bool st = !(fl & kChgMask) && d.nz[lp][i] <= 1;
-        if (st) {
+        int bx, by, bz;
+        unpack_key(d.key[i], bx, by, bz);
+        if (st && d.near_blk[S.b_off + (box_rank(d, S, bx, by, bz) >> 6)]) {
             const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
             const double L2 = S.L * S.L;
-            int bx, by, bz;
-            unpack_key(d.key[i], bx, by, bz);
             for (int oz = -1; oz <= 1 && st; ++oz)
                 for (int oy = -1; oy <= 1 && st; ++oy)
                     for (int ox = -1; ox <= 1 && st; ++ox) {
@@ -1145,9 +1155,12 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
         hipLaunchKernelGGL(k_uscan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_div_apply, dim3(grid_agents), dim3(256), 0, st, d);
     }
-    if (any_static) hipLaunchKernelGGL(k_static, dim3(grid_agents), dim3(256), 0, st, d);
+    if (any_static) {
+        launch_near_marks(d, st, grid_boxes, false);
+        hipLaunchKernelGGL(k_static, dim3(grid_agents), dim3(256), 0, st, d);
+    }
     launch_end(d, st, grid_boxes, any_static);
-    if (resort) launch_resort(d, st, grid_agents, grid_boxes, false);
+    if (resort) launch_resort(d, st, grid_agents, grid_boxes, false, any_static);
     launch_grid_build(d, st, grid_agents, grid_boxes, any_static);
 }
 
