@@ -242,6 +242,34 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
+def mechanics_population(kind, agents, resort_every=10, sweep_grid=2048):
+    """The mechanics workload at scale, in the launch configuration that is
+    timed: (population, agents, description).  The full-size parity tests
+    build their population through this function as well."""
+    from paper_2503_10796_amd import abm, inputs
+
+    if kind == "uniform":
+        pos, diam = inputs.at_density(agents, seed=1)
+        side = inputs.cube_side(agents)
+        workload = (f"plain mechanics: {agents} agents uniform in a {side:.1f} um cube (1 per 1000 um^3), "
+                    f"diameters U[10,15) um, box 15 um, Morton re-sort every {resort_every} iterations")
+    else:
+        n_side = round(agents ** (1.0 / 3.0))
+        pos, diam = inputs.relaxed_lattice(n_side, seed=2)
+        side = n_side * 15.5
+        workload = (f"pre-relaxed mechanics: {n_side}^3 agents on a jittered 15.5 um lattice with 5% moved next to a "
+                    f"neighbour, diameters U[10,15) um, box 15 um, static skip on, Morton re-sort every "
+                    f"{resort_every} iterations")
+    n = pos.shape[0]
+    dims = side / 15.0 + 4.0
+    box_cap = int(1.1 * dims ** 3) + 4096
+    p = abm.params(box_len=15.0, resort_every=resort_every, detect_static=(kind == "relaxed"))
+    pop = abm.Population(p, pos, diam, capacity=n, box_capacity=box_cap)
+    del pos, diam
+    pop.set_sweep_grid(sweep_grid)
+    return pop, n, workload
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,30 +312,12 @@ def main():
     if args.workload == "surrogate":
         bench_surrogate(args)
         return
-    from paper_2503_10796_amd import abm, inputs
+    from paper_2503_10796_amd import abm
 
     abm.lib()
     t_gen = time.perf_counter()
-    if args.workload == "uniform":
-        pos, diam = inputs.at_density(args.agents, seed=1)
-        side = inputs.cube_side(args.agents)
-        workload = (f"plain mechanics: {args.agents} agents uniform in a {side:.1f} um cube (1 per 1000 um^3), "
-                    f"diameters U[10,15) um, box 15 um, Morton re-sort every {args.resort_every} iterations")
-    else:
-        n_side = round(args.agents ** (1.0 / 3.0))
-        pos, diam = inputs.relaxed_lattice(n_side, seed=2)
-        side = n_side * 15.5
-        workload = (f"pre-relaxed mechanics: {n_side}^3 agents on a jittered 15.5 um lattice with 5% moved next to a "
-                    f"neighbour, diameters U[10,15) um, box 15 um, static skip on, Morton re-sort every "
-                    f"{args.resort_every} iterations")
-    n = pos.shape[0]
-    log(f"[bench] generated {n} agents in {time.perf_counter() - t_gen:.1f} s")
-    dims = side / 15.0 + 4.0
-    box_cap = int(1.1 * dims ** 3) + 4096
-    p = abm.params(box_len=15.0, resort_every=args.resort_every, detect_static=(args.workload == "relaxed"))
-    pop = abm.Population(p, pos, diam, capacity=n, box_capacity=box_cap)
-    del pos, diam
-    pop.set_sweep_grid(args.sweep_grid)
+    pop, n, workload = mechanics_population(args.workload, args.agents, args.resort_every, args.sweep_grid)
+    log(f"[bench] generated and uploaded {n} agents in {time.perf_counter() - t_gen:.1f} s")
     pop.set_timing(True)  # graphs are captured during the warmup
     torch.cuda.synchronize()
     log(f"[bench] population created; workspace {pop.workspace.numel() / 2**30:.1f} GiB")

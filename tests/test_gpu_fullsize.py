@@ -1,0 +1,120 @@
+"""Parity at full size: 1e8 agents in the launch configuration the benchmark
+times (graph-captured iterations, row culling and reach tests, static skip
+for the pre-relaxed population, Morton re-sort every 10 iterations), checked
+on sampled agents that the oracle computes one at a time.
+
+A contact needs a centre distance below the mean of the two diameters, which
+is at most the box length L (Sec 4.4.3: the box length is the largest diameter).  Every
+contact of an agent inside an inner cube therefore lies inside that cube
+grown by L on each side, and the oracle is given only the grown cube.  The
+oracle's own grid over that sub-population differs from the GPU's, but the
+set of touching pairs, hence the force (Eq 4.1-4.2) and the displacement,
+does not depend on where the boxes fall."""
+import time
+
+import numpy as np
+import pytest
+
+import bench
+from oracle import sim as osim
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+N_AGENTS = 100_000_000
+L = 15.0
+HALF = 45.0  # half side of an inner cube, um
+
+
+@pytest.fixture(scope="module")
+def abm():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_10796_amd import abm as _abm
+    _abm.lib()
+    return _abm
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _centres(lo, hi, rng, k):
+    """A domain corner, a face centre, the domain centre, then random points."""
+    mid = 0.5 * (lo + hi)
+    out = [lo.copy(), np.array([lo[0], mid[1], mid[2]]), mid]
+    while len(out) < k:
+        out.append(rng.uniform(lo, hi))
+    return out
+
+
+def _check_step(abm, pop, op, rng, n_regions):
+    """Step the population once and compare every agent of n_regions inner
+    cubes with the oracle's single step from the same state."""
+    t0 = time.perf_counter()
+    pos0 = pop.query(abm.POS)
+    diam0 = pop.query(abm.DIAM)
+    uid0 = pop.query(abm.UID).astype(np.int64)
+    pop.step(1)
+    pos1 = pop.query(abm.POS)
+    uid1 = pop.query(abm.UID).astype(np.int64)
+    n = pos0.shape[0]
+    assert pos1.shape[0] == n
+    # no growth here: the uids stay a permutation of 0..n-1
+    inv = np.full(n, -1, dtype=np.int64)
+    inv[uid1] = np.arange(n, dtype=np.int64)
+    assert np.all(inv >= 0), "uids are not a permutation"
+    lo, hi = pos0.min(axis=0), pos0.max(axis=0)
+    scale = op.dt / op.mass
+    checked = moved = 0
+    worst = 0.0
+    for c in _centres(lo, hi, rng, n_regions):
+        cand = np.nonzero(np.abs(pos0[:, 0] - c[0]) < HALF + L + 0.5)[0]
+        grown = cand[np.all(np.abs(pos0[cand] - c) < HALF + L + 0.5, axis=1)]
+        p_sub = pos0[grown]
+        inner = np.nonzero(np.all(np.abs(p_sub - c) < HALF, axis=1))[0]
+        if inner.size == 0:
+            continue
+        o = osim.OracleSim(p_sub, diam0[grown], op, uid=uid0[grown])
+        _, _, d, tol = o.forces_subset(inner)
+        start = p_sub[inner]
+        expect = start + d
+        got = pos1[inv[uid0[grown][inner]]]
+        mv_o = np.any(d != 0, axis=1)
+        mv_g = np.any(got != start, axis=1)
+        assert np.array_equal(mv_g, mv_o), f"move decisions differ in the cube at {c}"
+        bound = scale * (1e-5 * tol[:, 0] + H.E_DELTA_REL * L * tol[:, 1]) + 1e-12
+        err = np.linalg.norm(got - expect, axis=1)
+        ok = err <= bound + 1e-13 * np.abs(expect).max(axis=1)
+        assert np.all(ok), f"positions differ in the cube at {c}: worst err/bound {float((err / bound).max())}"
+        checked += inner.size
+        moved += int(mv_o.sum())
+        worst = max(worst, float((err / bound).max()))
+    _say(f"  checked {checked} agents ({moved} moved), worst err/bound {worst:.3g}, "
+         f"{time.perf_counter() - t0:.1f} s")
+    assert checked > 1000
+    return moved
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("kind", ["uniform", "relaxed"])
+def test_full_size_sampled_agents_match_oracle(abm, kind):
+    t0 = time.perf_counter()
+    pop, n, _ = bench.mechanics_population(kind, N_AGENTS)
+    _say(f"[{kind}] {n} agents uploaded in {time.perf_counter() - t0:.1f} s")
+    op = H.oracle_params(detect_static=(kind == "relaxed"))
+    rng = np.random.default_rng(11)
+    pop.step(5)  # the benchmark's warmup: graphs captured, static flags set
+    # iterations 5, 9 and 10: before, at and after a Morton re-sort
+    for it, before in ((5, 0), (9, 3), (10, 0)):
+        if before:
+            pop.step(before)
+        _say(f"[{kind}] iteration {it}")
+        moved = _check_step(abm, pop, op, rng, n_regions=10)
+        if kind == "uniform":
+            assert moved > 0
+    static = pop.query(abm.STATIC)
+    if kind == "relaxed":
+        assert static.mean() > 0.9
+    del pop
