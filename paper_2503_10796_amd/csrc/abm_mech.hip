@@ -136,18 +136,19 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
 // path that reads the payload from global memory.
 constexpr int kMaxT = 320;      // targets per unit on the LDS path
 constexpr int kBuckets = 64;    // task lengths 1..63, longer rows share the last bucket
-constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 16 | staged index)
-constexpr uint32_t kUncBit = 0x80000000u;  // acnt: the target needs the FP64 path
-constexpr uint32_t kNzUncOne = 0x10000u;   // acnt bits 16..30: contacts whose force may be zero
+constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 20 | target's staged
+                                // index << 10 | candidate's staged index)
+constexpr unsigned long long kUncBit = 0x80000000ull;  // acm: the target needs the FP64 path
+constexpr unsigned long long kNzUncOne = 0x10000ull;   // acm bits 16..30: contacts whose force may be zero
 constexpr uint16_t kNoTarget = 0xffff;
 
 template <bool DIAG>
 struct SweepLds {
     float4 sp[kStage];                      // staged payload, block-relative coordinates
     unsigned long long acc[3][kMaxT];       // force sums, 2^-40 units (two's complement)
-    uint32_t acnt[kMaxT];                   // contacts with a certain non-zero force (bits 0..15),
-                                            // contacts whose force may be zero (16..30), kUncBit
-    uint32_t aeacc[kMaxT];                  // FP32 error bound of the sum, 2^-26 units
+    unsigned long long acm[kMaxT];          // contacts with a certain non-zero force (bits 0..15),
+                                            // contacts whose force may be zero (16..30), kUncBit,
+                                            // FP32 error bound of the sum in 2^-26 units (32..63)
     uint32_t anbr[DIAG ? kMaxT : 1];        // neighbours within the box length
     uint32_t sbeg[kNb + 1];                 // exclusive prefix of the staged box counts
     uint32_t gsrc[kNb];                     // global slot start of every staged box
@@ -255,12 +256,10 @@ template <bool DIAG>
 __device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32_t cnt, float e, float g, float kf,
                                    float gf, float L2m, float L2p) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t ent = qw[lane];
-    const uint32_t t = lane < cnt ? ent >> 16 : 0u;
-    const uint32_t q = lane < cnt ? ent & 0xffffu : 0u;
-    const uint32_t self = L.tself[t];
-    const bool valid = lane < cnt && q != self && self != kNoTarget;
-    const float4 own = L.sp[valid ? self : 0u];
+    const uint32_t ent = lane < cnt ? qw[lane] : 0u;
+    const uint32_t t = ent >> 20, self = (ent >> 10) & 1023u, q = ent & 1023u;
+    const bool valid = lane < cnt && q != self;
+    const float4 own = L.sp[self];
     const float4 c = L.sp[q];
     const float ddx = own.x - c.x, ddy = own.y - c.y, ddz = own.z - c.z;
     const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
@@ -271,10 +270,10 @@ __device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32
         atomicAdd(&L.acc[0][t], fixbits(fma(f, (double)ddx, kFixMagic)) - mb);
         atomicAdd(&L.acc[1][t], fixbits(fma(f, (double)ddy, kFixMagic)) - mb);
         atomicAdd(&L.acc[2][t], fixbits(fma(f, (double)ddz, kFixMagic)) - mb);
-        atomicAdd(&L.acnt[t], o.nz_unc ? kNzUncOne : 1u);
-        atomicAdd(&L.aeacc[t], (uint32_t)ceilf(o.ep * 0x1.0p26f));
+        atomicAdd(&L.acm[t], (o.nz_unc ? kNzUncOne : 1ull) |
+                                 ((unsigned long long)(uint32_t)ceilf(o.ep * 0x1.0p26f) << 32));
     }
-    if (o.unc || (DIAG && o.nz_unc)) atomicOr(&L.acnt[t], kUncBit);
+    if (o.unc || (DIAG && o.nz_unc)) atomicOr(&L.acm[t], kUncBit);
 }
 
 __device__ inline void core_box_coords(int c, int &cx, int &cy, int &cz) {
@@ -522,8 +521,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             L.acc[0][t] = 0;
             L.acc[1][t] = 0;
             L.acc[2][t] = 0;
-            L.acnt[t] = 0;
-            L.aeacc[t] = 0;
+            L.acm[t] = 0;
             if (DIAG) L.anbr[t] = 0;
         }
         if (!__syncthreads_or(active)) continue;  // every target static: nothing to stage or sweep
@@ -542,21 +540,33 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             L.sp[k] = c;
         }
         __syncthreads();
-        // ---- setup: rows within reach of every active target, task counts per row length
-        for (uint32_t t = tid; t < nt; t += blockDim.x) {
+        // ---- setup: rows within reach of every active target (at most two per
+        // thread), task counts per row length; the length bucket of every row
+        // (6 bits each) stays in registers for the task scatter
+        static_assert(kMaxT <= 512 && kBuckets == 64, "two targets per thread, 6-bit buckets");
+        unsigned long long bk[2] = {0ull, 0ull};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t t = (uint32_t)tid + 256u * (uint32_t)h;
+            if (t >= nt) continue;
             const uint32_t self = L.tself[t];
             if (self == kNoTarget) continue;
             int cx, cy, cz;
             core_box_coords(L.tbox[t], cx, cy, cz);
             const uint32_t rows = row_mask<DIAG>(L.sp[self], cx, cy, cz, Lf, reach_add);
             L.trow[t] = rows;
+            unsigned long long b = 0;
+#pragma unroll
             for (int r = 0; r < 9; ++r) {
                 const uint32_t rb = (rows >> (3 * r)) & 7u;
-                if (!rb) continue;
                 const int row = task_row(cx, cy, cz, r);
-                const uint32_t len = L.sbeg[row + ((rb & 4u) ? 3 : 2)] - L.sbeg[row + ((rb & 2u) ? 0 : 1)];
-                if (len) atomicAdd(&L.bcnt[len < kBuckets ? len : kBuckets - 1], 1u);
+                const uint32_t len =
+                    rb ? L.sbeg[row + ((rb & 4u) ? 3 : 2)] - L.sbeg[row + ((rb & 2u) ? 0 : 1)] : 0u;
+                const uint32_t bu = len < kBuckets ? len : kBuckets - 1;
+                if (bu) atomicAdd(&L.bcnt[bu], 1u);
+                b |= (unsigned long long)bu << (6 * r);
             }
+            bk[h] = b;
         }
         __syncthreads();
         if (tid < 64) {  // bucket offsets, longest rows first (one wave)
@@ -571,18 +581,14 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             if (tid == 63) L.ntask = x;
         }
         __syncthreads();
-        for (uint32_t t = tid; t < nt; t += blockDim.x) {
-            if (L.tself[t] == kNoTarget) continue;
-            int cx, cy, cz;
-            core_box_coords(L.tbox[t], cx, cy, cz);
-            const uint32_t rows = L.trow[t];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t t = (uint32_t)tid + 256u * (uint32_t)h;
+#pragma unroll
             for (int r = 0; r < 9; ++r) {
-                const uint32_t rb = (rows >> (3 * r)) & 7u;
-                if (!rb) continue;
-                const int row = task_row(cx, cy, cz, r);
-                const uint32_t len = L.sbeg[row + ((rb & 4u) ? 3 : 2)] - L.sbeg[row + ((rb & 2u) ? 0 : 1)];
-                if (len) {
-                    const uint32_t p = atomicAdd(&L.boff[len < kBuckets ? len : kBuckets - 1], 1u);
+                const uint32_t bu = (uint32_t)(bk[h] >> (6 * r)) & 63u;
+                if (bu) {
+                    const uint32_t p = atomicAdd(&L.boff[bu], 1u);
                     L.task[p] = (uint16_t)((t << 4) | (uint32_t)r);
                 }
             }
@@ -607,7 +613,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                 const uint32_t self = L.tself[t];
                 const float4 own = L.sp[self];
                 const float owg = own.w + g;
-                const uint32_t tq = (t << 16) + b0;
+                const uint32_t tq = (t << 20) | (self << 10) | b0;  // + kk: b0 + kk < kStage
                 uint32_t nb = 0;
                 bool un = false;
                 // candidates b0, b0+1, ...: lanes past their row end read
@@ -616,23 +622,24 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                 float4 cc = L.sp[q];
                 for (uint32_t kk = 0;; ++kk) {
                     const bool in = kk < len;
-                    if (!__builtin_amdgcn_ballot_w64(in)) break;
+                    const uint64_t im = __builtin_amdgcn_ballot_w64(in);
+                    if (!im) break;
                     const uint32_t qn1 = (q + 1) & (kStage - 1);
                     const float4 cn = L.sp[qn1];
                     const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
                     const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
                     const float sg = owg + cc.w;
-                    const bool sv = in && d2 < sg * sg;
+                    const bool hit = d2 < sg * sg;
                     if (DIAG) {
                         const bool other = in && q != self;
                         nb += (other && d2 < L2m) ? 1u : 0u;
                         un |= other && d2 >= L2m && d2 < L2p;
                     }
-                    const uint64_t m = __builtin_amdgcn_ballot_w64(sv);
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit) & im;
                     if (m) {
-                        const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        if (sv) qw[qn + below] = tq + kk;
+                        if (in && hit)
+                            qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = tq + kk;
                         qn += (uint32_t)__popcll(m);
                         if (qn >= 64) {
                             __builtin_amdgcn_wave_barrier();
@@ -648,7 +655,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                 }
                 if (DIAG && tv) {
                     atomicAdd(&L.anbr[t], nb);
-                    if (un) atomicOr(&L.acnt[t], kUncBit);
+                    if (un) atomicOr(&L.acm[t], kUncBit);
                 }
             }
             if (qn) {
@@ -666,15 +673,16 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
             const int64_t i = d.sorted_idx[L.gsrc[lb] + (t - L.coff[c])];
             const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
-            const uint32_t ac = L.acnt[t];
+            const unsigned long long acm = L.acm[t];
+            const uint32_t ac = (uint32_t)acm;
             const int nz_min = (int)(ac & 0xffffu), nz_unc = (int)((ac >> 16) & 0x7fffu);
-            bool unc = (ac & kUncBit) != 0 || !nz_decided(S, nz_min, nz_unc);
+            bool unc = (ac & (uint32_t)kUncBit) != 0 || !nz_decided(S, nz_min, nz_unc);
             if (!unc) {
                 const double fx = (double)(long long)L.acc[0][t] * kFixUnit;
                 const double fy = (double)(long long)L.acc[1][t] * kFixUnit;
                 const double fz = (double)(long long)L.acc[2][t] * kFixUnit;
                 const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
-                const double ebound = (double)L.aeacc[t] * 0x1.0p-26 + 1e-9;
+                const double ebound = (double)(uint32_t)(acm >> 32) * 0x1.0p-26 + 1e-9;
                 if (fabs(fnorm - S.adherence) <= ebound) {
                     unc = true;
                 } else {
