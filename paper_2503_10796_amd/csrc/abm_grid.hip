@@ -511,22 +511,39 @@ __global__ void __launch_bounds__(256) k_rs_count(Dev d) {
     }
 }
 
-// Out of place: the source buffers are only read.  Positions land in the
-// other position buffer only, so every agent is marked as having differing
-// buffers.
-__global__ void __launch_bounds__(256) k_rs_move(Dev d) {
+// The move is a gather: k_rs_dest writes the source of every destination
+// slot into sorted_idx (rebuilt by the grid build that follows), and
+// k_rs_move copies each destination's fields from its source, so that the
+// writes are coalesced.  Out of place: the source buffers are only read.
+// Positions land in the other position buffer only, so every agent is
+// marked as having differing buffers.
+__global__ void __launch_bounds__(256) k_rs_dest(Dev d) {
     if (ABM_ABORTED(d) || !d.ctl->resort_now) return;
-    const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
-    const int64_t A = d.A;
     const int64_t total = d.ctl->total_tiles;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         int s = find_sim(d.tile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
         int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
         if (loc >= S.n || S.nboxes == 0) continue;
-        int64_t i = S.a_off + loc;
-        int64_t j = (int64_t)d.box_start[S.sb_off + d.key[i]] + d.rank[i];
-        const int nl = 1 - lp;
+        const int64_t i = S.a_off + loc;
+        const int64_t j = (int64_t)d.box_start[S.sb_off + d.key[i]] + d.rank[i];
+        d.sorted_idx[j] = (uint32_t)i;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_rs_move(Dev d) {
+    if (ABM_ABORTED(d) || !d.ctl->resort_now) return;
+    const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
+    const int64_t A = d.A;
+    const int64_t total = d.ctl->total_tiles;
+    const int nl = 1 - lp;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        int s = find_sim(d.tile_begin, d.n_sims, t);
+        const SimDesc &S = d.sims[s];
+        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
+        if (loc >= S.n || S.nboxes == 0) continue;
+        const int64_t j = S.a_off + loc;
+        const int64_t i = d.sorted_idx[j];
         for (int a = 0; a < 3; ++a) d.pos[1 - P][a * A + j] = d.pos[P][a * A + i];
         d.diam[nl][j] = d.diam[lp][i];
         d.vol[nl][j] = d.vol[lp][i];
@@ -733,6 +750,7 @@ void launch_resort(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes
     hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d);
     hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_rs_dest, dim3(grid_agents), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_rs_move, dim3(grid_agents), dim3(256), 0, st, d);
     if (any_static) hipLaunchKernelGGL(k_rs_sync, dim3(grid_agents), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_rs_end, dim3(1), dim3(64), 0, st, d);
