@@ -28,8 +28,7 @@ constexpr double kFixUnit = 0x1.0p-40;
 constexpr int kHalo = kBlk + 2;              // 6
 constexpr int kNb = kHalo * kHalo * kHalo;   // 216 staged boxes
 constexpr int kCore = kBlk * kBlk * kBlk;    // 64 target boxes
-constexpr int kStage = 1024;                 // staged agents (16 KB of float4), a power of two
-static_assert((kStage & (kStage - 1)) == 0, "staged indices are wrapped with a mask");
+constexpr int kStage = 960;                  // staged agents (15 KB of float4)
 static_assert(kStage >= 4 * 64, "the dense path uses 64 staged entries per wave of a 256-thread block");
 
 __device__ inline unsigned long long fixbits(double v) { return (unsigned long long)__double_as_longlong(v); }
@@ -134,7 +133,8 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
 //   commit   per target: threshold, displacement, write-back (or FP64 path)
 // Units whose region does not fit in LDS (dense packings) take a box-wise
 // path that reads the payload from global memory.
-constexpr int kMaxT = 320;      // targets per unit on the LDS path
+constexpr int kMaxT = 300;      // targets per unit on the LDS path (mean 216 at 1 agent per 1000 um^3)
+constexpr int kRows = 10;       // tasks per target: nine rows, the own row's left halo box apart
 constexpr int kBuckets = 64;    // task lengths 1..63, longer rows share the last bucket
 constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 20 | target's staged
                                 // index << 10 | candidate's staged index)
@@ -153,16 +153,18 @@ struct SweepLds {
     uint32_t sbeg[kNb + 1];                 // exclusive prefix of the staged box counts
     uint32_t gsrc[kNb];                     // global slot start of every staged box
     uint32_t coff[kCore + 1];               // prefix of the target counts of the core boxes
-    uint32_t scnt[kNb];
     uint32_t bcnt[kBuckets], boff[kBuckets];
     uint32_t queue[4][kQueue];
     uint32_t sh[4];
     uint32_t ntask;
-    uint16_t task[9 * kMaxT];               // target << 4 | row, sorted by row length (longest first)
+    uint16_t task[kRows * kMaxT];           // target << 4 | row, sorted by length (longest first)
     uint32_t trow[kMaxT];                   // per row r, bits 3r..3r+2: row used, left box, right box
     uint16_t tself[kMaxT];                  // staged index of each target (kNoTarget: static)
+    uint16_t tmap[kStage];                  // target of each staged agent (kNoTarget: halo or static)
     uint8_t tbox[kMaxT];                    // core box of each target
 };
+static_assert(sizeof(SweepLds<false>) <= 40960, "four blocks of 256 threads per CU");
+static_assert(kStage < 1024 && kMaxT < 512, "queue entries: 9-bit target, 10-bit staged indices");
 
 // Per-target accumulator of the global-memory path.
 struct Acc {
@@ -252,9 +254,12 @@ __device__ inline bool nz_decided(const SimDesc &S, int nz_min, int nz_unc) {
 }
 
 // Drains `cnt` (<= 64) queued pairs of this wave (lane l takes entry l).
+// With the half shell (n3), a pair of two targets is drained once and adds
+// the opposite force (exact in fixed point) and the same counts to the
+// candidate's accumulators.
 template <bool DIAG>
 __device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32_t cnt, float e, float g, float kf,
-                                   float gf, float L2m, float L2p) {
+                                   float gf, float L2m, float L2p, bool n3) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t ent = lane < cnt ? qw[lane] : 0u;
     const uint32_t t = ent >> 20, self = (ent >> 10) & 1023u, q = ent & 1023u;
@@ -264,16 +269,30 @@ __device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32
     const float ddx = own.x - c.x, ddy = own.y - c.y, ddz = own.z - c.z;
     const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
     const PairOut o = pair_math(ddx, ddy, ddz, d2, own.w, c.w, e, g, kf, gf, L2m, L2p, valid);
+    const uint32_t tq = n3 ? L.tmap[q] : kNoTarget;
     if (o.contact) {
         const double f = (double)o.f;
         const unsigned long long mb = fixbits(kFixMagic);
-        atomicAdd(&L.acc[0][t], fixbits(fma(f, (double)ddx, kFixMagic)) - mb);
-        atomicAdd(&L.acc[1][t], fixbits(fma(f, (double)ddy, kFixMagic)) - mb);
-        atomicAdd(&L.acc[2][t], fixbits(fma(f, (double)ddz, kFixMagic)) - mb);
-        atomicAdd(&L.acm[t], (o.nz_unc ? kNzUncOne : 1ull) |
-                                 ((unsigned long long)(uint32_t)ceilf(o.ep * 0x1.0p26f) << 32));
+        const unsigned long long fx = fixbits(fma(f, (double)ddx, kFixMagic)) - mb;
+        const unsigned long long fy = fixbits(fma(f, (double)ddy, kFixMagic)) - mb;
+        const unsigned long long fz = fixbits(fma(f, (double)ddz, kFixMagic)) - mb;
+        const unsigned long long cm =
+            (o.nz_unc ? kNzUncOne : 1ull) | ((unsigned long long)(uint32_t)ceilf(o.ep * 0x1.0p26f) << 32);
+        atomicAdd(&L.acc[0][t], fx);
+        atomicAdd(&L.acc[1][t], fy);
+        atomicAdd(&L.acc[2][t], fz);
+        atomicAdd(&L.acm[t], cm);
+        if (tq != kNoTarget) {
+            atomicAdd(&L.acc[0][tq], 0ull - fx);
+            atomicAdd(&L.acc[1][tq], 0ull - fy);
+            atomicAdd(&L.acc[2][tq], 0ull - fz);
+            atomicAdd(&L.acm[tq], cm);
+        }
     }
-    if (o.unc || (DIAG && o.nz_unc)) atomicOr(&L.acm[t], kUncBit);
+    if (o.unc || (DIAG && o.nz_unc)) {
+        atomicOr(&L.acm[t], kUncBit);
+        if (tq != kNoTarget) atomicOr(&L.acm[tq], kUncBit);
+    }
 }
 
 __device__ inline void core_box_coords(int c, int &cx, int &cy, int &cz) {
@@ -315,6 +334,47 @@ __device__ inline uint32_t row_mask(float4 own, int cx, int cy, int cz, float Lf
     return m;
 }
 
+// Candidate range of task r of a target in core box (cx,cy,cz) with staged
+// index self and kept boxes `rows` (row_mask): r < 9 is row r, r == 9 the
+// own row's left halo box under the half shell.  Without the half shell a
+// row is its kept boxes.  With it (n3: every target of the unit active), a
+// pair of two targets is taken once, by the one with the smaller staged
+// index (staging runs in box order, x fastest): rows before the own row keep
+// only their halo box (core lines have at most one, at x = -1 or x = 4),
+// the own row keeps the candidates after the target (task r) and its halo
+// left box (task 9), rows after it are kept whole.  Lines outside the core
+// hold no targets and are kept whole.
+template <bool DIAG>
+__device__ inline void task_range(const SweepLds<DIAG> &L, uint32_t rows, int cx, int cy, int cz, int r, bool n3,
+                                  uint32_t self, uint32_t &b0, uint32_t &len) {
+    const int rr = r < 9 ? r : 4;  // task 9 belongs to the own row
+    const uint32_t rb = (rows >> (3 * rr)) & 7u;
+    const int row = task_row(cx, cy, cz, rr);  // staged box of the row's left box
+    uint32_t lo = L.sbeg[row + ((rb & 2u) ? 0 : 1)], hi = L.sbeg[row + ((rb & 4u) ? 3 : 2)];
+    bool keep = rb != 0 && (r < 9 || n3);
+    if (keep && n3) {
+        const int dy = rr % 3 - 1, dz = rr / 3 - 1;
+        const int y = cy + dy, z = cz + dz;
+        if (y >= 0 && y < kBlk && z >= 0 && z < kBlk) {
+            const bool lh = cx == 0 && (rb & 2u), rh = cx == kBlk - 1 && (rb & 4u);  // kept halo boxes
+            if (r == 9) {  // own row, halo left box
+                keep = lh;
+                hi = L.sbeg[row + 1];
+            } else if (dz < 0 || (dz == 0 && dy < 0)) {  // before the own row
+                keep = lh || rh;
+                if (lh) hi = L.sbeg[row + 1];
+                else lo = L.sbeg[row + 2];
+            } else if (dz == 0 && dy == 0) {  // own row: after the target
+                lo = self + 1;
+            }
+        } else {
+            keep = r < 9;
+        }
+    }
+    b0 = lo;
+    len = keep && hi > lo ? hi - lo : 0u;
+}
+
 // Exact sum of the accumulators of the lanes lane ^ off for off = g, 2g, ..., 32
 // (the streams of one target, see sweep_unit_dense).
 __device__ inline void acc_reduce_streams(Acc &a, int g) {
@@ -350,7 +410,7 @@ __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> 
         int cx, cy, cz;
         core_box_coords(c, cx, cy, cz);
         const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
-        const uint32_t cnt = L.scnt[lb];
+        const uint32_t cnt = L.sbeg[lb + 1] - L.sbeg[lb];
         if (cnt == 0) continue;
         const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
         for (uint32_t p0 = 0; p0 < cnt;) {
@@ -378,7 +438,7 @@ __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> 
                     for (int ox = -1; ox <= 1; ++ox) {
                         const int lbb = row + ox + 1;
                         const float qx2 = own.x - (float)ox * Lf;
-                        const uint32_t b0 = L.gsrc[lbb], nn = L.scnt[lbb];
+                        const uint32_t b0 = L.gsrc[lbb], nn = L.sbeg[lbb + 1] - L.sbeg[lbb];
                         // the box's candidates 64 at a time: one coalesced load
                         // per chunk into this wave's LDS slice, then broadcast reads
                         for (uint32_t c0 = 0; c0 < nn; c0 += 64) {
@@ -456,7 +516,6 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                 cnt = d.box_start[S.sb_off + m + 1] - src;
             }
             L.gsrc[tid] = src;
-            L.scnt[tid] = cnt;
         }
         uint32_t v[4] = {cnt, 0u, 0u, 0u};
         uint32_t total;
@@ -466,7 +525,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
         __syncthreads();
         if (tid < 64) {  // prefix of the target counts over the 64 core boxes (one wave)
             const int lb = (tid % 4 + 1) + kHalo * ((tid / 4 % 4 + 1) + kHalo * (tid / 16 + 1));
-            const uint32_t cc = L.scnt[lb];
+            const uint32_t cc = L.sbeg[lb + 1] - L.sbeg[lb];
             uint32_t x = cc;
             for (int off = 1; off < 64; off <<= 1) {
                 uint32_t y = __shfl_up(x, off);
@@ -494,7 +553,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             continue;
         }
         // ---- targets: static skip (Sec 5.5), staged index, core box, zero accumulators
-        int active = 0;
+        int active = 0, anystat = 0;
         for (uint32_t t = tid; t < nt; t += blockDim.x) {
             int c = 0, hi = kCore;
             while (hi - c > 1) {
@@ -516,6 +575,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                 }
             }
             active |= stat ? 0 : 1;
+            anystat |= stat ? 1 : 0;
             L.tself[t] = stat ? kNoTarget : (uint16_t)(L.sbeg[lb] + k);
             L.tbox[t] = (uint8_t)c;
             L.acc[0][t] = 0;
@@ -525,6 +585,8 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             if (DIAG) L.anbr[t] = 0;
         }
         if (!__syncthreads_or(active)) continue;  // every target static: nothing to stage or sweep
+        // the half shell needs every core agent of the unit to be a target
+        const bool n3 = !DIAG && !(S.detect_static && __syncthreads_or(anystat));
         // ---- stage: box-relative -> relative to the centre of the 6x6x6 region (|x| < 3L)
         for (uint32_t k = tid; k < total; k += blockDim.x) {
             int lo = 0, hi = kNb;  // largest lb with sbeg[lb] <= k
@@ -538,12 +600,18 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             c.y += (float)(ly - 3) * Lf;
             c.z += (float)(lz - 3) * Lf;
             L.sp[k] = c;
+            uint16_t tm = kNoTarget;
+            if (lx >= 1 && lx <= kBlk && ly >= 1 && ly <= kBlk && lz >= 1 && lz <= kBlk) {
+                const uint32_t t = L.coff[(lx - 1) + kBlk * ((ly - 1) + kBlk * (lz - 1))] + (k - L.sbeg[lo]);
+                if (L.tself[t] != kNoTarget) tm = (uint16_t)t;
+            }
+            L.tmap[k] = tm;
         }
         __syncthreads();
         // ---- setup: rows within reach of every active target (at most two per
         // thread), task counts per row length; the length bucket of every row
         // (6 bits each) stays in registers for the task scatter
-        static_assert(kMaxT <= 512 && kBuckets == 64, "two targets per thread, 6-bit buckets");
+        static_assert(kMaxT <= 512 && kBuckets == 64 && kRows <= 10, "two targets per thread, 6-bit buckets");
         unsigned long long bk[2] = {0ull, 0ull};
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -557,11 +625,9 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             L.trow[t] = rows;
             unsigned long long b = 0;
 #pragma unroll
-            for (int r = 0; r < 9; ++r) {
-                const uint32_t rb = (rows >> (3 * r)) & 7u;
-                const int row = task_row(cx, cy, cz, r);
-                const uint32_t len =
-                    rb ? L.sbeg[row + ((rb & 4u) ? 3 : 2)] - L.sbeg[row + ((rb & 2u) ? 0 : 1)] : 0u;
+            for (int r = 0; r < kRows; ++r) {
+                uint32_t b0, len;
+                task_range<DIAG>(L, rows, cx, cy, cz, r, n3, self, b0, len);
                 const uint32_t bu = len < kBuckets ? len : kBuckets - 1;
                 if (bu) atomicAdd(&L.bcnt[bu], 1u);
                 b |= (unsigned long long)bu << (6 * r);
@@ -585,7 +651,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
         for (int h = 0; h < 2; ++h) {
             const uint32_t t = (uint32_t)tid + 256u * (uint32_t)h;
 #pragma unroll
-            for (int r = 0; r < 9; ++r) {
+            for (int r = 0; r < kRows; ++r) {
                 const uint32_t bu = (uint32_t)(bk[h] >> (6 * r)) & 63u;
                 if (bu) {
                     const uint32_t p = atomicAdd(&L.boff[bu], 1u);
@@ -603,28 +669,27 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                 const uint32_t j = c0 + lane;
                 const bool tv = j < ntask;
                 const uint32_t tk = L.task[tv ? j : c0];
-                const uint32_t t = tk >> 4, r = tk & 15u;
+                const uint32_t t = tk >> 4;
                 int cx, cy, cz;
                 core_box_coords(L.tbox[t], cx, cy, cz);
-                const int row = task_row(cx, cy, cz, (int)r);
-                const uint32_t rb = (L.trow[t] >> (3 * r)) & 7u;
-                const uint32_t b0 = L.sbeg[row + ((rb & 2u) ? 0 : 1)];
-                const uint32_t len = tv ? L.sbeg[row + ((rb & 4u) ? 3 : 2)] - b0 : 0u;
                 const uint32_t self = L.tself[t];
+                uint32_t b0, len;
+                task_range<DIAG>(L, L.trow[t], cx, cy, cz, (int)(tk & 15u), n3, self, b0, len);
+                if (!tv) len = 0;
                 const float4 own = L.sp[self];
                 const float owg = own.w + g;
                 const uint32_t tq = (t << 20) | (self << 10) | b0;  // + kk: b0 + kk < kStage
                 uint32_t nb = 0;
                 bool un = false;
                 // candidates b0, b0+1, ...: lanes past their row end read
-                // wrapped indices and are masked; the next one is prefetched
-                uint32_t q = b0 & (kStage - 1);
+                // clamped indices and are masked; the next one is prefetched
+                uint32_t q = b0 < (uint32_t)kStage ? b0 : kStage - 1;
                 float4 cc = L.sp[q];
                 for (uint32_t kk = 0;; ++kk) {
                     const bool in = kk < len;
                     const uint64_t im = __builtin_amdgcn_ballot_w64(in);
                     if (!im) break;
-                    const uint32_t qn1 = (q + 1) & (kStage - 1);
+                    const uint32_t qn1 = q + 1 < (uint32_t)kStage ? q + 1 : kStage - 1;
                     const float4 cn = L.sp[qn1];
                     const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
                     const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
@@ -643,7 +708,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                         qn += (uint32_t)__popcll(m);
                         if (qn >= 64) {
                             __builtin_amdgcn_wave_barrier();
-                            drain_queue<DIAG>(L, qw, 64u, e, g, kf, gf, L2m, L2p);
+                            drain_queue<DIAG>(L, qw, 64u, e, g, kf, gf, L2m, L2p, n3);
                             __builtin_amdgcn_wave_barrier();
                             qn -= 64;
                             if (lane < qn) qw[lane] = qw[64 + lane];
@@ -660,7 +725,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             }
             if (qn) {
                 __builtin_amdgcn_wave_barrier();
-                drain_queue<DIAG>(L, qw, qn, e, g, kf, gf, L2m, L2p);
+                drain_queue<DIAG>(L, qw, qn, e, g, kf, gf, L2m, L2p, n3);
             }
         }
         __syncthreads();
