@@ -683,13 +683,13 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                 bool un = false;
                 // candidates b0, b0+1, ...: lanes past their row end read
                 // clamped indices and are masked; the next one is prefetched
-                uint32_t q = b0 < (uint32_t)kStage ? b0 : kStage - 1;
+                uint32_t q = min(b0, (uint32_t)kStage - 1u);
                 float4 cc = L.sp[q];
                 for (uint32_t kk = 0;; ++kk) {
                     const bool in = kk < len;
                     const uint64_t im = __builtin_amdgcn_ballot_w64(in);
                     if (!im) break;
-                    const uint32_t qn1 = q + 1 < (uint32_t)kStage ? q + 1 : kStage - 1;
+                    const uint32_t qn1 = min(q + 1u, (uint32_t)kStage - 1u);
                     const float4 cn = L.sp[qn1];
                     const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
                     const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
