@@ -133,7 +133,7 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
 //   commit   per target: threshold, displacement, write-back (or FP64 path)
 // Units whose region does not fit in LDS (dense packings) take a box-wise
 // path that reads the payload from global memory.
-constexpr int kMaxT = 300;      // targets per unit on the LDS path (mean 216 at 1 agent per 1000 um^3)
+constexpr int kMaxT = 280;      // targets per unit on the LDS path (mean 216 at 1 agent per 1000 um^3)
 constexpr int kRows = 10;       // tasks per target: nine rows, the own row's left halo box apart
 constexpr int kBuckets = 64;    // task lengths 1..63, longer rows share the last bucket
 constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 20 | target's staged
@@ -160,6 +160,7 @@ struct SweepLds {
     uint16_t task[kRows * kMaxT];           // target << 4 | row, sorted by length (longest first)
     uint32_t trow[kMaxT];                   // per row r, bits 3r..3r+2: row used, left box, right box
     uint16_t tself[kMaxT];                  // staged index of each target (kNoTarget: static)
+    uint32_t tidx[kMaxT];                   // agent index of each target
     uint16_t tmap[kStage];                  // target of each staged agent (kNoTarget: halo or static)
     uint8_t tbox[kMaxT];                    // core box of each target
 };
@@ -554,6 +555,8 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
         }
         // ---- targets: static skip (Sec 5.5), staged index, core box, zero accumulators
         int active = 0, anystat = 0;
+        uint32_t ti[2] = {0u, 0u};  // agent indices, written to LDS after the stage (their loads overlap it)
+        static_assert(kMaxT <= 512, "at most two targets per thread");
         for (uint32_t t = tid; t < nt; t += blockDim.x) {
             int c = 0, hi = kCore;
             while (hi - c > 1) {
@@ -564,9 +567,11 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             core_box_coords(c, cx, cy, cz);
             const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
             const uint32_t k = t - L.coff[c];
+            const uint32_t ia = d.sorted_idx[L.gsrc[lb] + k];
+            ti[t < 256u ? 0 : 1] = ia;
             bool stat = false;
             if (S.detect_static) {
-                const int64_t i = d.sorted_idx[L.gsrc[lb] + k];
+                const int64_t i = ia;
                 const uint8_t fl = d.flags[lp][i];
                 if (fl & kStatic) {
                     skip_static<DIAG>(d, i, P, lp, fl,
@@ -607,6 +612,8 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             }
             L.tmap[k] = tm;
         }
+        if ((uint32_t)tid < nt) L.tidx[tid] = ti[0];
+        if ((uint32_t)tid + 256u < nt) L.tidx[tid + 256] = ti[1];
         __syncthreads();
         // ---- setup: rows within reach of every active target (at most two per
         // thread), task counts per row length; the length bucket of every row
@@ -735,8 +742,7 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
             const int c = L.tbox[t];
             int cx, cy, cz;
             core_box_coords(c, cx, cy, cz);
-            const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
-            const int64_t i = d.sorted_idx[L.gsrc[lb] + (t - L.coff[c])];
+            const int64_t i = L.tidx[t];
             const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
             const unsigned long long acm = L.acm[t];
             const uint32_t ac = (uint32_t)acm;
@@ -753,7 +759,8 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
                 } else {
                     const int nzc = nz_min + nz_unc;
                     const uint8_t fl = d.flags[lp][i];
-                    const uint32_t m = box_rank(d, S, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz);
+                    // box slot: the unit's block has Morton rank u - wblk_begin (its blist entry)
+                    const uint32_t m = (uint32_t)(u - d.wblk_begin[s]) * 64u + local_morton(cx, cy, cz);
                     commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
                                        fz, nzc, DIAG ? (int)L.anbr[t] : 0, nzc, m, lin);
                 }
