@@ -249,8 +249,10 @@ __global__ void __launch_bounds__(256) k_bin(Dev d) {
 
 // ------------------------------------------------------------------ segmented scan
 // Exclusive scan of per-box counts (Morton-rank order) into slot starts.
-__global__ void __launch_bounds__(256) k_scan_tiles(Dev d) {
-    if (ABM_ABORTED(d)) return;
+// The scan kernels serve the grid build (resort = 0) and the Morton re-sort
+// (resort = 1: they do nothing in iterations without a re-sort).
+__global__ void __launch_bounds__(256) k_scan_tiles(Dev d, int resort) {
+    if (ABM_ABORTED(d) || (resort && !d.ctl->resort_now)) return;
     __shared__ uint32_t sh[4];
     const int64_t total = d.ctl->total_btiles;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
@@ -294,14 +296,14 @@ __device__ inline void scan_tile_sums(const Dev &d, const int64_t *begin) {
     }
 }
 
-__global__ void __launch_bounds__(1024) k_scan_top(Dev d) {
-    if (ABM_ABORTED(d)) return;
+__global__ void __launch_bounds__(1024) k_scan_top(Dev d, int resort) {
+    if (ABM_ABORTED(d) || (resort && !d.ctl->resort_now)) return;
     scan_tile_sums(d, d.btile_begin);
 }
 
 // box_start[sb_off + m] = a_off + prefix; zeroes the counts.
-__global__ void __launch_bounds__(256) k_scan_apply(Dev d) {
-    if (ABM_ABORTED(d)) return;
+__global__ void __launch_bounds__(256) k_scan_apply(Dev d, int resort) {
+    if (ABM_ABORTED(d) || (resort && !d.ctl->resort_now)) return;
     __shared__ uint32_t sh[4];
     const int64_t total = d.ctl->total_btiles;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
@@ -356,44 +358,58 @@ __global__ void __launch_bounds__(256) k_scatter(Dev d) {
 // being static when a changed agent (including a new daughter) lies within
 // the previous iteration's radius of it (Sec 5.5).  Boxes holding a changed
 // agent were marked by k_bin.
+// One wave per aligned block; only blocks next to an arrival can lose a
+// static flag (or every block, when the box length shrank).
 __global__ void __launch_bounds__(256) k_static_fix(Dev d) {
     if (ABM_ABORTED(d)) return;
+    constexpr int kTB = kBoxTile / 64;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
+    const int64_t nq = d.ctl->total_btiles * kTB;
+    const int lane = threadIdx.x & 63;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nq; q += (int64_t)gridDim.x * 4) {
+        const int64_t t = q / kTB;
+        int s = find_sim(d.btile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
         if (!S.detect_static) continue;
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n_start) continue;
-        int64_t i = S.a_off + loc;
-        uint8_t fl = d.flags[lp][i];
-        if (!(fl & kStatic)) continue;
-        bool st = S.L >= S.L_prev;  // a shrunken grid cannot cover the old radius: be conservative
-        int bx, by, bz;
-        unpack_key(d.key[i], bx, by, bz);
-        if (st && d.near_blk[S.b_off + (box_rank(d, S, bx, by, bz) >> 6)]) {
-            const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
-            const double L2 = S.L_prev * S.L_prev;
-            for (int oz = -1; oz <= 1 && st; ++oz)
-                for (int oy = -1; oy <= 1 && st; ++oy)
-                    for (int ox = -1; ox <= 1 && st; ++ox) {
-                        int cx = bx + ox, cy = by + oy, cz = bz + oz;
-                        if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2]) continue;
-                        uint32_t m = box_rank(d, S, cx, cy, cz);
-                        if (!d.arrive[S.b_off + m]) continue;
-                        uint32_t s0 = d.box_start[S.sb_off + m], s1 = d.box_start[S.sb_off + m + 1];
-                        for (uint32_t slot = s0; slot < s1 && st; ++slot) {
-                            int64_t j = d.sorted_idx[slot];
-                            if (j == i || !(d.flags[lp][j] & kChgMask)) continue;
-                            if (near_point(x, y, z, d.pos[P][j], d.pos[P][A + j], d.pos[P][2 * A + j], L2)) st = false;
+        const int64_t blk = (t - d.btile_begin[s]) * kTB + q % kTB;
+        if (blk >= S.nblocks) continue;
+        const bool shrunk = !(S.L >= S.L_prev);  // a shrunken grid cannot cover the old radius: be conservative
+        if (!shrunk && !d.near_blk[S.b_off + blk]) continue;
+        const uint32_t s0 = d.box_start[S.sb_off + blk * 64], s1 = d.box_start[S.sb_off + blk * 64 + 64];
+        for (uint32_t slot0 = s0; slot0 < s1; slot0 += 64) {
+            const uint32_t slot = slot0 + (uint32_t)lane;
+            if (slot >= s1) continue;
+            const int64_t i = d.sorted_idx[slot];
+            const uint8_t fl = d.flags[lp][i];
+            if (!(fl & kStatic)) continue;
+            bool st = !shrunk;
+            int bx, by, bz;
+            unpack_key(d.key[i], bx, by, bz);
+            if (st) {
+                const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
+                const double L2 = S.L_prev * S.L_prev;
+                for (int oz = -1; oz <= 1 && st; ++oz)
+                    for (int oy = -1; oy <= 1 && st; ++oy)
+                        for (int ox = -1; ox <= 1 && st; ++ox) {
+                            int cx = bx + ox, cy = by + oy, cz = bz + oz;
+                            if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2])
+                                continue;
+                            uint32_t m = box_rank(d, S, cx, cy, cz);
+                            if (!d.arrive[S.b_off + m]) continue;
+                            uint32_t b0 = d.box_start[S.sb_off + m], b1 = d.box_start[S.sb_off + m + 1];
+                            for (uint32_t sl = b0; sl < b1 && st; ++sl) {
+                                int64_t j = d.sorted_idx[sl];
+                                if (j == i || !(d.flags[lp][j] & kChgMask)) continue;
+                                if (near_point(x, y, z, d.pos[P][j], d.pos[P][A + j], d.pos[P][2 * A + j], L2))
+                                    st = false;
+                            }
                         }
-                    }
-        }
-        if (!st) {
-            d.flags[lp][i] = fl & ~kStatic;
-            d.active_blk[S.b_off + (box_rank(d, S, bx, by, bz) >> 6)] = 1;
+            }
+            if (!st) {
+                d.flags[lp][i] = fl & ~kStatic;
+                d.active_blk[S.b_off + blk] = 1;
+            }
         }
     }
 }
@@ -403,13 +419,17 @@ __global__ void __launch_bounds__(256) k_static_fix(Dev d) {
 // one box of it.  One thread per block (block tiles of 16 blocks).
 __global__ void __launch_bounds__(256) k_near_marks(Dev d, int arrivals) {
     if (ABM_ABORTED(d)) return;
+    constexpr int kTB = kBoxTile / 64;  // aligned blocks per box tile
     const int64_t total = d.ctl->total_btiles;
     const uint8_t *marks = arrivals ? d.arrive_blk : d.dirty_blk;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    // one thread per aligned block: 256 / kTB box tiles per pass of a thread block
+    for (int64_t t0 = (int64_t)blockIdx.x * (256 / kTB); t0 < total; t0 += (int64_t)gridDim.x * (256 / kTB)) {
+        const int64_t t = t0 + threadIdx.x / kTB;
+        if (t >= total) continue;
         int s = find_sim(d.btile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
-        if (!S.detect_static || threadIdx.x >= kBoxTile / 64) continue;
-        const int64_t blk = (t - d.btile_begin[s]) * (kBoxTile / 64) + threadIdx.x;
+        if (!S.detect_static) continue;
+        const int64_t blk = (t - d.btile_begin[s]) * kTB + threadIdx.x % kTB;
         if (blk >= S.nblocks) continue;
         int qx, qy, qz;
         unpack_key(d.blist[S.b_off + blk], qx, qy, qz);
@@ -734,9 +754,9 @@ void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_b
     hipLaunchKernelGGL(k_brank, dim3(grid_boxes), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_grid_done, dim3(1), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_bin, dim3(grid_agents), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d);
-    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d, 0);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d, 0);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d, 0);
     hipLaunchKernelGGL(k_scatter, dim3(grid_agents), dim3(256), 0, st, d);
     if (any_static) {
         launch_near_marks(d, st, grid_boxes, true);
@@ -747,9 +767,9 @@ void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_b
 void launch_resort(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool force, bool any_static) {
     if (force) hipLaunchKernelGGL(k_force_resort, dim3(1), dim3(64), 0, st, d);
     hipLaunchKernelGGL(k_rs_count, dim3(grid_agents), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d);
-    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d, 1);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d, 1);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d, 1);
     hipLaunchKernelGGL(k_rs_dest, dim3(grid_agents), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_rs_move, dim3(grid_agents), dim3(256), 0, st, d);
     if (any_static) hipLaunchKernelGGL(k_rs_sync, dim3(grid_agents), dim3(256), 0, st, d);

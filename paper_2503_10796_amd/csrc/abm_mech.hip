@@ -1173,44 +1173,60 @@ __global__ void __launch_bounds__(256) k_div_apply(Dev d) {
 // 27-box neighbourhood are checked (boxes marked dirty prune the search);
 // changed agents that arrive from farther away are caught by k_static_fix on
 // the next grid.
+// One wave per aligned block.  A block with no active agent and no changed
+// agent within one box keeps the flags of its agents: they stay static.
 __global__ void __launch_bounds__(256) k_static(Dev d) {
     if (ABM_ABORTED(d)) return;
+    constexpr int kTB = kBoxTile / 64;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
-    const int64_t total = d.ctl->total_tiles;  // tiles over n_start (daughters are new: never static)
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
+    const int64_t nq = d.ctl->total_btiles * kTB;
+    const int lane = threadIdx.x & 63;
+    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nq; q += (int64_t)gridDim.x * 4) {
+        const int64_t t = q / kTB;
+        int s = find_sim(d.btile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
         if (!S.detect_static) continue;
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        if (loc >= S.n_start) continue;
-        int64_t i = S.a_off + loc;
-        uint8_t fl = d.flags[lp][i];
-        bool st = !(fl & kChgMask) && d.nz[lp][i] <= 1;
-        int bx, by, bz;
-        unpack_key(d.key[i], bx, by, bz);
-        if (st && d.near_blk[S.b_off + (box_rank(d, S, bx, by, bz) >> 6)]) {
-            const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
-            const double L2 = S.L * S.L;
-            for (int oz = -1; oz <= 1 && st; ++oz)
-                for (int oy = -1; oy <= 1 && st; ++oy)
-                    for (int ox = -1; ox <= 1 && st; ++ox) {
-                        int cx = bx + ox, cy = by + oy, cz = bz + oz;
-                        if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2]) continue;
-                        uint32_t m = box_rank(d, S, cx, cy, cz);
-                        if (!d.dirty[S.b_off + m]) continue;
-                        uint32_t s0 = d.box_start[S.sb_off + m], s1 = d.box_start[S.sb_off + m + 1];
-                        for (uint32_t slot = s0; slot < s1 && st; ++slot) {
-                            int64_t j = d.sorted_idx[slot];
-                            if (j == i || !(d.flags[lp][j] & kChgMask)) continue;
-                            // start position (buffer P) and committed position (buffer 1-P)
-                            if (near_point(x, y, z, d.pos[P][j], d.pos[P][A + j], d.pos[P][2 * A + j], L2) ||
-                                near_point(x, y, z, d.pos[1 - P][j], d.pos[1 - P][A + j], d.pos[1 - P][2 * A + j], L2))
-                                st = false;
+        const int64_t blk = (t - d.btile_begin[s]) * kTB + q % kTB;
+        if (blk >= S.nblocks) continue;
+        const bool near = d.near_blk[S.b_off + blk] != 0;
+        if (!near && !d.active_blk[S.b_off + blk]) continue;
+        // the agents binned at the start of the iteration (daughters are new: never static)
+        const uint32_t s0 = d.box_start[S.sb_off + blk * 64], s1 = d.box_start[S.sb_off + blk * 64 + 64];
+        for (uint32_t slot0 = s0; slot0 < s1; slot0 += 64) {
+            const uint32_t slot = slot0 + (uint32_t)lane;
+            if (slot >= s1) continue;
+            const int64_t i = d.sorted_idx[slot];
+            const uint8_t fl = d.flags[lp][i];
+            bool st = !(fl & kChgMask) && d.nz[lp][i] <= 1;
+            if (st && near) {
+                int bx, by, bz;
+                unpack_key(d.key[i], bx, by, bz);
+                const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
+                const double L2 = S.L * S.L;
+                for (int oz = -1; oz <= 1 && st; ++oz)
+                    for (int oy = -1; oy <= 1 && st; ++oy)
+                        for (int ox = -1; ox <= 1 && st; ++ox) {
+                            int cx = bx + ox, cy = by + oy, cz = bz + oz;
+                            if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2])
+                                continue;
+                            uint32_t m = box_rank(d, S, cx, cy, cz);
+                            if (!d.dirty[S.b_off + m]) continue;
+                            uint32_t b0 = d.box_start[S.sb_off + m], b1 = d.box_start[S.sb_off + m + 1];
+                            for (uint32_t sl = b0; sl < b1 && st; ++sl) {
+                                int64_t j = d.sorted_idx[sl];
+                                if (j == i || !(d.flags[lp][j] & kChgMask)) continue;
+                                // start position (buffer P) and committed position (buffer 1-P)
+                                if (near_point(x, y, z, d.pos[P][j], d.pos[P][A + j], d.pos[P][2 * A + j], L2) ||
+                                    near_point(x, y, z, d.pos[1 - P][j], d.pos[1 - P][A + j], d.pos[1 - P][2 * A + j],
+                                               L2))
+                                    st = false;
+                            }
                         }
-                    }
+            }
+            const uint8_t nf = st ? (fl | kStatic) : (fl & ~kStatic);
+            if (nf != fl) d.flags[lp][i] = nf;
         }
-        d.flags[lp][i] = st ? (fl | kStatic) : (fl & ~kStatic);
     }
 }
 
@@ -1237,7 +1253,7 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
     }
     if (any_static) {
         launch_near_marks(d, st, grid_boxes, false);
-        hipLaunchKernelGGL(k_static, dim3(grid_agents), dim3(256), 0, st, d);
+        hipLaunchKernelGGL(k_static, dim3(grid_boxes), dim3(256), 0, st, d);
     }
     launch_end(d, st, grid_boxes, any_static);
     if (resort) launch_resort(d, st, grid_agents, grid_boxes, false, any_static);
