@@ -241,7 +241,7 @@ static int capture(abm_batch *b, int part, int diag) {
         launch_iteration(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, b->sweep_grid, diag != 0, b->any_growth,
                          b->any_static, resort);
     else if (part == 1)
-        launch_sweep(b->d, b->cap_stream, b->sweep_grid, diag != 0);
+        launch_sweep(b->d, b->cap_stream, b->sweep_grid, diag != 0, b->any_static);
     else
         launch_after_sweep(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, diag != 0, b->any_growth, b->any_static,
                            resort);

@@ -169,7 +169,7 @@ int set_error(int code, const char *msg);
 void launch_iteration(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, int sweep_grid, bool diag,
                       bool any_growth, bool any_static, bool resort);
 void launch_grid_build(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool any_static);
-void launch_sweep(const Dev &d, hipStream_t s, int sweep_grid, bool diag);
+void launch_sweep(const Dev &d, hipStream_t s, int sweep_grid, bool diag, bool any_static);
 void launch_after_sweep(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool diag, bool any_growth,
                         bool any_static, bool resort);
 void launch_resort(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool force, bool any_static);

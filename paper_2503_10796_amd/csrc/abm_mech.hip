@@ -157,6 +157,7 @@ struct SweepLds {
     uint32_t queue[4][kQueue];
     uint32_t sh[4];
     uint32_t ntask;
+    unsigned long long ahead[2][4];         // look-ahead over units: active-unit ballots of the 4 waves
     uint16_t task[kRows * kMaxT];           // target << 4 | row, sorted by length (longest first)
     uint32_t trow[kMaxT];                   // per row r, bits 3r..3r+2: row used, left box, right box
     uint16_t tself[kMaxT];                  // staged index of each target (kNoTarget: static)
@@ -482,7 +483,7 @@ __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> 
 }
 
 template <bool DIAG>
-__global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: at most 128 VGPRs
+__global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 blocks per CU: at most 128 VGPRs
     __shared__ SweepLds<DIAG> L;
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
@@ -496,7 +497,38 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d) {  // 4 blocks per CU: 
     const int64_t per_xcd = (int64_t)(gridDim.x >> 3);
     const int64_t chunk = ceil_div(U, 8);
     const int64_t u_end = (xcd + 1) * chunk < U ? (xcd + 1) * chunk : U;
+    int par = 0;
     for (int64_t u = xcd * chunk + (blockIdx.x >> 3); u < u_end; u += per_xcd) {
+        if (!DIAG && lookahead) {
+            // with static detection most units may have no active agent: the
+            // 256 threads test the next 256 units of this block at once and
+            // jump to the first active one
+            for (;;) {
+                const int64_t uu = u + (int64_t)tid * per_xcd;
+                bool act = false;
+                if (uu < u_end) {
+                    const int s2 = find_sim(d.wblk_begin, d.n_sims, uu);
+                    const SimDesc &S2 = d.sims[s2];
+                    act = !S2.detect_static || d.active_blk[S2.b_off + (uu - d.wblk_begin[s2])] != 0;
+                }
+                const uint64_t am = __builtin_amdgcn_ballot_w64(act);
+                if (lane == 0) L.ahead[par][w] = am;
+                __syncthreads();  // (two buffers: the next pass writes the other one)
+                int first = -1;
+                for (int v = 0; v < 4 && first < 0; ++v) {
+                    const uint64_t mv = L.ahead[par][v];
+                    if (mv) first = v * 64 + __ffsll((long long)mv) - 1;
+                }
+                par ^= 1;
+                if (first >= 0) {
+                    u += (int64_t)first * per_xcd;
+                    break;
+                }
+                u += 256 * per_xcd;
+                if (u >= u_end) break;
+            }
+            if (u >= u_end) break;
+        }
         const int s = find_sim(d.wblk_begin, d.n_sims, u);
         const SimDesc &S = d.sims[s];
         // with static detection, a block whose agents are all static and
@@ -1231,9 +1263,9 @@ __global__ void __launch_bounds__(256) k_static(Dev d) {
 }
 
 // ------------------------------------------------------------------ launchers
-void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag) {
-    if (diag) hipLaunchKernelGGL(k_sweep<true>, dim3(sweep_grid), dim3(256), 0, st, d);
-    else hipLaunchKernelGGL(k_sweep<false>, dim3(sweep_grid), dim3(256), 0, st, d);
+void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag, bool any_static) {
+    if (diag) hipLaunchKernelGGL(k_sweep<true>, dim3(sweep_grid), dim3(256), 0, st, d, 0);
+    else hipLaunchKernelGGL(k_sweep<false>, dim3(sweep_grid), dim3(256), 0, st, d, any_static ? 1 : 0);
 }
 
 // Everything of one iteration after the sweep; ends by building the grid of
@@ -1263,7 +1295,7 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
 // One iteration on the grid built at the end of the previous one.
 void launch_iteration(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, int sweep_grid, bool diag,
                       bool any_growth, bool any_static, bool resort) {
-    launch_sweep(d, st, sweep_grid, diag);
+    launch_sweep(d, st, sweep_grid, diag, any_static);
     launch_after_sweep(d, st, grid_agents, grid_boxes, diag, any_growth, any_static, resort);
 }
 
