@@ -28,7 +28,7 @@ constexpr double kFixUnit = 0x1.0p-40;
 constexpr int kHalo = kBlk + 2;              // 6
 constexpr int kNb = kHalo * kHalo * kHalo;   // 216 staged boxes
 constexpr int kCore = kBlk * kBlk * kBlk;    // 64 target boxes
-constexpr int kStage = 960;                  // staged agents (15 KB of float4)
+constexpr int kStage = 928;                  // staged agents (14.5 KB of float4)
 static_assert(kStage >= 4 * 64, "the dense path uses 64 staged entries per wave of a 256-thread block");
 
 __device__ inline unsigned long long fixbits(double v) { return (unsigned long long)__double_as_longlong(v); }
@@ -135,6 +135,7 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
 // path that reads the payload from global memory.
 constexpr int kMaxT = 280;      // targets per unit on the LDS path (mean 216 at 1 agent per 1000 um^3)
 constexpr int kRows = 10;       // tasks per target: nine rows, the own row's left halo box apart
+constexpr int kTaskCap = 2048;  // tasks per unit on the LDS path (about 7.5 per target)
 constexpr int kBuckets = 64;    // task lengths 1..63, longer rows share the last bucket
 constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 20 | target's staged
                                 // index << 10 | candidate's staged index)
@@ -158,15 +159,15 @@ struct SweepLds {
     uint32_t sh[4];
     uint32_t ntask;
     unsigned long long ahead[2][4];         // look-ahead over units: active-unit ballots of the 4 waves
-    uint16_t task[kRows * kMaxT];           // target << 4 | row, sorted by length (longest first)
-    uint32_t trow[kMaxT];                   // per row r, bits 3r..3r+2: row used, left box, right box
+    uint32_t task[kTaskCap];                // target | first candidate << 9 | candidates << 19,
+                                            // sorted by length (longest first)
     uint16_t tself[kMaxT];                  // staged index of each target (kNoTarget: static)
     uint32_t tidx[kMaxT];                   // agent index of each target
     uint16_t tmap[kStage];                  // target of each staged agent (kNoTarget: halo or static)
     uint8_t tbox[kMaxT];                    // core box of each target
 };
 static_assert(sizeof(SweepLds<false>) <= 40960, "four blocks of 256 threads per CU");
-static_assert(kStage < 1024 && kMaxT < 512, "queue entries: 9-bit target, 10-bit staged indices");
+static_assert(kStage < 1024 && kMaxT < 512, "queue and task entries: 9-bit target, 10-bit staged indices");
 
 // Per-target accumulator of the global-memory path.
 struct Acc {
@@ -647,34 +648,34 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
         if ((uint32_t)tid < nt) L.tidx[tid] = ti[0];
         if ((uint32_t)tid + 256u < nt) L.tidx[tid + 256] = ti[1];
         __syncthreads();
-        // ---- setup: rows within reach of every active target (at most two per
-        // thread), task counts per row length; the length bucket of every row
-        // (6 bits each) stays in registers for the task scatter
-        static_assert(kMaxT <= 512 && kBuckets == 64 && kRows <= 10, "two targets per thread, 6-bit buckets");
-        unsigned long long bk[2] = {0ull, 0ull};
+        // ---- setup: candidate ranges of every active target (at most two per
+        // thread), task counts per length; the ranges stay in registers for
+        // the task scatter
+        static_assert(kMaxT <= 512, "two targets per thread");
+        uint32_t rw[2][kRows];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t t = (uint32_t)tid + 256u * (uint32_t)h;
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) rw[h][r] = 0u;
             if (t >= nt) continue;
             const uint32_t self = L.tself[t];
             if (self == kNoTarget) continue;
             int cx, cy, cz;
             core_box_coords(L.tbox[t], cx, cy, cz);
             const uint32_t rows = row_mask<DIAG>(L.sp[self], cx, cy, cz, Lf, reach_add);
-            L.trow[t] = rows;
-            unsigned long long b = 0;
 #pragma unroll
             for (int r = 0; r < kRows; ++r) {
                 uint32_t b0, len;
                 task_range<DIAG>(L, rows, cx, cy, cz, r, n3, self, b0, len);
-                const uint32_t bu = len < kBuckets ? len : kBuckets - 1;
-                if (bu) atomicAdd(&L.bcnt[bu], 1u);
-                b |= (unsigned long long)bu << (6 * r);
+                if (len) {
+                    atomicAdd(&L.bcnt[len < kBuckets ? len : kBuckets - 1], 1u);
+                    rw[h][r] = (b0 << 9) | (len << 19);
+                }
             }
-            bk[h] = b;
         }
         __syncthreads();
-        if (tid < 64) {  // bucket offsets, longest rows first (one wave)
+        if (tid < 64) {  // bucket offsets, longest tasks first (one wave)
             const uint32_t b = kBuckets - 1 - tid;
             const uint32_t cc = L.bcnt[b];
             uint32_t x = cc;
@@ -686,15 +687,20 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
             if (tid == 63) L.ntask = x;
         }
         __syncthreads();
+        if (L.ntask > (uint32_t)kTaskCap) {  // rare: more tasks than the list holds
+            sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            __syncthreads();  // the next unit reuses the LDS tables
+            continue;
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const uint32_t t = (uint32_t)tid + 256u * (uint32_t)h;
 #pragma unroll
             for (int r = 0; r < kRows; ++r) {
-                const uint32_t bu = (uint32_t)(bk[h] >> (6 * r)) & 63u;
-                if (bu) {
-                    const uint32_t p = atomicAdd(&L.boff[bu], 1u);
-                    L.task[p] = (uint16_t)((t << 4) | (uint32_t)r);
+                const uint32_t len = rw[h][r] >> 19;
+                if (len) {
+                    const uint32_t p = atomicAdd(&L.boff[len < kBuckets ? len : kBuckets - 1], 1u);
+                    L.task[p] = rw[h][r] | t;
                 }
             }
         }
@@ -708,13 +714,10 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
                 const uint32_t j = c0 + lane;
                 const bool tv = j < ntask;
                 const uint32_t tk = L.task[tv ? j : c0];
-                const uint32_t t = tk >> 4;
-                int cx, cy, cz;
-                core_box_coords(L.tbox[t], cx, cy, cz);
+                const uint32_t t = tk & 511u;
+                const uint32_t b0 = (tk >> 9) & 1023u;
+                const uint32_t len = tv ? tk >> 19 : 0u;
                 const uint32_t self = L.tself[t];
-                uint32_t b0, len;
-                task_range<DIAG>(L, L.trow[t], cx, cy, cz, (int)(tk & 15u), n3, self, b0, len);
-                if (!tv) len = 0;
                 const float4 own = L.sp[self];
                 const float owg = own.w + g;
                 const uint32_t tq = (t << 20) | (self << 10) | b0;  // + kk: b0 + kk < kStage
