@@ -402,6 +402,158 @@ __device__ inline void acc_reduce_streams(Acc &a, int g) {
 // streams interleaved; the exact fixed-point sums of a target's streams are
 // then added across lanes.  Payload is read from global memory in coalesced
 // chunks of 64 candidates staged in the wave's slice of the LDS stage.
+// Drain of the box-wise path: lane l takes queue entry l (target lane | candidate
+// index in the staged chunk << 6) and adds the pair's contact force and counts
+// to the target's LDS accumulators (force x, y, z; counts | error bound << 32).
+__device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const float4 *ob, const float4 *buf,
+                                   unsigned long long *acc, float ox, float oy, float oz, float e, float g, float kf,
+                                   float gf, float L2m, float L2p) {
+    const uint32_t lane = threadIdx.x & 63;
+    const bool valid = lane < cnt;
+    const uint32_t ent = valid ? qw[lane] : 0u;
+    const uint32_t tl = ent & 63u, j = ent >> 6;
+    const float4 own = ob[tl];
+    const float4 c = buf[j];
+    // the target's coordinates in the candidate box's frame, as in pair_fp32
+    const float ddx = (own.x - ox) - c.x, ddy = (own.y - oy) - c.y, ddz = (own.z - oz) - c.z;
+    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+    const PairOut o = pair_math(ddx, ddy, ddz, d2, own.w, c.w, e, g, kf, gf, L2m, L2p, valid);
+    if (o.contact) {
+        const double f = (double)o.f;
+        const unsigned long long mb = fixbits(kFixMagic);
+        atomicAdd(&acc[4 * tl], fixbits(fma(f, (double)ddx, kFixMagic)) - mb);
+        atomicAdd(&acc[4 * tl + 1], fixbits(fma(f, (double)ddy, kFixMagic)) - mb);
+        atomicAdd(&acc[4 * tl + 2], fixbits(fma(f, (double)ddz, kFixMagic)) - mb);
+        atomicAdd(&acc[4 * tl + 3], (o.nz_unc ? kNzUncOne : 1ull) |
+                                        ((unsigned long long)(uint32_t)ceilf(o.ep * 0x1.0p26f) << 32));
+    }
+    if (o.unc) atomicOr(&acc[4 * tl + 3], kUncBit);
+}
+
+// Box-wise path of the production sweep.  As in sweep_unit_dense, each wave
+// takes one core box at a time with (target, stream) lanes over the box's
+// 27-box candidates, staged 64 at a time in the wave's LDS slice.  Each lane
+// only tests the pair against its contact reach; survivors go to a per-wave
+// queue and the contact math runs on full 64-pair drains (and on the rest at
+// the end of each staged chunk), with exact fixed-point LDS accumulators per
+// target.  The LDS tables of the unit path are free here.
+__device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<false> &L, int P, int lp, int qx, int qy,
+                                   int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
+    static_assert(kStage >= 512 && sizeof(L.task) >= 4 * 64 * 4 * sizeof(unsigned long long),
+                  "per wave: 64 staged candidates and 64 targets in the stage, 64 accumulators in the task list");
+    const int64_t A = d.A;
+    const float Lf = (float)S.L;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float4 *buf = L.sp + 64 * w;                // staged candidates
+    float4 *ob = L.sp + 256 + 64 * w;           // the targets of the pass
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(L.task) + 256 * w;
+    uint32_t *qw = L.queue[w];
+    for (int c = w; c < kCore; c += blockDim.x >> 6) {
+        int cx, cy, cz;
+        core_box_coords(c, cx, cy, cz);
+        const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
+        const uint32_t cnt = L.sbeg[lb + 1] - L.sbeg[lb];
+        if (cnt == 0) continue;
+        const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
+        for (uint32_t p0 = 0; p0 < cnt;) {
+            int gsz = 1;
+            while (gsz < 64 && (uint32_t)gsz < cnt - p0) gsz <<= 1;
+            const int nstream = 64 / gsz;
+            const int tl = lane & (gsz - 1), sid = lane / gsz;
+            const uint32_t k = p0 + (uint32_t)tl;
+            const bool tv = k < cnt;
+            const uint32_t slot = L.gsrc[lb] + (tv ? k : 0u);
+            const int64_t i = d.sorted_idx[slot];
+            const uint8_t fl = d.flags[lp][i];
+            const bool stat = tv && S.detect_static && (fl & kStatic);
+            const bool act = tv && !stat;
+            if (stat && sid == 0) skip_static<false>(d, i, P, lp, fl, lin);
+            const float4 own = d.payload[slot];
+            __builtin_amdgcn_wave_barrier();
+            if (sid == 0) {
+                ob[tl] = own;
+                acc[4 * tl] = 0;
+                acc[4 * tl + 1] = 0;
+                acc[4 * tl + 2] = 0;
+                acc[4 * tl + 3] = 0;
+            }
+            __builtin_amdgcn_wave_barrier();
+            const float owg = own.w + g;
+            uint32_t qn = 0;  // wave-uniform queue fill
+            for (int oz = -1; oz <= 1; ++oz)
+                for (int oy = -1; oy <= 1; ++oy) {
+                    const int row = cx + kHalo * ((cy + 1 + oy) + kHalo * (cz + 1 + oz));
+                    const float fy = (float)oy * Lf, fz = (float)oz * Lf;
+                    const float qy2 = own.y - fy, qz2 = own.z - fz;
+                    for (int ox = -1; ox <= 1; ++ox) {
+                        const int lbb = row + ox + 1;
+                        const float fx = (float)ox * Lf;
+                        const float qx2 = own.x - fx;
+                        const uint32_t b0 = L.gsrc[lbb], nn = L.sbeg[lbb + 1] - L.sbeg[lbb];
+                        for (uint32_t c0 = 0; c0 < nn; c0 += 64) {
+                            const uint32_t mc = nn - c0 < 64u ? nn - c0 : 64u;
+                            __builtin_amdgcn_wave_barrier();
+                            if ((uint32_t)lane < mc) buf[lane] = d.payload[b0 + c0 + (uint32_t)lane];
+                            __builtin_amdgcn_wave_barrier();
+                            for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
+                                const uint32_t j = j0 + (uint32_t)sid;
+                                const bool in = j < mc && act && b0 + c0 + j != slot;
+                                const float4 cc = buf[j < mc ? j : 0u];
+                                const float ddx = qx2 - cc.x, ddy = qy2 - cc.y, ddz = qz2 - cc.z;
+                                const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                                const float sg = owg + cc.w;  // the reach test of pair_math
+                                const bool hit = in && d2 < sg * sg;
+                                const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                                if (m) {
+                                    if (hit)
+                                        qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                                            (uint32_t)tl | (j << 6);
+                                    qn += (uint32_t)__popcll(m);
+                                    if (qn >= 64) {
+                                        __builtin_amdgcn_wave_barrier();
+                                        drain_dense(qw, 64u, ob, buf, acc, fx, fy, fz, e, g, kf, gf, L2m, L2p);
+                                        __builtin_amdgcn_wave_barrier();
+                                        qn -= 64;
+                                        if ((uint32_t)lane < qn) qw[lane] = qw[64 + lane];
+                                        __builtin_amdgcn_wave_barrier();
+                                    }
+                                }
+                            }
+                            if (qn) {  // the chunk is restaged next: drain the rest now
+                                __builtin_amdgcn_wave_barrier();
+                                drain_dense(qw, qn, ob, buf, acc, fx, fy, fz, e, g, kf, gf, L2m, L2p);
+                                qn = 0;
+                            }
+                        }
+                    }
+                }
+            __builtin_amdgcn_wave_barrier();
+            p0 += (uint32_t)gsz;
+            if (!act || sid != 0) continue;
+            const unsigned long long am = acc[4 * tl + 3];
+            const uint32_t ac = (uint32_t)am;
+            const int nz_min = (int)(ac & 0xffffu), nz_unc = (int)((ac >> 16) & 0x7fffu);
+            bool unc = (ac & (uint32_t)kUncBit) != 0 || !nz_decided(S, nz_min, nz_unc);
+            if (!unc) {
+                const double fx = (double)(long long)acc[4 * tl] * kFixUnit;
+                const double fy = (double)(long long)acc[4 * tl + 1] * kFixUnit;
+                const double fz = (double)(long long)acc[4 * tl + 2] * kFixUnit;
+                const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
+                const double ebound = (double)(uint32_t)(am >> 32) * 0x1.0p-26 + 1e-9;
+                if (fabs(fnorm - S.adherence) <= ebound) {
+                    unc = true;
+                } else {
+                    const uint32_t m = box_rank(d, S, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz);
+                    commit_agent<false>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
+                                        fz, nz_min + nz_unc, 0, nz_min + nz_unc, m, lin);
+                }
+            }
+            if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
+        }
+    }
+}
+
 template <bool DIAG>
 __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> &L, int P, int lp, int qx, int qy,
                                  int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
@@ -582,7 +734,8 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
         const float reach_add = (float)S.rmax + g + (float)ldexp(S.L, -10);
         const bool lds_path = total <= (uint32_t)kStage && nt <= (uint32_t)kMaxT;
         if (!lds_path) {
-            sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            if constexpr (DIAG) sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            else sweep_unit_dense_q(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
         }
@@ -688,7 +841,8 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
         }
         __syncthreads();
         if (L.ntask > (uint32_t)kTaskCap) {  // rare: more tasks than the list holds
-            sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            if constexpr (DIAG) sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            else sweep_unit_dense_q(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
         }
