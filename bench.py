@@ -145,9 +145,12 @@ def bench_sweep(args):
         f"{int(counts[:, 0].sum())} agents at the start, {int(counts[:, -1].sum())} at the end")
     _, t_batch, n_end, grid = sweep.run_batched(cfg, record=False, tune=True, log=log)
     assert np.array_equal(n_end, counts[:, -1].astype(np.int64)), "agent counts differ from the lineage count"
-    secs = sweep.run_per_sim(cfg, list(range(cfg.n_sims)))
-    t_single = float(secs.sum())
-    log(f"[bench] per-simulation path: {t_single:.3f} s for {cfg.n_sims} simulations")
+    if args.batched_only:
+        t_single = float("nan")
+    else:
+        secs = sweep.run_per_sim(cfg, list(range(cfg.n_sims)))
+        t_single = float(secs.sum())
+        log(f"[bench] per-simulation path: {t_single:.3f} s for {cfg.n_sims} simulations")
     out = {
         "metric": "batched parameter sweep: agent updates/s, speedup over the per-simulation path",
         "value": updates / t_batch, "unit": "agent updates/s", "n_gpus": 1, "steps": cfg.iters, "warmup": 1,
@@ -158,7 +161,8 @@ def bench_sweep(args):
                                f"log-uniform [1e3,5e4]; {cfg.iters} iterations",
                    "agents_start": int(counts[:, 0].sum()), "agents_end": int(counts[:, -1].sum()),
                    "sweep_workgroups": grid},
-        "batched_s": t_batch, "per_simulation_s": t_single, "speedup_vs_per_simulation": t_single / t_batch,
+        "batched_s": t_batch, "per_simulation_s": None if args.batched_only else t_single,
+        "speedup_vs_per_simulation": None if args.batched_only else t_single / t_batch,
     }
     print(json.dumps(out), flush=True)
 
@@ -281,6 +285,8 @@ def main():
                          "sweep vs the per-simulation path; surrogate: screening speedup and error")
     ap.add_argument("--sims", type=int, default=256, help="sweep: simulations")
     ap.add_argument("--sweep-iters", type=int, default=300, help="sweep: iterations per simulation")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="sweep: time the batched path only (for kernel traces), no per-simulation comparison")
     ap.add_argument("--train-steps", type=int, default=3000, help="surrogate: Adam steps")
     ap.add_argument("--resort-every", type=int, default=10)
     ap.add_argument("--sweep-grid", type=int, default=2048)
