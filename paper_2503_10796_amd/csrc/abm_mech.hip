@@ -739,68 +739,56 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
         }
-        // ---- targets: static skip (Sec 5.5), staged index, core box, zero accumulators
+        // ---- stage: box-relative -> relative to the centre of the 6x6x6 region
+        // (|x| < 3L).  A staged agent of a core box is a target: static skip
+        // (Sec 5.5), staged index, core box, agent index, zero accumulators.
         int active = 0, anystat = 0;
-        uint32_t ti[2] = {0u, 0u};  // agent indices, written to LDS after the stage (their loads overlap it)
-        static_assert(kMaxT <= 512, "at most two targets per thread");
-        for (uint32_t t = tid; t < nt; t += blockDim.x) {
-            int c = 0, hi = kCore;
-            while (hi - c > 1) {
-                int mid = (c + hi) >> 1;
-                if (L.coff[mid] <= t) c = mid; else hi = mid;
-            }
-            int cx, cy, cz;
-            core_box_coords(c, cx, cy, cz);
-            const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
-            const uint32_t k = t - L.coff[c];
-            const uint32_t ia = d.sorted_idx[L.gsrc[lb] + k];
-            ti[t < 256u ? 0 : 1] = ia;
-            bool stat = false;
-            if (S.detect_static) {
-                const int64_t i = ia;
-                const uint8_t fl = d.flags[lp][i];
-                if (fl & kStatic) {
-                    skip_static<DIAG>(d, i, P, lp, fl,
-                                      linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims));
-                    stat = true;
-                }
-            }
-            active |= stat ? 0 : 1;
-            anystat |= stat ? 1 : 0;
-            L.tself[t] = stat ? kNoTarget : (uint16_t)(L.sbeg[lb] + k);
-            L.tbox[t] = (uint8_t)c;
-            L.acc[0][t] = 0;
-            L.acc[1][t] = 0;
-            L.acc[2][t] = 0;
-            L.acm[t] = 0;
-            if (DIAG) L.anbr[t] = 0;
-        }
-        if (!__syncthreads_or(active)) continue;  // every target static: nothing to stage or sweep
-        // the half shell needs every core agent of the unit to be a target
-        const bool n3 = !DIAG && !(S.detect_static && __syncthreads_or(anystat));
-        // ---- stage: box-relative -> relative to the centre of the 6x6x6 region (|x| < 3L)
         for (uint32_t k = tid; k < total; k += blockDim.x) {
             int lo = 0, hi = kNb;  // largest lb with sbeg[lb] <= k
             while (hi - lo > 1) {
                 int mid = (lo + hi) >> 1;
                 if (L.sbeg[mid] <= k) lo = mid; else hi = mid;
             }
-            float4 c = d.payload[L.gsrc[lo] + (k - L.sbeg[lo])];
+            const uint32_t kb = k - L.sbeg[lo];
+            float4 c = d.payload[L.gsrc[lo] + kb];
             const int lx = lo % kHalo, ly = (lo / kHalo) % kHalo, lz = lo / (kHalo * kHalo);
+            uint16_t tm = kNoTarget;
+            if (lx >= 1 && lx <= kBlk && ly >= 1 && ly <= kBlk && lz >= 1 && lz <= kBlk) {
+                const int cb = (lx - 1) + kBlk * ((ly - 1) + kBlk * (lz - 1));
+                const uint32_t t = L.coff[cb] + kb;
+                const uint32_t ia = d.sorted_idx[L.gsrc[lo] + kb];
+                bool stat = false;
+                if (S.detect_static) {
+                    const int64_t i = ia;
+                    const uint8_t fl = d.flags[lp][i];
+                    if (fl & kStatic) {
+                        skip_static<DIAG>(d, i, P, lp, fl,
+                                          linear_box(qx * kBlk + lx - 1, qy * kBlk + ly - 1, qz * kBlk + lz - 1,
+                                                     S.dims));
+                        stat = true;
+                    }
+                }
+                active |= stat ? 0 : 1;
+                anystat |= stat ? 1 : 0;
+                L.tself[t] = stat ? kNoTarget : (uint16_t)k;
+                L.tbox[t] = (uint8_t)cb;
+                L.tidx[t] = ia;
+                L.acc[0][t] = 0;
+                L.acc[1][t] = 0;
+                L.acc[2][t] = 0;
+                L.acm[t] = 0;
+                if (DIAG) L.anbr[t] = 0;
+                if (!stat) tm = (uint16_t)t;
+            }
             c.x += (float)(lx - 3) * Lf;
             c.y += (float)(ly - 3) * Lf;
             c.z += (float)(lz - 3) * Lf;
             L.sp[k] = c;
-            uint16_t tm = kNoTarget;
-            if (lx >= 1 && lx <= kBlk && ly >= 1 && ly <= kBlk && lz >= 1 && lz <= kBlk) {
-                const uint32_t t = L.coff[(lx - 1) + kBlk * ((ly - 1) + kBlk * (lz - 1))] + (k - L.sbeg[lo]);
-                if (L.tself[t] != kNoTarget) tm = (uint16_t)t;
-            }
             L.tmap[k] = tm;
         }
-        if ((uint32_t)tid < nt) L.tidx[tid] = ti[0];
-        if ((uint32_t)tid + 256u < nt) L.tidx[tid + 256] = ti[1];
-        __syncthreads();
+        if (!__syncthreads_or(active)) continue;  // every target static: nothing to sweep
+        // the half shell needs every core agent of the unit to be a target
+        const bool n3 = !DIAG && !(S.detect_static && __syncthreads_or(anystat));
         // ---- setup: candidate ranges of every active target (at most two per
         // thread), task counts per length; the ranges stay in registers for
         // the task scatter
