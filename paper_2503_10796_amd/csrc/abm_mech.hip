@@ -157,6 +157,7 @@ struct SweepLds {
     uint32_t bcnt[kBuckets], boff[kBuckets];
     uint32_t queue[4][kQueue];
     uint32_t sh[4];
+    unsigned long long sh64[4];             // per-wave totals of the table scan
     uint32_t ntask;
     unsigned long long ahead[2][4];         // look-ahead over units: active-unit ballots of the 4 waves
     uint32_t task[kTaskCap];                // target | first candidate << 9 | candidates << 19,
@@ -690,8 +691,11 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
         if (!DIAG && S.detect_static && !d.active_blk[S.b_off + (u - d.wblk_begin[s])]) continue;
         int qx, qy, qz;
         unpack_key(d.blist[S.b_off + (u - d.wblk_begin[s])], qx, qy, qz);
-        // ---- table of the 6x6x6 staged boxes (x fastest)
+        // ---- table of the 6x6x6 staged boxes (x fastest).  One scan of packed
+        // counts gives the staged index of every box (low word) and the target
+        // index of every core box (high word).
         uint32_t cnt = 0;
+        int cb = -1;  // core box index (targets), or -1
         if (tid < kNb) {
             const int lx = tid % kHalo, ly = (tid / kHalo) % kHalo, lz = tid / (kHalo * kHalo);
             const int gx = qx * kBlk + lx - 1, gy = qy * kBlk + ly - 1, gz = qz * kBlk + lz - 1;
@@ -702,28 +706,37 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
                 cnt = d.box_start[S.sb_off + m + 1] - src;
             }
             L.gsrc[tid] = src;
+            if (lx >= 1 && lx <= kBlk && ly >= 1 && ly <= kBlk && lz >= 1 && lz <= kBlk)
+                cb = (lx - 1) + kBlk * ((ly - 1) + kBlk * (lz - 1));
         }
-        uint32_t v[4] = {cnt, 0u, 0u, 0u};
-        uint32_t total;
-        const uint32_t pre = block_excl_scan_4(v, L.sh, total);
-        if (tid < kNb) L.sbeg[tid] = pre;
-        if (tid == 0) L.sbeg[kNb] = total;
-        __syncthreads();
-        if (tid < 64) {  // prefix of the target counts over the 64 core boxes (one wave)
-            const int lb = (tid % 4 + 1) + kHalo * ((tid / 4 % 4 + 1) + kHalo * (tid / 16 + 1));
-            const uint32_t cc = L.sbeg[lb + 1] - L.sbeg[lb];
-            uint32_t x = cc;
+        uint32_t total, nt;
+        {
+            const unsigned long long pv = (unsigned long long)cnt | ((unsigned long long)(cb >= 0 ? cnt : 0u) << 32);
+            unsigned long long x = pv;
             for (int off = 1; off < 64; off <<= 1) {
-                uint32_t y = __shfl_up(x, off);
-                if (tid >= off) x += y;
+                const unsigned long long y = __shfl_up(x, off);
+                if ((int)lane >= off) x += y;
             }
-            L.coff[tid] = x - cc;
-            if (tid == 63) L.coff[64] = x;
-            L.bcnt[tid] = 0;
+            if (lane == 63) L.sh64[w] = x;  // read after the barrier; rewritten only in the next unit
+            __syncthreads();
+            unsigned long long pre = x - pv, tot = 0;
+            for (int v = 0; v < 4; ++v) {
+                const unsigned long long sv = L.sh64[v];
+                if (v < (int)w) pre += sv;
+                tot += sv;
+            }
+            if (tid < kNb) L.sbeg[tid] = (uint32_t)pre;
+            if (cb >= 0) L.coff[cb] = (uint32_t)(pre >> 32);
+            if (tid == 0) {
+                L.sbeg[kNb] = (uint32_t)tot;
+                L.coff[kCore] = (uint32_t)(tot >> 32);
+            }
+            if (tid < kBuckets) L.bcnt[tid] = 0;
+            total = (uint32_t)tot;
+            nt = (uint32_t)(tot >> 32);
         }
         __syncthreads();
         const float Lf = (float)S.L;
-        const uint32_t nt = L.coff[kCore];
         const float e = S.e_delta, g = 2.0f * e;
         const float kf = (float)S.k, gf = (float)S.gamma;
         const float L2 = (float)(S.L * S.L);
