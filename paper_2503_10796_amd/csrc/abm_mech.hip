@@ -145,7 +145,8 @@ constexpr uint16_t kNoTarget = 0xffff;
 
 template <bool DIAG>
 struct SweepLds {
-    float4 sp[kStage];                      // staged payload, block-relative coordinates
+    float4 sp[kStage + 1];                  // staged payload, block-relative coordinates (one
+                                            // entry past the largest stage: read ahead, unused)
     unsigned long long acc[3][kMaxT];       // force sums, 2^-40 units (two's complement)
     unsigned long long acm[kMaxT];          // contacts with a certain non-zero force (bits 0..15),
                                             // contacts whose force may be zero (16..30), kUncBit,
@@ -161,7 +162,8 @@ struct SweepLds {
     uint32_t ntask;
     unsigned long long ahead[2][4];         // look-ahead over units: active-unit ballots of the 4 waves
     uint32_t task[kTaskCap];                // target | first candidate << 9 | candidates << 19,
-                                            // sorted by length (longest first)
+                                            // sorted by length (longest first); before the
+                                            // setup, the staged box of every staged agent (bytes)
     uint16_t tself[kMaxT];                  // staged index of each target (kNoTarget: static)
     uint32_t tidx[kMaxT];                   // agent index of each target
     uint16_t tmap[kStage];                  // target of each staged agent (kNoTarget: halo or static)
@@ -169,6 +171,7 @@ struct SweepLds {
 };
 static_assert(sizeof(SweepLds<false>) <= 40960, "four blocks of 256 threads per CU");
 static_assert(kStage < 1024 && kMaxT < 512, "queue and task entries: 9-bit target, 10-bit staged indices");
+static_assert(kNb <= 256 && kStage <= 4 * kTaskCap, "the stage map: one byte per staged agent in the task list");
 
 // Per-target accumulator of the global-memory path.
 struct Acc {
@@ -296,6 +299,42 @@ __device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32
     if (o.unc || (DIAG && o.nz_unc)) {
         atomicOr(&L.acm[t], kUncBit);
         if (tq != kNoTarget) atomicOr(&L.acm[tq], kUncBit);
+    }
+}
+
+// Reach test of candidate kk of a lane's task (staged payload c, staged index
+// b0 + kk) against the lane's target; survivors go to the wave's queue, which
+// is drained whenever it holds 64 pairs (qn: wave-uniform fill).  CHECK: some
+// lane's task may have fewer than kk + 1 candidates.
+template <bool DIAG, bool CHECK>
+__device__ inline void reach_test(SweepLds<DIAG> &L, uint32_t *qw, uint32_t &qn, float4 own, float owg, float4 c,
+                                  uint32_t kk, uint32_t len, uint32_t tq, uint32_t self, uint32_t b0, uint32_t &nb,
+                                  bool &un, float e, float g, float kf, float gf, float L2m, float L2p, bool n3) {
+    const uint32_t lane = threadIdx.x & 63;
+    const bool in = !CHECK || kk < len;
+    const float ddx = own.x - c.x, ddy = own.y - c.y, ddz = own.z - c.z;
+    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+    const float sg = owg + c.w;
+    const bool hit = in && d2 < sg * sg;
+    if (DIAG) {
+        const bool other = in && b0 + kk != self;
+        nb += (other && d2 < L2m) ? 1u : 0u;
+        un |= other && d2 >= L2m && d2 < L2p;
+    }
+    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+    if (m) {
+        if (hit)
+            qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                tq + kk;
+        qn += (uint32_t)__popcll(m);
+        if (qn >= 64) {
+            __builtin_amdgcn_wave_barrier();
+            drain_queue<DIAG>(L, qw, 64u, e, g, kf, gf, L2m, L2p, n3);
+            __builtin_amdgcn_wave_barrier();
+            qn -= 64;
+            if (lane < qn) qw[lane] = qw[64 + lane];
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 }
 
@@ -727,6 +766,12 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
             }
             if (tid < kNb) L.sbeg[tid] = (uint32_t)pre;
             if (cb >= 0) L.coff[cb] = (uint32_t)(pre >> 32);
+            if ((uint32_t)tot <= (uint32_t)kStage) {
+                // staged box of every staged agent, for the stage loop (the
+                // task list is free until the setup)
+                uint8_t *smap = reinterpret_cast<uint8_t *>(L.task);
+                for (uint32_t j = 0; j < cnt; ++j) smap[(uint32_t)pre + j] = (uint8_t)tid;
+            }
             if (tid == 0) {
                 L.sbeg[kNb] = (uint32_t)tot;
                 L.coff[kCore] = (uint32_t)(tot >> 32);
@@ -756,12 +801,9 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
         // (|x| < 3L).  A staged agent of a core box is a target: static skip
         // (Sec 5.5), staged index, core box, agent index, zero accumulators.
         int active = 0, anystat = 0;
+        const uint8_t *smap = reinterpret_cast<const uint8_t *>(L.task);
         for (uint32_t k = tid; k < total; k += blockDim.x) {
-            int lo = 0, hi = kNb;  // largest lb with sbeg[lb] <= k
-            while (hi - lo > 1) {
-                int mid = (lo + hi) >> 1;
-                if (L.sbeg[mid] <= k) lo = mid; else hi = mid;
-            }
+            const int lo = smap[k];
             const uint32_t kb = k - L.sbeg[lo];
             float4 c = d.payload[L.gsrc[lo] + kb];
             const int lx = lo % kHalo, ly = (lo / kHalo) % kHalo, lz = lo / (kHalo * kHalo);
@@ -878,42 +920,48 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
                 const uint32_t tq = (t << 20) | (self << 10) | b0;  // + kk: b0 + kk < kStage
                 uint32_t nb = 0;
                 bool un = false;
-                // candidates b0, b0+1, ...: lanes past their row end read
-                // clamped indices and are masked; the next one is prefetched
-                uint32_t q = min(b0, (uint32_t)kStage - 1u);
-                float4 cc = L.sp[q];
-                for (uint32_t kk = 0;; ++kk) {
-                    const bool in = kk < len;
-                    const uint64_t im = __builtin_amdgcn_ballot_w64(in);
-                    if (!im) break;
-                    const uint32_t qn1 = min(q + 1u, (uint32_t)kStage - 1u);
-                    const float4 cn = L.sp[qn1];
-                    const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
-                    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                    const float sg = owg + cc.w;
-                    const bool hit = d2 < sg * sg;
-                    if (DIAG) {
-                        const bool other = in && q != self;
-                        nb += (other && d2 < L2m) ? 1u : 0u;
-                        un |= other && d2 >= L2m && d2 < L2p;
+                // wave-uniform trip counts: the tasks are sorted by length, longest
+                // first, and buckets below the last (kBuckets - 1 and up) hold one
+                // length each, so the chunk's first task is its longest unless it
+                // lies in the last bucket, and every task has at least as many
+                // candidates as the last lane's (an invalid lane has none) or
+                // kBuckets - 1, whichever is smaller
+                uint32_t maxlen = __builtin_amdgcn_readlane(len, 0);
+                if (maxlen >= (uint32_t)kBuckets - 1u) {
+                    uint32_t mx = len;
+                    for (int off = 1; off < 64; off <<= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off));
+                    maxlen = __builtin_amdgcn_readlane(mx, 0);
+                }
+                const uint32_t minlen = min((uint32_t)__builtin_amdgcn_readlane(len, 63), (uint32_t)kBuckets - 1u);
+                // candidates b0, b0+1, ... two per trip, each loaded one test ahead.
+                // Below minlen every lane is inside its row (the read-ahead stays
+                // within the stage's guard entry); past it, lanes beyond their row
+                // end read clamped indices and are masked
+                uint32_t kk = 0;
+                if (minlen >= 2) {
+                    const float4 *row = L.sp + b0;
+                    float4 ca = row[0];
+                    for (; kk + 1u < minlen; kk += 2) {
+                        const float4 cb = row[kk + 1u];
+                        reach_test<DIAG, false>(L, qw, qn, own, owg, ca, kk, len, tq, self, b0, nb, un, e, g, kf, gf,
+                                                L2m, L2p, n3);
+                        ca = row[kk + 2u];
+                        reach_test<DIAG, false>(L, qw, qn, own, owg, cb, kk + 1u, len, tq, self, b0, nb, un, e, g, kf,
+                                                gf, L2m, L2p, n3);
                     }
-                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit) & im;
-                    if (m) {
-                        if (in && hit)
-                            qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = tq + kk;
-                        qn += (uint32_t)__popcll(m);
-                        if (qn >= 64) {
-                            __builtin_amdgcn_wave_barrier();
-                            drain_queue<DIAG>(L, qw, 64u, e, g, kf, gf, L2m, L2p, n3);
-                            __builtin_amdgcn_wave_barrier();
-                            qn -= 64;
-                            if (lane < qn) qw[lane] = qw[64 + lane];
-                            __builtin_amdgcn_wave_barrier();
-                        }
+                }
+                if (kk < maxlen) {
+                    const uint32_t last = (uint32_t)kStage - 1u;
+                    float4 ca = L.sp[min(b0 + kk, last)];
+                    for (; kk < maxlen; kk += 2) {
+                        const float4 cb = L.sp[min(b0 + kk + 1u, last)];
+                        reach_test<DIAG, true>(L, qw, qn, own, owg, ca, kk, len, tq, self, b0, nb, un, e, g, kf, gf,
+                                               L2m, L2p, n3);
+                        ca = L.sp[min(b0 + kk + 2u, last)];
+                        if (kk + 1u < maxlen)
+                            reach_test<DIAG, true>(L, qw, qn, own, owg, cb, kk + 1u, len, tq, self, b0, nb, un, e, g,
+                                                   kf, gf, L2m, L2p, n3);
                     }
-                    cc = cn;
-                    q = qn1;
                 }
                 if (DIAG && tv) {
                     atomicAdd(&L.anbr[t], nb);
