@@ -214,15 +214,18 @@ __global__ void k_grid_done(Dev d) {
 }
 
 // ------------------------------------------------------------------ bin
-__global__ void __launch_bounds__(256) k_bin(Dev d) {
+// (sims, tiles: the descriptors and the tile prefix, read-only and not
+// aliased, so that their wave-uniform reads are scalar loads)
+__global__ void __launch_bounds__(256) k_bin(Dev d, const SimDesc *__restrict__ sims,
+                                             const int64_t *__restrict__ tiles) {
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
     const int64_t total = d.ctl->total_tiles;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        const int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
+        int s = find_sim(tiles, d.n_sims, t);
+        const SimDesc &S = sims[s];
+        const int64_t loc = (t - tiles[s]) * kTile + threadIdx.x;
         const bool valid = loc < S.n_start;  // the invalid lanes are the last of the tile
         const int64_t i = S.a_off + (valid ? loc : 0);
         uint32_t m = 0;
@@ -328,15 +331,16 @@ __global__ void __launch_bounds__(256) k_scan_apply(Dev d, int resort) {
 }
 
 // ------------------------------------------------------------------ scatter
-__global__ void __launch_bounds__(256) k_scatter(Dev d) {
+__global__ void __launch_bounds__(256) k_scatter(Dev d, const SimDesc *__restrict__ sims,
+                                                 const int64_t *__restrict__ tiles) {
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
     const int64_t total = d.ctl->total_tiles;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
+        int s = find_sim(tiles, d.n_sims, t);
+        const SimDesc &S = sims[s];
+        int64_t loc = (t - tiles[s]) * kTile + threadIdx.x;
         if (loc >= S.n_start) continue;
         int64_t i = S.a_off + loc;
         int bx, by, bz;
@@ -753,11 +757,13 @@ void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_b
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_brank, dim3(grid_boxes), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_grid_done, dim3(1), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_bin, dim3(grid_agents), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_bin, dim3(grid_agents), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                       (const int64_t *)d.tile_begin);
     hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d, 0);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d, 0);
     hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d, 0);
-    hipLaunchKernelGGL(k_scatter, dim3(grid_agents), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_scatter, dim3(grid_agents), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                       (const int64_t *)d.tile_begin);
     if (any_static) {
         launch_near_marks(d, st, grid_boxes, true);
         hipLaunchKernelGGL(k_static_fix, dim3(grid_agents), dim3(256), 0, st, d);

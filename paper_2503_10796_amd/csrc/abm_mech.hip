@@ -675,8 +675,13 @@ __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> 
     }
 }
 
+// The simulation descriptors and unit tables come in as read-only,
+// non-aliased arguments as well, so that their wave-uniform reads are scalar
+// loads.
 template <bool DIAG>
-__global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 blocks per CU: at most 128 VGPRs
+__global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
+    k_sweep(Dev d, const SimDesc *__restrict__ sims, const int64_t *__restrict__ wblk,
+            const uint32_t *__restrict__ blist, const uint8_t *__restrict__ active_blk, int lookahead) {
     __shared__ SweepLds<DIAG> L;
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
@@ -700,9 +705,9 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
                 const int64_t uu = u + (int64_t)tid * per_xcd;
                 bool act = false;
                 if (uu < u_end) {
-                    const int s2 = find_sim(d.wblk_begin, d.n_sims, uu);
-                    const SimDesc &S2 = d.sims[s2];
-                    act = !S2.detect_static || d.active_blk[S2.b_off + (uu - d.wblk_begin[s2])] != 0;
+                    const int s2 = find_sim(wblk, d.n_sims, uu);
+                    const SimDesc &S2 = sims[s2];
+                    act = !S2.detect_static || active_blk[S2.b_off + (uu - wblk[s2])] != 0;
                 }
                 const uint64_t am = __builtin_amdgcn_ballot_w64(act);
                 if (lane == 0) L.ahead[par][w] = am;
@@ -722,14 +727,14 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
             }
             if (u >= u_end) break;
         }
-        const int s = find_sim(d.wblk_begin, d.n_sims, u);
-        const SimDesc &S = d.sims[s];
+        const int s = find_sim(wblk, d.n_sims, u);
+        const SimDesc &S = sims[s];
         // with static detection, a block whose agents are all static and
         // settled needs no visit (marked while binning the grid); the
         // diagnostic mode visits every block to write its per-agent fields
-        if (!DIAG && S.detect_static && !d.active_blk[S.b_off + (u - d.wblk_begin[s])]) continue;
+        if (!DIAG && S.detect_static && !active_blk[S.b_off + (u - wblk[s])]) continue;
         int qx, qy, qz;
-        unpack_key(d.blist[S.b_off + (u - d.wblk_begin[s])], qx, qy, qz);
+        unpack_key(blist[S.b_off + (u - wblk[s])], qx, qy, qz);
         // ---- table of the 6x6x6 staged boxes (x fastest).  One scan of packed
         // counts gives the staged index of every box (low word) and the target
         // index of every core box (high word).
@@ -996,9 +1001,9 @@ __global__ void __launch_bounds__(256, 4) k_sweep(Dev d, int lookahead) {  // 4 
                     unc = true;
                 } else {
                     const int nzc = nz_min + nz_unc;
-                    const uint8_t fl = d.flags[lp][i];
                     // box slot: the unit's block has Morton rank u - wblk_begin (its blist entry)
-                    const uint32_t m = (uint32_t)(u - d.wblk_begin[s]) * 64u + local_morton(cx, cy, cz);
+                    const uint32_t m = (uint32_t)(u - wblk[s]) * 64u + local_morton(cx, cy, cz);
+                    const uint8_t fl = d.flags[lp][i];
                     commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
                                        fz, nzc, DIAG ? (int)L.anbr[t] : 0, nzc, m, lin);
                 }
@@ -1088,7 +1093,8 @@ __device__ inline double wave_sum_f64(double v) {
 // neighbour box b, the candidates of all 27 boxes are dealt to the lanes,
 // and the exact per-lane sums are added over the wave.
 template <bool DIAG>
-__global__ void __launch_bounds__(256) k_fixup(Dev d) {
+__global__ void __launch_bounds__(256)
+    k_fixup(Dev d, const SimDesc *__restrict__ sims, const int64_t *__restrict__ a_begin) {  // (read-only: scalar loads)
 #pragma clang fp contract(off)
     __shared__ uint32_t bst[4][27], bpre[4][28];
     if (ABM_ABORTED(d)) return;
@@ -1097,9 +1103,9 @@ __global__ void __launch_bounds__(256) k_fixup(Dev d) {
     const uint32_t nf = d.ctl->n_fix;
     const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (uint32_t q = blockIdx.x * 4 + w; q < nf; q += gridDim.x * 4) {
-        const int64_t i = d.fix_list[q];
-        const int s = find_sim(d.a_begin, d.n_sims, i);
-        const SimDesc &S = d.sims[s];
+        const int64_t i = (uint32_t)__builtin_amdgcn_readfirstlane(d.fix_list[q]);  // one agent per wave
+        const int s = find_sim(a_begin, d.n_sims, i);
+        const SimDesc &S = sims[s];
         const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
         const double ri = 0.5 * d.diam[lp][i];
         const double L2 = S.L * S.L;
@@ -1470,8 +1476,13 @@ __global__ void __launch_bounds__(256) k_static(Dev d) {
 
 // ------------------------------------------------------------------ launchers
 void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag, bool any_static) {
-    if (diag) hipLaunchKernelGGL(k_sweep<true>, dim3(sweep_grid), dim3(256), 0, st, d, 0);
-    else hipLaunchKernelGGL(k_sweep<false>, dim3(sweep_grid), dim3(256), 0, st, d, any_static ? 1 : 0);
+    const SimDesc *sims = d.sims;
+    if (diag)
+        hipLaunchKernelGGL(k_sweep<true>, dim3(sweep_grid), dim3(256), 0, st, d, sims, d.wblk_begin, d.blist,
+                           d.active_blk, 0);
+    else
+        hipLaunchKernelGGL(k_sweep<false>, dim3(sweep_grid), dim3(256), 0, st, d, sims, d.wblk_begin, d.blist,
+                           d.active_blk, any_static ? 1 : 0);
 }
 
 // Everything of one iteration after the sweep; ends by building the grid of
@@ -1479,8 +1490,10 @@ void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag, bool 
 void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool diag, bool any_growth,
                         bool any_static, bool resort) {
     // one wave per agent on the FP64 path (16384 waves, grid-stride beyond)
-    if (diag) hipLaunchKernelGGL(k_fixup<true>, dim3(4096), dim3(256), 0, st, d);
-    else hipLaunchKernelGGL(k_fixup<false>, dim3(4096), dim3(256), 0, st, d);
+    const SimDesc *sims = d.sims;
+    const int64_t *a_begin = d.a_begin;
+    if (diag) hipLaunchKernelGGL(k_fixup<true>, dim3(4096), dim3(256), 0, st, d, sims, a_begin);
+    else hipLaunchKernelGGL(k_fixup<false>, dim3(4096), dim3(256), 0, st, d, sims, a_begin);
     if (any_growth) {
         hipLaunchKernelGGL(k_div_mark, dim3(grid_agents), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_div_check, dim3(1), dim3(256), 0, st, d);
