@@ -157,7 +157,7 @@ struct SweepLds {
     uint32_t coff[kCore + 1];               // prefix of the target counts of the core boxes
     uint32_t bcnt[kBuckets], boff[kBuckets];
     uint32_t queue[4][kQueue];
-    uint32_t sh[4];
+    uint32_t sh[4];                         // per-wave flags: an active target, a static target
     unsigned long long sh64[4];             // per-wave totals of the table scan
     uint32_t ntask;
     unsigned long long ahead[2][4];         // look-ahead over units: active-unit ballots of the 4 waves
@@ -846,9 +846,18 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
             L.sp[k] = c;
             L.tmap[k] = tm;
         }
-        if (!__syncthreads_or(active)) continue;  // every target static: nothing to sweep
+        // whether any target is active, and whether any is static: the waves'
+        // ballots meet in LDS (one barrier)
+        {
+            const uint64_t ba = __builtin_amdgcn_ballot_w64(active != 0);
+            const uint64_t bs = __builtin_amdgcn_ballot_w64(anystat != 0);
+            if (lane == 0) L.sh[w] = (ba ? 1u : 0u) | (bs ? 2u : 0u);  // read below; rewritten a unit later
+        }
+        __syncthreads();
+        const uint32_t any = L.sh[0] | L.sh[1] | L.sh[2] | L.sh[3];
+        if (!(any & 1u)) continue;  // every target static: nothing to sweep
         // the half shell needs every core agent of the unit to be a target
-        const bool n3 = !DIAG && !(S.detect_static && __syncthreads_or(anystat));
+        const bool n3 = !DIAG && !(S.detect_static && (any & 2u));
         // ---- setup: candidate ranges of every active target (at most two per
         // thread), task counts per length; the ranges stay in registers for
         // the task scatter
