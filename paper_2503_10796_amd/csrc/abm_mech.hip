@@ -1080,39 +1080,41 @@ struct Fix128 {
 // FP64 re-evaluation with the exact expressions of the method for agents the
 // FP32 sweep could not decide.  Neighbours are read from the start-of-iteration
 // FP64 state through the grid (copy semantics).
-// 128-bit sum over the lanes of a wave (two's complement, exact).
-__device__ inline void wave_sum128(uint64_t &lo, uint64_t &hi) {
-    for (int off = 32; off > 0; off >>= 1) {
+// 128-bit sum over the lanes of a half wave (two's complement, exact).
+__device__ inline void half_sum128(uint64_t &lo, uint64_t &hi) {
+    for (int off = 16; off > 0; off >>= 1) {
         const uint64_t olo = __shfl_xor(lo, off), ohi = __shfl_xor(hi, off);
         const uint64_t nlo = lo + olo;
         hi = hi + ohi + (nlo < lo ? 1ull : 0ull);
         lo = nlo;
     }
 }
-__device__ inline int wave_sum_i32(int v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+__device__ inline int half_sum_i32(int v) {
+    for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
 }
-__device__ inline double wave_sum_f64(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+__device__ inline double half_sum_f64(double v) {
+    for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
 }
 
-// One wave per agent on the FP64 path: lane b < 27 reads the slot range of
-// neighbour box b, the candidates of all 27 boxes are dealt to the lanes,
-// and the exact per-lane sums are added over the wave.
+// Two agents per wave on the FP64 path, one per half wave: lane b < 27 of a
+// half reads the slot range of neighbour box b, the candidates of all 27
+// boxes are dealt to the half's lanes, and the exact per-lane sums are added
+// over the half.  (All shuffles stay within a half, so a half that has no
+// agent left may drop out while the other goes on.)
 template <bool DIAG>
 __global__ void __launch_bounds__(256)
-    k_fixup(Dev d, const SimDesc *__restrict__ sims, const int64_t *__restrict__ a_begin) {  // (read-only: scalar loads)
+    k_fixup(Dev d, const SimDesc *__restrict__ sims, const int64_t *__restrict__ a_begin) {  // (read-only, not aliased)
 #pragma clang fp contract(off)
-    __shared__ uint32_t bst[4][27], bpre[4][28];
+    __shared__ uint32_t bst[8][27], bpre[8][28];
     if (ABM_ABORTED(d)) return;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
     const uint32_t nf = d.ctl->n_fix;
-    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (uint32_t q = blockIdx.x * 4 + w; q < nf; q += gridDim.x * 4) {
-        const int64_t i = (uint32_t)__builtin_amdgcn_readfirstlane(d.fix_list[q]);  // one agent per wave
+    const uint32_t w = threadIdx.x >> 5, lane = threadIdx.x & 31;  // half wave, lane in it
+    for (uint32_t q = blockIdx.x * 8 + w; q < nf; q += gridDim.x * 8) {
+        const int64_t i = d.fix_list[q];
         const int s = find_sim(a_begin, d.n_sims, i);
         const SimDesc &S = sims[s];
         const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
@@ -1129,12 +1131,12 @@ __global__ void __launch_bounds__(256)
                 cnt = d.box_start[S.sb_off + m + 1] - st;
             }
         }
-        uint32_t pre = cnt;  // inclusive scan over the lanes
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t o = __shfl_up(pre, off);
+        uint32_t pre = cnt;  // inclusive scan over the half's lanes
+        for (int off = 1; off < 32; off <<= 1) {
+            const uint32_t o = __shfl_up(pre, off, 32);
             if (lane >= (uint32_t)off) pre += o;
         }
-        const uint32_t total = __shfl(pre, 63);
+        const uint32_t total = __shfl(pre, 31, 32);
         if (lane < 27) {
             bst[w][lane] = st;
             bpre[w][lane] = pre - cnt;
@@ -1144,7 +1146,7 @@ __global__ void __launch_bounds__(256)
         double fx = 0.0, fy = 0.0, fz = 0.0;  // plain sums, used only when a term is huge
         Fix128 sx, sy, sz;
         int nbr = 0, contacts = 0, nzc = 0;
-        for (uint32_t c = lane; c < total; c += 64) {
+        for (uint32_t c = lane; c < total; c += 32) {
             int lo = 0, hi = 27;  // box of candidate c: the largest b with bpre[b] <= c
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -1175,18 +1177,19 @@ __global__ void __launch_bounds__(256)
             }
         }
         __builtin_amdgcn_wave_barrier();  // the box tables are rewritten for the next agent
-        nbr = wave_sum_i32(nbr);
-        contacts = wave_sum_i32(contacts);
-        nzc = wave_sum_i32(nzc);
-        const bool wide = __builtin_amdgcn_ballot_w64(sx.wide || sy.wide || sz.wide) != 0;
+        nbr = half_sum_i32(nbr);
+        contacts = half_sum_i32(contacts);
+        nzc = half_sum_i32(nzc);
+        const uint64_t bw = __builtin_amdgcn_ballot_w64(sx.wide || sy.wide || sz.wide);
+        const bool wide = ((w & 1u) ? (bw >> 32) : (bw & 0xffffffffull)) != 0;
         if (wide) {
-            fx = wave_sum_f64(fx);
-            fy = wave_sum_f64(fy);
-            fz = wave_sum_f64(fz);
+            fx = half_sum_f64(fx);
+            fy = half_sum_f64(fy);
+            fz = half_sum_f64(fz);
         } else {
-            wave_sum128(sx.lo, sx.hi);
-            wave_sum128(sy.lo, sy.hi);
-            wave_sum128(sz.lo, sz.hi);
+            half_sum128(sx.lo, sx.hi);
+            half_sum128(sy.lo, sy.hi);
+            half_sum128(sz.lo, sz.hi);
             fx = sx.value();
             fy = sy.value();
             fz = sz.value();
