@@ -391,29 +391,30 @@ template <bool DIAG>
 __device__ inline void task_range(const SweepLds<DIAG> &L, uint32_t rows, int cx, int cy, int cz, int r, bool n3,
                                   uint32_t self, uint32_t &b0, uint32_t &len) {
     const int rr = r < 9 ? r : 4;  // task 9 belongs to the own row
+    const int dy = rr % 3 - 1, dz = rr / 3 - 1;
     const uint32_t rb = (rows >> (3 * rr)) & 7u;
     const int row = task_row(cx, cy, cz, rr);  // staged box of the row's left box
-    uint32_t lo = L.sbeg[row + ((rb & 2u) ? 0 : 1)], hi = L.sbeg[row + ((rb & 4u) ? 3 : 2)];
-    bool keep = rb != 0 && (r < 9 || n3);
-    if (keep && n3) {
-        const int dy = rr % 3 - 1, dz = rr / 3 - 1;
-        const int y = cy + dy, z = cz + dz;
-        if (y >= 0 && y < kBlk && z >= 0 && z < kBlk) {
-            const bool lh = cx == 0 && (rb & 2u), rh = cx == kBlk - 1 && (rb & 4u);  // kept halo boxes
-            if (r == 9) {  // own row, halo left box
-                keep = lh;
-                hi = L.sbeg[row + 1];
-            } else if (dz < 0 || (dz == 0 && dy < 0)) {  // before the own row
-                keep = lh || rh;
-                if (lh) hi = L.sbeg[row + 1];
-                else lo = L.sbeg[row + 2];
-            } else if (dz == 0 && dy == 0) {  // own row: after the target
-                lo = self + 1;
-            }
-        } else {
-            keep = r < 9;
+    const bool lk = (rb & 2u) != 0, rk = (rb & 4u) != 0;  // left / right box kept
+    int lo_i = lk ? row : row + 1, hi_i = rk ? row + 3 : row + 2;
+    bool keep = rb != 0 && r < 9;
+    bool after_self = false;
+    // (r is a constant once the task loop is unrolled: the cases below
+    // reduce to a few selects)
+    const bool inner = (unsigned)(cy + dy) < (unsigned)kBlk && (unsigned)(cz + dz) < (unsigned)kBlk;
+    const bool lh = cx == 0 && lk, rh = cx == kBlk - 1 && rk;  // kept halo boxes
+    if (r == 9) {  // own row, halo left box
+        keep = n3 && lh;
+        hi_i = row + 1;
+    } else if (dz < 0 || (dz == 0 && dy < 0)) {  // before the own row: its halo box only
+        if (n3 && inner) {
+            keep = keep && (lh || rh);
+            hi_i = lh ? row + 1 : hi_i;
+            lo_i = lh ? lo_i : row + 2;
         }
+    } else if (dz == 0 && dy == 0) {  // own row: the candidates after the target
+        after_self = n3;
     }
+    const uint32_t lo = after_self ? self + 1u : L.sbeg[lo_i], hi = L.sbeg[hi_i];
     b0 = lo;
     len = keep && hi > lo ? hi - lo : 0u;
 }
