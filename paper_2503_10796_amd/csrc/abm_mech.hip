@@ -736,6 +736,11 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
         if (!DIAG && S.detect_static && !active_blk[S.b_off + (u - wblk[s])]) continue;
         int qx, qy, qz;
         unpack_key(blist[S.b_off + (u - wblk[s])], qx, qy, qz);
+        // Wave priority rises as a unit advances through its phases (table 0,
+        // stage 1, setup 2, pair tests and commit 3): waves further along issue
+        // first, so the waves of a block reach its barriers together while
+        // other blocks' loads fill the gaps.
+        __builtin_amdgcn_s_setprio(0);
         // ---- table of the 6x6x6 staged boxes (x fastest).  One scan of packed
         // counts gives the staged index of every box (low word) and the target
         // index of every core box (high word).
@@ -803,6 +808,7 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
         }
+        __builtin_amdgcn_s_setprio(1);
         // ---- stage: box-relative -> relative to the centre of the 6x6x6 region
         // (|x| < 3L).  A staged agent of a core box is a target: static skip
         // (Sec 5.5), staged index, core box, agent index, zero accumulators.
@@ -859,6 +865,7 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
         if (!(any & 1u)) continue;  // every target static: nothing to sweep
         // the half shell needs every core agent of the unit to be a target
         const bool n3 = !DIAG && !(S.detect_static && (any & 2u));
+        __builtin_amdgcn_s_setprio(2);
         // ---- setup: candidate ranges of every active target (at most two per
         // thread), task counts per length; the ranges stay in registers for
         // the task scatter
@@ -917,6 +924,7 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
             }
         }
         __syncthreads();
+        __builtin_amdgcn_s_setprio(3);
         // ---- sweep: chunks of 64 tasks per wave, survivors through the queue
         {
             uint32_t *qw = L.queue[w];
