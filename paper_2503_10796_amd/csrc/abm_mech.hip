@@ -17,6 +17,7 @@
 // result does not depend on the order in which neighbours are visited: every
 // run is bitwise reproducible regardless of atomics (Sec 7.1.4 asks for this).
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "abm_device.h"
@@ -443,20 +444,25 @@ __device__ inline void acc_reduce_streams(Acc &a, int g) {
 // streams interleaved; the exact fixed-point sums of a target's streams are
 // then added across lanes.  Payload is read from global memory in coalesced
 // chunks of 64 candidates staged in the wave's slice of the LDS stage.
-// Drain of the box-wise path: lane l takes queue entry l (target lane | candidate
-// index in the staged chunk << 6) and adds the pair's contact force and counts
-// to the target's LDS accumulators (force x, y, z; counts | error bound << 32).
+// Box-wise path of the production sweep: candidates per wave and chunk.
+constexpr int kDenseChunk = 224;
+
+// Drain of the box-wise path: lane l takes queue entry l (target lane |
+// candidate index in the staged chunk << 6) and adds the pair's contact
+// force and counts to the target's LDS accumulators (force x, y, z; counts |
+// error bound << 32).  Candidates are staged in the frame of the targets' box;
+// cs holds their slots (the target of lane tl has slot tslot0 + tl: a target
+// is not its own candidate).
 __device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const float4 *ob, const float4 *buf,
-                                   unsigned long long *acc, float ox, float oy, float oz, float e, float g, float kf,
-                                   float gf, float L2m, float L2p) {
+                                   const uint32_t *cs, uint32_t tslot0, unsigned long long *acc, float e, float g,
+                                   float kf, float gf, float L2m, float L2p) {
     const uint32_t lane = threadIdx.x & 63;
-    const bool valid = lane < cnt;
-    const uint32_t ent = valid ? qw[lane] : 0u;
+    const uint32_t ent = lane < cnt ? qw[lane] : 0u;
     const uint32_t tl = ent & 63u, j = ent >> 6;
+    const bool valid = lane < cnt && cs[j] != tslot0 + tl;
     const float4 own = ob[tl];
     const float4 c = buf[j];
-    // the target's coordinates in the candidate box's frame, as in pair_fp32
-    const float ddx = (own.x - ox) - c.x, ddy = (own.y - oy) - c.y, ddz = (own.z - oz) - c.z;
+    const float ddx = own.x - c.x, ddy = own.y - c.y, ddz = own.z - c.z;
     const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
     const PairOut o = pair_math(ddx, ddy, ddz, d2, own.w, c.w, e, g, kf, gf, L2m, L2p, valid);
     if (o.contact) {
@@ -472,22 +478,30 @@ __device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const float
 }
 
 // Box-wise path of the production sweep.  As in sweep_unit_dense, each wave
-// takes one core box at a time with (target, stream) lanes over the box's
-// 27-box candidates, staged 64 at a time in the wave's LDS slice.  Each lane
-// only tests the pair against its contact reach; survivors go to a per-wave
-// queue and the contact math runs on full 64-pair drains (and on the rest at
-// the end of each staged chunk), with exact fixed-point LDS accumulators per
-// target.  The LDS tables of the unit path are free here.
+// takes one core box at a time with (target, stream) lanes.  The candidates
+// of all 27 boxes are staged in chunks of up to kDenseChunk per wave, all of
+// a chunk's loads in flight together, and shifted into the frame of the
+// targets' box.  Each lane only tests the pair against its contact reach;
+// survivors go to a per-wave queue and the contact math runs on full 64-pair
+// drains (and on the rest at the end of each chunk), with exact fixed-point
+// LDS accumulators per target.  The LDS tables of the unit path are free here.
 __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<false> &L, int P, int lp, int qx, int qy,
                                    int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
-    static_assert(kStage >= 512 && sizeof(L.task) >= 4 * 64 * 4 * sizeof(unsigned long long),
-                  "per wave: 64 staged candidates and 64 targets in the stage, 64 accumulators in the task list");
+    static_assert(4 * kDenseChunk <= kStage + 1, "per wave: a chunk of candidates in the stage");
+    static_assert(offsetof(SweepLds<false>, acm) == offsetof(SweepLds<false>, acc) + sizeof(L.acc) &&
+                      sizeof(L.acc) + sizeof(L.acm) >= 4 * 64 * sizeof(float4) + 4 * kDenseChunk * sizeof(uint32_t),
+                  "per wave: 64 targets and the candidates' slots in the accumulator arrays");
+    static_assert(sizeof(L.task) >= 4 * 64 * 4 * sizeof(unsigned long long), "per wave: 64 target accumulators");
+    static_assert(sizeof(L.tmap) >= 4 * 2 * 28 * sizeof(uint32_t), "per wave: the 27-box prefix and sources");
     const int64_t A = d.A;
     const float Lf = (float)S.L;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    float4 *buf = L.sp + 64 * w;                // staged candidates
-    float4 *ob = L.sp + 256 + 64 * w;           // the targets of the pass
+    float4 *buf = L.sp + kDenseChunk * w;                                       // staged candidates
+    float4 *ob = reinterpret_cast<float4 *>(&L.acc[0][0]) + 64 * w;            // the targets of the pass
+    uint32_t *cs = reinterpret_cast<uint32_t *>(reinterpret_cast<float4 *>(&L.acc[0][0]) + 256) + kDenseChunk * w;
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(L.task) + 256 * w;
+    uint32_t *pre = reinterpret_cast<uint32_t *>(L.tmap) + 56 * w;  // 28 prefix entries, then 27 box sources
+    uint32_t *src = pre + 28;
     uint32_t *qw = L.queue[w];
     for (int c = w; c < kCore; c += blockDim.x >> 6) {
         int cx, cy, cz;
@@ -496,6 +510,23 @@ __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<fals
         const uint32_t cnt = L.sbeg[lb + 1] - L.sbeg[lb];
         if (cnt == 0) continue;
         const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
+        // prefix of the candidate counts of the 27 boxes (lane b: box b, x fastest)
+        uint32_t nnb = 0, srcb = 0;
+        if (lane < 27) {
+            const int lbb = (cx + lane % 3) + kHalo * ((cy + lane / 3 % 3) + kHalo * (cz + lane / 9));
+            nnb = L.sbeg[lbb + 1] - L.sbeg[lbb];
+            srcb = L.gsrc[lbb];
+        }
+        uint32_t inc = nnb;
+        for (int off = 1; off < 32; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off);
+            if (lane >= off) inc += o;
+        }
+        const uint32_t T = __shfl(inc, 26);  // candidates of the 27 boxes
+        __builtin_amdgcn_wave_barrier();
+        if (lane < 28) pre[lane] = inc - nnb;  // lane 27: T
+        if (lane < 27) src[lane] = srcb;
+        __builtin_amdgcn_wave_barrier();
         for (uint32_t p0 = 0; p0 < cnt;) {
             int gsz = 1;
             while (gsz < 64 && (uint32_t)gsz < cnt - p0) gsz <<= 1;
@@ -503,7 +534,8 @@ __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<fals
             const int tl = lane & (gsz - 1), sid = lane / gsz;
             const uint32_t k = p0 + (uint32_t)tl;
             const bool tv = k < cnt;
-            const uint32_t slot = L.gsrc[lb] + (tv ? k : 0u);
+            const uint32_t tslot0 = L.gsrc[lb] + p0;
+            const uint32_t slot = tslot0 + (tv ? (uint32_t)tl : 0u);
             const int64_t i = d.sorted_idx[slot];
             const uint8_t fl = d.flags[lp][i];
             const bool stat = tv && S.detect_static && (fl & kStatic);
@@ -521,55 +553,78 @@ __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<fals
             __builtin_amdgcn_wave_barrier();
             const float owg = own.w + g;
             uint32_t qn = 0;  // wave-uniform queue fill
-            for (int oz = -1; oz <= 1; ++oz)
-                for (int oy = -1; oy <= 1; ++oy) {
-                    const int row = cx + kHalo * ((cy + 1 + oy) + kHalo * (cz + 1 + oz));
-                    const float fy = (float)oy * Lf, fz = (float)oz * Lf;
-                    const float qy2 = own.y - fy, qz2 = own.z - fz;
-                    for (int ox = -1; ox <= 1; ++ox) {
-                        const int lbb = row + ox + 1;
-                        const float fx = (float)ox * Lf;
-                        const float qx2 = own.x - fx;
-                        const uint32_t b0 = L.gsrc[lbb], nn = L.sbeg[lbb + 1] - L.sbeg[lbb];
-                        for (uint32_t c0 = 0; c0 < nn; c0 += 64) {
-                            const uint32_t mc = nn - c0 < 64u ? nn - c0 : 64u;
-                            __builtin_amdgcn_wave_barrier();
-                            if ((uint32_t)lane < mc) buf[lane] = d.payload[b0 + c0 + (uint32_t)lane];
-                            __builtin_amdgcn_wave_barrier();
-                            for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
-                                const uint32_t j = j0 + (uint32_t)sid;
-                                const bool in = j < mc && act && b0 + c0 + j != slot;
-                                const float4 cc = buf[j < mc ? j : 0u];
-                                const float ddx = qx2 - cc.x, ddy = qy2 - cc.y, ddz = qz2 - cc.z;
-                                const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                                const float sg = owg + cc.w;  // the reach test of pair_math
-                                const bool hit = in && d2 < sg * sg;
-                                const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-                                if (m) {
-                                    if (hit)
-                                        qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
-                                            (uint32_t)tl | (j << 6);
-                                    qn += (uint32_t)__popcll(m);
-                                    if (qn >= 64) {
-                                        __builtin_amdgcn_wave_barrier();
-                                        drain_dense(qw, 64u, ob, buf, acc, fx, fy, fz, e, g, kf, gf, L2m, L2p);
-                                        __builtin_amdgcn_wave_barrier();
-                                        qn -= 64;
-                                        if ((uint32_t)lane < qn) qw[lane] = qw[64 + lane];
-                                        __builtin_amdgcn_wave_barrier();
-                                    }
-                                }
+            for (uint32_t cb0 = 0; cb0 < T; cb0 += kDenseChunk) {
+                const uint32_t mc = T - cb0 < (uint32_t)kDenseChunk ? T - cb0 : (uint32_t)kDenseChunk;
+                // stage the chunk, two candidates per lane at a time: the loads
+                // first, then the shift into the targets' frame (box b is at
+                // offset (b % 3 - 1, b / 3 % 3 - 1, b / 9 - 1) boxes)
+                for (uint32_t q0 = (uint32_t)lane; q0 < mc; q0 += 128u) {
+                    float4 v[2];
+                    uint32_t vs[2];
+                    int vb[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t q = q0 + 64u * (uint32_t)h;
+                        vb[h] = 0;
+                        if (q < mc) {
+                            const uint32_t kk = cb0 + q;
+                            int lo = 0, hi = 27;  // the box of candidate kk: largest b with pre[b] <= kk
+                            while (hi - lo > 1) {
+                                const int mid = (lo + hi) >> 1;
+                                if (pre[mid] <= kk) lo = mid; else hi = mid;
                             }
-                            if (qn) {  // the chunk is restaged next: drain the rest now
-                                __builtin_amdgcn_wave_barrier();
-                                drain_dense(qw, qn, ob, buf, acc, fx, fy, fz, e, g, kf, gf, L2m, L2p);
-                                qn = 0;
-                            }
+                            vb[h] = lo;
+                            vs[h] = src[lo] + (kk - pre[lo]);
+                            v[h] = d.payload[vs[h]];
+                        }
+                    }
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const uint32_t q = q0 + 64u * (uint32_t)h;
+                        if (q < mc) {
+                            const int b = vb[h];
+                            float4 cc = v[h];
+                            cc.x += (float)(b % 3 - 1) * Lf;
+                            cc.y += (float)(b / 3 % 3 - 1) * Lf;
+                            cc.z += (float)(b / 9 - 1) * Lf;
+                            buf[q] = cc;
+                            cs[q] = vs[h];
                         }
                     }
                 }
-            __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_wave_barrier();
+                for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
+                    const uint32_t j = j0 + (uint32_t)sid;
+                    const bool in = j < mc && act;
+                    const float4 cc = buf[j < mc ? j : 0u];
+                    const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
+                    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                    const float sg = owg + cc.w;  // the reach test of pair_math
+                    const bool hit = in && d2 < sg * sg;
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                    if (m) {
+                        if (hit)
+                            qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                                (uint32_t)tl | (j << 6);
+                        qn += (uint32_t)__popcll(m);
+                        if (qn >= 64) {
+                            __builtin_amdgcn_wave_barrier();
+                            drain_dense(qw, 64u, ob, buf, cs, tslot0, acc, e, g, kf, gf, L2m, L2p);
+                            __builtin_amdgcn_wave_barrier();
+                            qn -= 64;
+                            if ((uint32_t)lane < qn) qw[lane] = qw[64 + lane];
+                            __builtin_amdgcn_wave_barrier();
+                        }
+                    }
+                }
+                if (qn) {  // the chunk is restaged next: drain the rest now
+                    __builtin_amdgcn_wave_barrier();
+                    drain_dense(qw, qn, ob, buf, cs, tslot0, acc, e, g, kf, gf, L2m, L2p);
+                    qn = 0;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
             p0 += (uint32_t)gsz;
             if (!act || sid != 0) continue;
             const unsigned long long am = acc[4 * tl + 3];

@@ -41,16 +41,25 @@ def test_c0_every_iteration_matches_oracle_single_step(abm, detect_static, workl
         st = H.gpu_state(abm, b)
 
 
-@pytest.mark.parametrize("detect_static,workload", [(False, "c0"), (True, "relaxed_lattice"), (False, "dense")])
+@pytest.mark.parametrize("detect_static,workload", [(False, "c0"), (True, "relaxed_lattice"), (False, "dense"),
+                                                     (False, "dense_small"), (False, "packed")])
 def test_production_path_single_step_matches_oracle(abm, detect_static, workload):
     """The launch configuration of the benchmark (no diagnostics: row culling
-    and reach tests active) against the oracle, one iteration at a time."""
+    and reach tests active) against the oracle, one iteration at a time.  The
+    dense workloads overflow the LDS stage of a unit and take the box-wise
+    path: about 7 agents per box (one candidate chunk per core box), 19 small
+    agents per box (several chunks) and 80 per box (several passes over the
+    targets of a box, about ten chunks, most agents on the FP64 path)."""
     if workload == "c0":
         pos, diam = c0()
     elif workload == "relaxed_lattice":
         pos, diam = inputs.relaxed_lattice(16, seed=2)
-    else:  # twice the density of the uniform workload: more contacts per agent
+    elif workload == "dense":  # twice the density of the uniform workload: more contacts per agent
         pos, diam = inputs.plain(4096, 127.0, seed=9)
+    elif workload == "dense_small":
+        pos, diam = inputs.plain(4096, 90.0, seed=9, dmin=3.0, dmax=5.0)
+    else:
+        pos, diam = inputs.plain(4096, 55.0, seed=9)
     gp = H.gpu_params(abm, detect_static=detect_static)
     b = abm.Population(gp, pos, diam, capacity=4096, box_capacity=1 << 16)
     op = H.oracle_params(detect_static=detect_static)
