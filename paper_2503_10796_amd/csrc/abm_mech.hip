@@ -445,7 +445,7 @@ __device__ inline void acc_reduce_streams(Acc &a, int g) {
 // then added across lanes.  Payload is read from global memory in coalesced
 // chunks of 64 candidates staged in the wave's slice of the LDS stage.
 // Box-wise path of the production sweep: candidates per wave and chunk.
-constexpr int kDenseChunk = 224;
+constexpr int kDenseChunk = 192;
 
 // Drain of the box-wise path: lane l takes queue entry l (target lane |
 // candidate index in the staged chunk << 6) and adds the pair's contact
@@ -528,12 +528,14 @@ __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<fals
         if (lane < 27) src[lane] = srcb;
         __builtin_amdgcn_wave_barrier();
         for (uint32_t p0 = 0; p0 < cnt;) {
-            int gsz = 1;
-            while (gsz < 64 && (uint32_t)gsz < cnt - p0) gsz <<= 1;
+            // gsz targets in this pass, 64 / gsz streams each (the lanes past
+            // gsz * nstream idle); the queue needs no cross-lane sums, so any
+            // target count fills the lanes
+            const int gsz = cnt - p0 < 64u ? (int)(cnt - p0) : 64;
             const int nstream = 64 / gsz;
-            const int tl = lane & (gsz - 1), sid = lane / gsz;
+            const int tl = lane % gsz, sid = lane / gsz;
             const uint32_t k = p0 + (uint32_t)tl;
-            const bool tv = k < cnt;
+            const bool tv = sid < nstream;
             const uint32_t tslot0 = L.gsrc[lb] + p0;
             const uint32_t slot = tslot0 + (tv ? (uint32_t)tl : 0u);
             const int64_t i = d.sorted_idx[slot];
@@ -555,41 +557,42 @@ __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<fals
             uint32_t qn = 0;  // wave-uniform queue fill
             for (uint32_t cb0 = 0; cb0 < T; cb0 += kDenseChunk) {
                 const uint32_t mc = T - cb0 < (uint32_t)kDenseChunk ? T - cb0 : (uint32_t)kDenseChunk;
-                // stage the chunk, two candidates per lane at a time: the loads
-                // first, then the shift into the targets' frame (box b is at
-                // offset (b % 3 - 1, b / 3 % 3 - 1, b / 9 - 1) boxes)
-                for (uint32_t q0 = (uint32_t)lane; q0 < mc; q0 += 128u) {
-                    float4 v[2];
-                    uint32_t vs[2];
-                    int vb[2];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const uint32_t q = q0 + 64u * (uint32_t)h;
-                        vb[h] = 0;
-                        if (q < mc) {
-                            const uint32_t kk = cb0 + q;
-                            int lo = 0, hi = 27;  // the box of candidate kk: largest b with pre[b] <= kk
-                            while (hi - lo > 1) {
-                                const int mid = (lo + hi) >> 1;
-                                if (pre[mid] <= kk) lo = mid; else hi = mid;
-                            }
-                            vb[h] = lo;
-                            vs[h] = src[lo] + (kk - pre[lo]);
-                            v[h] = d.payload[vs[h]];
+                // stage the chunk (up to three candidates per lane, all loads in
+                // flight together): box and slot first (the slot goes to LDS at
+                // once, the boxes stay packed in one register), then the shift
+                // into the targets' frame (box b is at offset (b % 3 - 1,
+                // b / 3 % 3 - 1, b / 9 - 1) boxes)
+                static_assert(kDenseChunk <= 3 * 64, "three candidates per lane");
+                uint32_t vb = 0;
+                for (int h = 0; h < 3; ++h) {
+                    const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
+                    if (q < mc) {
+                        const uint32_t kk = cb0 + q;
+                        int lo = 0, hi = 27;  // the box of candidate kk: largest b with pre[b] <= kk
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (pre[mid] <= kk) lo = mid; else hi = mid;
                         }
+                        vb |= (uint32_t)lo << (8 * h);
+                        cs[q] = src[lo] + (kk - pre[lo]);
                     }
+                }
+                float4 v[3];
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const uint32_t q = q0 + 64u * (uint32_t)h;
-                        if (q < mc) {
-                            const int b = vb[h];
-                            float4 cc = v[h];
-                            cc.x += (float)(b % 3 - 1) * Lf;
-                            cc.y += (float)(b / 3 % 3 - 1) * Lf;
-                            cc.z += (float)(b / 9 - 1) * Lf;
-                            buf[q] = cc;
-                            cs[q] = vs[h];
-                        }
+                for (int h = 0; h < 3; ++h) {
+                    const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
+                    if (q < mc) v[h] = d.payload[cs[q]];
+                }
+#pragma unroll
+                for (int h = 0; h < 3; ++h) {
+                    const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
+                    if (q < mc) {
+                        const int b = (int)((vb >> (8 * h)) & 0xffu);
+                        float4 cc = v[h];
+                        cc.x += (float)(b % 3 - 1) * Lf;
+                        cc.y += (float)(b / 3 % 3 - 1) * Lf;
+                        cc.z += (float)(b / 9 - 1) * Lf;
+                        buf[q] = cc;
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
