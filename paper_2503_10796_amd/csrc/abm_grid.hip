@@ -254,16 +254,34 @@ __global__ void __launch_bounds__(256) k_bin(Dev d, const SimDesc *__restrict__ 
 // Exclusive scan of per-box counts (Morton-rank order) into slot starts.
 // The scan kernels serve the grid build (resort = 0) and the Morton re-sort
 // (resort = 1: they do nothing in iterations without a re-sort).
-__global__ void __launch_bounds__(256) k_scan_tiles(Dev d, int resort) {
+// Four consecutive box counts of a thread: one 16-byte load where the four
+// lie in range and the address is 16-byte aligned (box ranges of a batch
+// start at arbitrary offsets), else one by one.
+__device__ inline void load_counts4(const uint32_t *count, int64_t at, int64_t k0, int64_t nboxes, uint32_t v[4]) {
+    if (k0 + 4 <= nboxes && (at & 3) == 0) {
+        const uint4 c = *reinterpret_cast<const uint4 *>(count + at);
+        v[0] = c.x;
+        v[1] = c.y;
+        v[2] = c.z;
+        v[3] = c.w;
+    } else {
+        for (int q = 0; q < 4; ++q) v[q] = (k0 + q < nboxes) ? count[at + q] : 0u;
+    }
+}
+
+// (sims, btiles: the descriptors and the box-tile prefix, read-only and not
+// aliased, so that their wave-uniform reads are scalar loads)
+__global__ void __launch_bounds__(256) k_scan_tiles(Dev d, const SimDesc *__restrict__ sims,
+                                                    const int64_t *__restrict__ btiles, int resort) {
     if (ABM_ABORTED(d) || (resort && !d.ctl->resort_now)) return;
     __shared__ uint32_t sh[4];
     const int64_t total = d.ctl->total_btiles;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t k0 = (t - d.btile_begin[s]) * kBoxTile + threadIdx.x * 4;
+        int s = find_sim(btiles, d.n_sims, t);
+        const SimDesc &S = sims[s];
+        int64_t k0 = (t - btiles[s]) * kBoxTile + threadIdx.x * 4;
         uint32_t v[4];
-        for (int q = 0; q < 4; ++q) v[q] = (k0 + q < S.nboxes) ? d.count[S.b_off + k0 + q] : 0u;
+        load_counts4(d.count, S.b_off + k0, k0, S.nboxes, v);
         uint32_t tot;
         block_excl_scan_4(v, sh, tot);
         if (threadIdx.x == 0) d.tile_sum[t] = tot;
@@ -305,27 +323,35 @@ __global__ void __launch_bounds__(1024) k_scan_top(Dev d, int resort) {
 }
 
 // box_start[sb_off + m] = a_off + prefix; zeroes the counts.
-__global__ void __launch_bounds__(256) k_scan_apply(Dev d, int resort) {
+__global__ void __launch_bounds__(256) k_scan_apply(Dev d, const SimDesc *__restrict__ sims,
+                                                    const int64_t *__restrict__ btiles, int resort) {
     if (ABM_ABORTED(d) || (resort && !d.ctl->resort_now)) return;
     __shared__ uint32_t sh[4];
     const int64_t total = d.ctl->total_btiles;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        int64_t k0 = (t - d.btile_begin[s]) * kBoxTile + threadIdx.x * 4;
+        int s = find_sim(btiles, d.n_sims, t);
+        const SimDesc &S = sims[s];
+        int64_t k0 = (t - btiles[s]) * kBoxTile + threadIdx.x * 4;
         uint32_t v[4];
-        for (int q = 0; q < 4; ++q) v[q] = (k0 + q < S.nboxes) ? d.count[S.b_off + k0 + q] : 0u;
+        load_counts4(d.count, S.b_off + k0, k0, S.nboxes, v);
         uint32_t tot;
         uint32_t pre = block_excl_scan_4(v, sh, tot);
-        uint32_t base = (uint32_t)S.a_off + d.tile_off[t] + pre;
-        for (int q = 0; q < 4; ++q) {
-            if (k0 + q < S.nboxes) {
-                d.box_start[S.sb_off + k0 + q] = base;
-                d.count[S.b_off + k0 + q] = 0u;
-            }
-            base += v[q];
+        const uint32_t base = (uint32_t)S.a_off + d.tile_off[t] + pre;
+        const uint32_t st[4] = {base, base + v[0], base + v[0] + v[1], base + v[0] + v[1] + v[2]};
+        const bool full = k0 + 4 <= S.nboxes;
+        if (full && ((S.sb_off + k0) & 3) == 0) {
+            *reinterpret_cast<uint4 *>(d.box_start + S.sb_off + k0) = make_uint4(st[0], st[1], st[2], st[3]);
+        } else {
+            for (int q = 0; q < 4; ++q)
+                if (k0 + q < S.nboxes) d.box_start[S.sb_off + k0 + q] = st[q];
         }
-        if (t == d.btile_begin[s + 1] - 1 && threadIdx.x == 0)
+        if (full && ((S.b_off + k0) & 3) == 0) {
+            *reinterpret_cast<uint4 *>(d.count + S.b_off + k0) = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int q = 0; q < 4; ++q)
+                if (k0 + q < S.nboxes) d.count[S.b_off + k0 + q] = 0u;
+        }
+        if (t == btiles[s + 1] - 1 && threadIdx.x == 0)
             d.box_start[S.sb_off + S.nboxes] = (uint32_t)(S.a_off + S.n_start);
     }
 }
@@ -759,9 +785,11 @@ void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_b
     hipLaunchKernelGGL(k_grid_done, dim3(1), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_bin, dim3(grid_agents), dim3(256), 0, st, d, (const SimDesc *)d.sims,
                        (const int64_t *)d.tile_begin);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d, 0);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                       (const int64_t *)d.btile_begin, 0);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d, 0);
-    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d, 0);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                       (const int64_t *)d.btile_begin, 0);
     hipLaunchKernelGGL(k_scatter, dim3(grid_agents), dim3(256), 0, st, d, (const SimDesc *)d.sims,
                        (const int64_t *)d.tile_begin);
     if (any_static) {
@@ -773,9 +801,11 @@ void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_b
 void launch_resort(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool force, bool any_static) {
     if (force) hipLaunchKernelGGL(k_force_resort, dim3(1), dim3(64), 0, st, d);
     hipLaunchKernelGGL(k_rs_count, dim3(grid_agents), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d, 1);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(grid_boxes), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                       (const int64_t *)d.btile_begin, 1);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, st, d, 1);
-    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d, 1);
+    hipLaunchKernelGGL(k_scan_apply, dim3(grid_boxes), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                       (const int64_t *)d.btile_begin, 1);
     hipLaunchKernelGGL(k_rs_dest, dim3(grid_agents), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_rs_move, dim3(grid_agents), dim3(256), 0, st, d);
     if (any_static) hipLaunchKernelGGL(k_rs_sync, dim3(grid_agents), dim3(256), 0, st, d);
