@@ -390,55 +390,69 @@ __global__ void __launch_bounds__(256) k_scatter(Dev d, const SimDesc *__restric
 // agent were marked by k_bin.
 // One wave per aligned block; only blocks next to an arrival can lose a
 // static flag (or every block, when the box length shrank).
-__global__ void __launch_bounds__(256) k_static_fix(Dev d) {
+// Each wave takes 64 aligned blocks at a time: every lane checks one whether
+// it needs a visit, and the wave then visits those blocks one by one.
+// (sims, btiles: read-only and not aliased, so that their wave-uniform reads
+// are scalar loads.)
+__global__ void __launch_bounds__(256) k_static_fix(Dev d, const SimDesc *__restrict__ sims,
+                                                    const int64_t *__restrict__ btiles) {
     if (ABM_ABORTED(d)) return;
     constexpr int kTB = kBoxTile / 64;
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const int64_t A = d.A;
     const int64_t nq = d.ctl->total_btiles * kTB;
     const int lane = threadIdx.x & 63;
-    for (int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q < nq; q += (int64_t)gridDim.x * 4) {
-        const int64_t t = q / kTB;
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        if (!S.detect_static) continue;
-        const int64_t blk = (t - d.btile_begin[s]) * kTB + q % kTB;
-        if (blk >= S.nblocks) continue;
-        const bool shrunk = !(S.L >= S.L_prev);  // a shrunken grid cannot cover the old radius: be conservative
-        if (!shrunk && !d.near_blk[S.b_off + blk]) continue;
-        const uint32_t s0 = d.box_start[S.sb_off + blk * 64], s1 = d.box_start[S.sb_off + blk * 64 + 64];
-        for (uint32_t slot0 = s0; slot0 < s1; slot0 += 64) {
-            const uint32_t slot = slot0 + (uint32_t)lane;
-            if (slot >= s1) continue;
-            const int64_t i = d.sorted_idx[slot];
-            const uint8_t fl = d.flags[lp][i];
-            if (!(fl & kStatic)) continue;
-            bool st = !shrunk;
-            int bx, by, bz;
-            unpack_key(d.key[i], bx, by, bz);
-            if (st) {
-                const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
-                const double L2 = S.L_prev * S.L_prev;
-                for (int oz = -1; oz <= 1 && st; ++oz)
-                    for (int oy = -1; oy <= 1 && st; ++oy)
-                        for (int ox = -1; ox <= 1 && st; ++ox) {
-                            int cx = bx + ox, cy = by + oy, cz = bz + oz;
-                            if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2])
-                                continue;
-                            uint32_t m = box_rank(d, S, cx, cy, cz);
-                            if (!d.arrive[S.b_off + m]) continue;
-                            uint32_t b0 = d.box_start[S.sb_off + m], b1 = d.box_start[S.sb_off + m + 1];
-                            for (uint32_t sl = b0; sl < b1 && st; ++sl) {
-                                int64_t j = d.sorted_idx[sl];
-                                if (j == i || !(d.flags[lp][j] & kChgMask)) continue;
-                                if (near_point(x, y, z, d.pos[P][j], d.pos[P][A + j], d.pos[P][2 * A + j], L2))
-                                    st = false;
+    for (int64_t q0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; q0 < nq; q0 += (int64_t)gridDim.x * 256) {
+        bool need = false;
+        if (q0 + lane < nq) {
+            const int64_t tl = (q0 + lane) / kTB;
+            const int sl = find_sim(btiles, d.n_sims, tl);
+            const SimDesc &Sl = sims[sl];
+            const int64_t bl = (tl - btiles[sl]) * kTB + (q0 + lane) % kTB;
+            // a shrunken grid cannot cover the old radius: every block is visited
+            need = Sl.detect_static && bl < Sl.nblocks && (!(Sl.L >= Sl.L_prev) || d.near_blk[Sl.b_off + bl]);
+        }
+        for (uint64_t mv = __builtin_amdgcn_ballot_w64(need); mv; mv &= mv - 1) {
+            const int64_t q = q0 + (__ffsll((long long)mv) - 1);
+            const int64_t t = q / kTB;
+            int s = find_sim(btiles, d.n_sims, t);
+            const SimDesc &S = sims[s];
+            const int64_t blk = (t - btiles[s]) * kTB + q % kTB;
+            const bool shrunk = !(S.L >= S.L_prev);  // a shrunken grid cannot cover the old radius: be conservative
+            const uint32_t s0 = d.box_start[S.sb_off + blk * 64], s1 = d.box_start[S.sb_off + blk * 64 + 64];
+            for (uint32_t slot0 = s0; slot0 < s1; slot0 += 64) {
+                const uint32_t slot = slot0 + (uint32_t)lane;
+                if (slot >= s1) continue;
+                const int64_t i = d.sorted_idx[slot];
+                const uint8_t fl = d.flags[lp][i];
+                if (!(fl & kStatic)) continue;
+                bool st = !shrunk;
+                int bx, by, bz;
+                unpack_key(d.key[i], bx, by, bz);
+                if (st) {
+                    const double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
+                    const double L2 = S.L_prev * S.L_prev;
+                    for (int oz = -1; oz <= 1 && st; ++oz)
+                        for (int oy = -1; oy <= 1 && st; ++oy)
+                            for (int ox = -1; ox <= 1 && st; ++ox) {
+                                int cx = bx + ox, cy = by + oy, cz = bz + oz;
+                                if (cx < 0 || cy < 0 || cz < 0 || cx >= S.dims[0] || cy >= S.dims[1] || cz >= S.dims[2])
+                                    continue;
+                                uint32_t m = box_rank(d, S, cx, cy, cz);
+                                if (!d.arrive[S.b_off + m]) continue;
+                                uint32_t b0 = d.box_start[S.sb_off + m], b1 = d.box_start[S.sb_off + m + 1];
+                                for (uint32_t sl = b0; sl < b1 && st; ++sl) {
+                                    int64_t j = d.sorted_idx[sl];
+                                    if (j == i || !(d.flags[lp][j] & kChgMask)) continue;
+                                    if (near_point(x, y, z, d.pos[P][j], d.pos[P][A + j], d.pos[P][2 * A + j], L2))
+                                        st = false;
+                                }
                             }
-                        }
-            }
-            if (!st) {
-                d.flags[lp][i] = fl & ~kStatic;
-                d.active_blk[S.b_off + blk] = 1;
+                }
+                if (!st) {
+                    d.flags[lp][i] = fl & ~kStatic;
+                    d.active_blk[S.b_off + blk] = 1;
+                }
             }
         }
     }
@@ -794,7 +808,8 @@ void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_b
                        (const int64_t *)d.tile_begin);
     if (any_static) {
         launch_near_marks(d, st, grid_boxes, true);
-        hipLaunchKernelGGL(k_static_fix, dim3(grid_agents), dim3(256), 0, st, d);
+        hipLaunchKernelGGL(k_static_fix, dim3(grid_agents), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                           (const int64_t *)d.btile_begin);
     }
 }
 
