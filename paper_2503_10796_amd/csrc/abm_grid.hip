@@ -74,7 +74,11 @@ __device__ inline void bounds_flush(const Dev &d, int s, double acc[7], double (
     acc[6] = -__builtin_huge_val();
 }
 
-__global__ void __launch_bounds__(256) k_bounds(Dev d) {
+// (sims, tiles: read through non-aliased pointers, so that their wave-uniform
+// reads are scalar loads; the only write to a descriptor, the non-finite flag,
+// goes through d.sims to a field that is never read here)
+__global__ void __launch_bounds__(256) k_bounds(Dev d, const SimDesc *__restrict__ sims,
+                                                const int64_t *__restrict__ tiles) {
     if (ABM_ABORTED(d)) return;
     __shared__ double red[7][4];
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
@@ -85,11 +89,11 @@ __global__ void __launch_bounds__(256) k_bounds(Dev d) {
     acc[6] = -__builtin_huge_val();
     int cur = -1;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.tile_begin, d.n_sims, t);
+        int s = find_sim(tiles, d.n_sims, t);
         if (s != cur && cur >= 0) bounds_flush(d, cur, acc, red);
         cur = s;
-        const SimDesc &S = d.sims[s];
-        int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
+        const SimDesc &S = sims[s];
+        int64_t loc = (t - tiles[s]) * kTile + threadIdx.x;
         if (loc < S.n_start) {
             int64_t i = S.a_off + loc;
             double x = d.pos[P][i], y = d.pos[P][A + i], z = d.pos[P][2 * A + i];
@@ -492,15 +496,18 @@ __global__ void __launch_bounds__(256) k_near_marks(Dev d, int arrivals) {
 
 // Clears the dirty and arrival marks of the current grid: the 64 box marks
 // of every marked block, then the block marks (a box tile holds 16 blocks).
-__global__ void __launch_bounds__(256) k_clear_marks(Dev d) {
+// (sims, btiles: read-only and not aliased, so that their wave-uniform reads
+// are scalar loads)
+__global__ void __launch_bounds__(256) k_clear_marks(Dev d, const SimDesc *__restrict__ sims,
+                                                     const int64_t *__restrict__ btiles) {
     if (ABM_ABORTED(d)) return;
     const int64_t total = d.ctl->total_btiles;
     const int q = threadIdx.x >> 4, e = threadIdx.x & 15;  // block of the tile, 16 threads per block
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
+        int s = find_sim(btiles, d.n_sims, t);
+        const SimDesc &S = sims[s];
         if (!S.detect_static) continue;
-        const int64_t blk = (t - d.btile_begin[s]) * (kBoxTile / 64) + q;
+        const int64_t blk = (t - btiles[s]) * (kBoxTile / 64) + q;
         if (blk >= S.nblocks) continue;
         const int64_t bi = S.b_off + blk;
         if (!d.dirty_blk[bi] && !d.arrive_blk[bi]) continue;
@@ -511,10 +518,10 @@ __global__ void __launch_bounds__(256) k_clear_marks(Dev d) {
     }
     __syncthreads();
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        int s = find_sim(d.btile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
+        int s = find_sim(btiles, d.n_sims, t);
+        const SimDesc &S = sims[s];
         if (!S.detect_static || e != 0) continue;
-        const int64_t blk = (t - d.btile_begin[s]) * (kBoxTile / 64) + q;
+        const int64_t blk = (t - btiles[s]) * (kBoxTile / 64) + q;
         if (blk >= S.nblocks) continue;
         d.dirty_blk[S.b_off + blk] = 0;
         d.arrive_blk[S.b_off + blk] = 0;
@@ -793,7 +800,8 @@ __global__ void k_init_tiles(Dev d) {
 // ------------------------------------------------------------------ launchers
 void launch_grid_build(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool any_static) {
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_bounds, dim3(grid_agents), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_bounds, dim3(grid_agents), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                       (const int64_t *)d.tile_begin);
     hipLaunchKernelGGL(k_grid, dim3(1), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_brank, dim3(grid_boxes), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_grid_done, dim3(1), dim3(256), 0, st, d);
@@ -832,7 +840,9 @@ void launch_near_marks(const Dev &d, hipStream_t st, int grid_boxes, bool arriva
 }
 
 void launch_end(const Dev &d, hipStream_t st, int grid_boxes, bool any_static) {
-    if (any_static) hipLaunchKernelGGL(k_clear_marks, dim3(grid_boxes), dim3(256), 0, st, d);
+    if (any_static)
+        hipLaunchKernelGGL(k_clear_marks, dim3(grid_boxes), dim3(256), 0, st, d, (const SimDesc *)d.sims,
+                           (const int64_t *)d.btile_begin);
     hipLaunchKernelGGL(k_end, dim3(1), dim3(256), 0, st, d);
 }
 
