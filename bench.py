@@ -246,10 +246,16 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
-def mechanics_population(kind, agents, resort_every=10, sweep_grid=2048):
+# Sweep work groups per workload, from a scan of 1,024 to 4,096 on one MI355X
+# (1,024 is one resident block per LDS slot of the 256 CUs).
+SWEEP_GRID = {"uniform": 1024, "relaxed": 2048}
+
+
+def mechanics_population(kind, agents, resort_every=10, sweep_grid=None):
     """The mechanics workload at scale, in the launch configuration that is
-    timed: (population, agents, description).  The full-size parity tests
-    build their population through this function as well."""
+    timed: (population, agents, description, sweep work groups).  The
+    full-size parity tests build their population through this function as
+    well."""
     from paper_2503_10796_amd import abm, inputs
 
     if kind == "uniform":
@@ -270,8 +276,10 @@ def mechanics_population(kind, agents, resort_every=10, sweep_grid=2048):
     p = abm.params(box_len=15.0, resort_every=resort_every, detect_static=(kind == "relaxed"))
     pop = abm.Population(p, pos, diam, capacity=n, box_capacity=box_cap)
     del pos, diam
+    if sweep_grid is None:
+        sweep_grid = SWEEP_GRID[kind]
     pop.set_sweep_grid(sweep_grid)
-    return pop, n, workload
+    return pop, n, workload, sweep_grid
 
 
 def main():
@@ -289,7 +297,8 @@ def main():
                     help="sweep: time the batched path only (for kernel traces), no per-simulation comparison")
     ap.add_argument("--train-steps", type=int, default=3000, help="surrogate: Adam steps")
     ap.add_argument("--resort-every", type=int, default=10)
-    ap.add_argument("--sweep-grid", type=int, default=2048)
+    ap.add_argument("--sweep-grid", type=int, default=None,
+                    help="sweep work groups (default: 1024 for uniform, 2048 for relaxed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-agents", type=int, default=4_000_000)
     ap.add_argument("--cpu-sample-iters", type=int, default=8)
@@ -322,7 +331,8 @@ def main():
 
     abm.lib()
     t_gen = time.perf_counter()
-    pop, n, workload = mechanics_population(args.workload, args.agents, args.resort_every, args.sweep_grid)
+    pop, n, workload, sweep_grid = mechanics_population(args.workload, args.agents, args.resort_every,
+                                                        args.sweep_grid)
     log(f"[bench] generated and uploaded {n} agents in {time.perf_counter() - t_gen:.1f} s")
     pop.set_timing(True)  # graphs are captured during the warmup
     torch.cuda.synchronize()
@@ -361,7 +371,7 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": workload, "agents": n, "box_len_um": 15.0, "grid_boxes": nboxes,
-                   "static_fraction_end": static_frac, "sweep_workgroups": args.sweep_grid},
+                   "static_fraction_end": static_frac, "sweep_workgroups": sweep_grid},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sweep", "kernel_ms": sweep_avg_s * 1e3,

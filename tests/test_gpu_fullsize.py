@@ -101,7 +101,7 @@ def _check_step(abm, pop, op, rng, n_regions):
 @pytest.mark.parametrize("kind", ["uniform", "relaxed"])
 def test_full_size_sampled_agents_match_oracle(abm, kind):
     t0 = time.perf_counter()
-    pop, n, _ = bench.mechanics_population(kind, N_AGENTS)
+    pop, n, _, _ = bench.mechanics_population(kind, N_AGENTS)
     _say(f"[{kind}] {n} agents uploaded in {time.perf_counter() - t0:.1f} s")
     op = H.oracle_params(detect_static=(kind == "relaxed"))
     rng = np.random.default_rng(11)
