@@ -394,8 +394,10 @@ __global__ void __launch_bounds__(256) k_scatter(Dev d, const SimDesc *__restric
 // agent were marked by k_bin.
 // One wave per aligned block; only blocks next to an arrival can lose a
 // static flag (or every block, when the box length shrank).
-// Each wave takes 64 aligned blocks at a time: every lane checks one whether
-// it needs a visit, and the wave then visits those blocks one by one.
+// Each wave checks 64 aligned blocks at a time, one per lane, strided by the
+// number of waves of the grid (so that blocks to visit spread over all waves,
+// one per wave when there are few): whether a block needs a visit; the wave
+// then visits those blocks.
 // (sims, btiles: read-only and not aliased, so that their wave-uniform reads
 // are scalar loads.)
 __global__ void __launch_bounds__(256) k_static_fix(Dev d, const SimDesc *__restrict__ sims,
@@ -406,18 +408,20 @@ __global__ void __launch_bounds__(256) k_static_fix(Dev d, const SimDesc *__rest
     const int64_t A = d.A;
     const int64_t nq = d.ctl->total_btiles * kTB;
     const int lane = threadIdx.x & 63;
-    for (int64_t q0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; q0 < nq; q0 += (int64_t)gridDim.x * 256) {
+    const int64_t nw = (int64_t)gridDim.x * 4;  // waves of the grid
+    for (int64_t q0 = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q0 < nq; q0 += 64 * nw) {
+        const int64_t qc = q0 + lane * nw;  // the block this lane checks
         bool need = false;
-        if (q0 + lane < nq) {
-            const int64_t tl = (q0 + lane) / kTB;
+        if (qc < nq) {
+            const int64_t tl = qc / kTB;
             const int sl = find_sim(btiles, d.n_sims, tl);
             const SimDesc &Sl = sims[sl];
-            const int64_t bl = (tl - btiles[sl]) * kTB + (q0 + lane) % kTB;
+            const int64_t bl = (tl - btiles[sl]) * kTB + qc % kTB;
             // a shrunken grid cannot cover the old radius: every block is visited
             need = Sl.detect_static && bl < Sl.nblocks && (!(Sl.L >= Sl.L_prev) || d.near_blk[Sl.b_off + bl]);
         }
         for (uint64_t mv = __builtin_amdgcn_ballot_w64(need); mv; mv &= mv - 1) {
-            const int64_t q = q0 + (__ffsll((long long)mv) - 1);
+            const int64_t q = q0 + (__ffsll((long long)mv) - 1) * nw;
             const int64_t t = q / kTB;
             int s = find_sim(btiles, d.n_sims, t);
             const SimDesc &S = sims[s];

@@ -1498,9 +1498,10 @@ __global__ void __launch_bounds__(256) k_div_apply(Dev d) {
 // the next grid.
 // One wave per aligned block.  A block with no active agent and no changed
 // agent within one box keeps the flags of its agents: they stay static.
-// Each wave takes 64 aligned blocks at a time: every lane checks one whether
-// it needs a visit (near a change, or holding active agents), and the wave
-// then visits those blocks one by one.  (sims, btiles: read-only and not
+// Each wave checks 64 aligned blocks at a time, one per lane, strided by the
+// number of waves of the grid (so that blocks to visit spread over all waves,
+// one per wave when there are few): whether a block needs a visit (near a
+// change, or holding active agents); the wave then visits those blocks.  (sims, btiles: read-only and not
 // aliased, so that their wave-uniform reads are scalar loads.)
 __global__ void __launch_bounds__(256) k_static(Dev d, const SimDesc *__restrict__ sims,
                                                 const int64_t *__restrict__ btiles) {
@@ -1510,13 +1511,15 @@ __global__ void __launch_bounds__(256) k_static(Dev d, const SimDesc *__restrict
     const int64_t A = d.A;
     const int64_t nq = d.ctl->total_btiles * kTB;
     const int lane = threadIdx.x & 63;
-    for (int64_t q0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 64; q0 < nq; q0 += (int64_t)gridDim.x * 256) {
+    const int64_t nw = (int64_t)gridDim.x * 4;  // waves of the grid
+    for (int64_t q0 = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); q0 < nq; q0 += 64 * nw) {
+        const int64_t qc = q0 + lane * nw;  // the block this lane checks
         uint32_t need = 0;  // bit 0: visit, bit 1: near a change
-        if (q0 + lane < nq) {
-            const int64_t tl = (q0 + lane) / kTB;
+        if (qc < nq) {
+            const int64_t tl = qc / kTB;
             const int sl = find_sim(btiles, d.n_sims, tl);
             const SimDesc &Sl = sims[sl];
-            const int64_t bl = (tl - btiles[sl]) * kTB + (q0 + lane) % kTB;
+            const int64_t bl = (tl - btiles[sl]) * kTB + qc % kTB;
             if (Sl.detect_static && bl < Sl.nblocks) {
                 const bool nr = d.near_blk[Sl.b_off + bl] != 0;
                 need = (nr || d.active_blk[Sl.b_off + bl]) ? (nr ? 3u : 1u) : 0u;
@@ -1524,7 +1527,7 @@ __global__ void __launch_bounds__(256) k_static(Dev d, const SimDesc *__restrict
         }
         for (uint64_t mv = __builtin_amdgcn_ballot_w64(need != 0); mv; mv &= mv - 1) {
             const int l = __ffsll((long long)mv) - 1;
-            const int64_t q = q0 + l;
+            const int64_t q = q0 + l * nw;
             const bool near = (__shfl(need, l) & 2u) != 0;
             const int64_t t = q / kTB;
             int s = find_sim(btiles, d.n_sims, t);
