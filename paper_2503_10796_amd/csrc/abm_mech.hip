@@ -11,7 +11,8 @@
 // with each XCD taking a contiguous range (its L2 then holds the shared halo).
 // A workgroup stages the FP32 payload of the block and its one-box halo
 // (6x6x6 boxes, about 730 agents at 3.4 agents per box) into LDS with
-// coalesced reads, then each thread sweeps one target's 27 boxes from LDS.
+// coalesced reads, then sweeps the targets' candidate rows from LDS as
+// length-sorted tasks, one per lane.
 //
 // Forces are summed as exact 64-bit fixed-point integers (2^-40 units), so the
 // result does not depend on the order in which neighbours are visited: every
@@ -123,10 +124,11 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
 // Per work unit (an aligned 4x4x4 block of boxes):
 //   table    start and count of the 6x6x6 staged boxes (block scan)
 //   stage    FP32 payload of the region into LDS, relative to its centre
-//   setup    per target: static skip (Sec 5.5) or nine tasks, one per row of
-//            three boxes (x-1..x+1) of its 27-box neighbourhood; the tasks
-//            are counting-sorted by row length, so the 64 lanes of a wave
-//            hold rows of about equal length and run equal trip counts
+//   setup    per target: static skip (Sec 5.5) or up to ten tasks, one per row
+//            of three boxes (x-1..x+1) of its 27-box neighbourhood trimmed to
+//            the reach (plus the own row's halo box under the half shell); the
+//            tasks are counting-sorted by row length, so the 64 lanes of a
+//            wave hold rows of about equal length and run equal trip counts
 //   sweep    each lane tests its row against the pair's contact reach plus
 //            the guard band; survivors go to a per-wave LDS queue, which is
 //            drained 64 pairs at a time through the contact math (Eq 4.1-4.2)
@@ -437,13 +439,6 @@ __device__ inline void acc_reduce_streams(Acc &a, int g) {
     }
 }
 
-// Dense units (region larger than the LDS stage, or more targets than kMaxT):
-// each wave takes one core box at a time.  All targets of a box share its
-// 27-box candidate set, so the lanes hold (target, stream) pairs, g targets
-// by 64 / g streams, and walk the candidates in wave-uniform loops with the
-// streams interleaved; the exact fixed-point sums of a target's streams are
-// then added across lanes.  Payload is read from global memory in coalesced
-// chunks of 64 candidates staged in the wave's slice of the LDS stage.
 // Box-wise path of the production sweep: candidates per wave and chunk.
 constexpr int kDenseChunk = 192;
 
@@ -653,6 +648,15 @@ __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<fals
     }
 }
 
+// Dense units (region larger than the LDS stage, or more targets than
+// kMaxT), diagnostic form: each wave takes one core box at a time.  All
+// targets of a box share its 27-box candidate set, so the lanes hold (target,
+// stream) pairs, g targets by 64 / g streams, and walk the candidates in
+// wave-uniform loops with the streams interleaved, the contact math inline for
+// every candidate (every neighbour within the box length is counted); the
+// exact fixed-point sums of a target's streams are then added across lanes.
+// Payload is read from global memory in coalesced chunks of 64 candidates
+// staged in the wave's slice of the LDS stage.
 template <bool DIAG>
 __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> &L, int P, int lp, int qx, int qy,
                                  int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
@@ -1588,7 +1592,7 @@ void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag, bool 
 // the committed state.
 void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool diag, bool any_growth,
                         bool any_static, bool resort) {
-    // one wave per agent on the FP64 path (16384 waves, grid-stride beyond)
+    // two agents per wave on the FP64 path (32768 at a time, grid-stride beyond)
     const SimDesc *sims = d.sims;
     const int64_t *a_begin = d.a_begin;
     if (diag) hipLaunchKernelGGL(k_fixup<true>, dim3(4096), dim3(256), 0, st, d, sims, a_begin);
