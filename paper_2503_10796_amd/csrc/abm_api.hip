@@ -222,7 +222,7 @@ struct abm_batch {
 static void destroy_graphs(abm_batch *b) {
     for (int part = 0; part < 3; ++part)
         for (int k = 0; k < 2; ++k) {
-            if (b->exec[part][k]) hipGraphExecDestroy(b->exec[part][k]);
+            if (b->exec[part][k]) (void)hipGraphExecDestroy(b->exec[part][k]);  // teardown: nothing to recover
             b->exec[part][k] = nullptr;
         }
 }
@@ -248,7 +248,7 @@ static int capture(abm_batch *b, int part, int diag) {
     hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (e != hipSuccess) return fail(ABM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&b->exec[part][diag], g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);  // the instantiated graph no longer needs its template
     if (e != hipSuccess) return fail(ABM_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
     return ABM_OK;
 }
@@ -787,31 +787,41 @@ extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out) {
     HIPCHK(hipMalloc(&snap, bytes));
     hipStream_t st = b->stream;
     hipError_t e = hipMemcpyAsync(snap, b->ws, bytes, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) { hipFree(snap); return fail(ABM_ERR_HIP, "snapshot copy failed"); }
+    if (e != hipSuccess) {
+        (void)hipFree(snap);
+        return fail(ABM_ERR_HIP, "snapshot copy failed: %s", hipGetErrorString(e));
+    }
     const int grids[4] = {512, 1024, 2048, 4096};
     const int resorts[4] = {0, 5, 10, 20};
     bool tune_resort = false;
     for (auto &S : b->host_sims) tune_resort |= S.resort_every < 0;
     int best_grid = b->sweep_grid, best_resort = b->resort_every;
     float best = 1e30f;
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ABM_OK;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        rc = fail(ABM_ERR_HIP, "event creation failed: %s", hipGetErrorString(e));
+    // the first failing call of a trial ends the tuning (the batch is restored below)
+#define TUNECHK(expr)                                                                             \
+    if ((e = (expr)) != hipSuccess) {                                                             \
+        rc = fail(ABM_ERR_HIP, "autotuner: %s: %s", #expr, hipGetErrorString(e));                \
+        break;                                                                                    \
+    }
     for (int bi = 0; bi < 4 && rc == ABM_OK; ++bi) {
         for (int ri = 0; ri < (tune_resort ? 4 : 1) && rc == ABM_OK; ++ri) {
             b->sweep_grid = grids[bi];
             if (tune_resort) b->resort_every = resorts[ri];
             destroy_graphs(b);
             if ((rc = capture(b, 0, 0))) break;
-            hipMemcpyAsync(b->ws, snap, bytes, hipMemcpyDeviceToDevice, st);
-            hipGraphLaunch(b->exec[0][0], st);  // warm-up
-            hipEventRecord(e0, st);
-            for (int it = 0; it < n_trial_iters; ++it) hipGraphLaunch(b->exec[0][0], st);
-            hipEventRecord(e1, st);
-            hipEventSynchronize(e1);
+            TUNECHK(hipMemcpyAsync(b->ws, snap, bytes, hipMemcpyDeviceToDevice, st));
+            TUNECHK(hipGraphLaunch(b->exec[0][0], st));  // warm-up
+            TUNECHK(hipEventRecord(e0, st));
+            for (int it = 0; it < n_trial_iters && e == hipSuccess; ++it) e = hipGraphLaunch(b->exec[0][0], st);
+            TUNECHK(e);
+            TUNECHK(hipEventRecord(e1, st));
+            TUNECHK(hipEventSynchronize(e1));
             float ms = 0.0f;
-            hipEventElapsedTime(&ms, e0, e1);
+            TUNECHK(hipEventElapsedTime(&ms, e0, e1));
             Ctl c;
             if ((rc = read_ctl(b, c))) break;
             if (!c.abort && ms < best) {
@@ -821,11 +831,15 @@ extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out) {
             }
         }
     }
-    hipMemcpyAsync(b->ws, snap, bytes, hipMemcpyDeviceToDevice, st);
-    hipStreamSynchronize(st);
-    hipFree(snap);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+#undef TUNECHK
+    // restore the batch as it was before the trials
+    if ((e = hipMemcpyAsync(b->ws, snap, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        if (rc == ABM_OK) rc = fail(ABM_ERR_HIP, "autotuner: restoring the batch failed: %s", hipGetErrorString(e));
+    }
+    (void)hipFree(snap);  // teardown: nothing to recover
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (rc) return rc;
     b->sweep_grid = best_grid;
     b->resort_every = best_resort;
@@ -855,8 +869,8 @@ extern "C" int abm_batch_destroy(abm_batch *b) {
     g_err.clear();
     if (!b) return ABM_OK;
     destroy_graphs(b);
-    for (hipEvent_t e : b->ev) hipEventDestroy(e);
-    if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);  // teardown: nothing to recover
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     delete b;
     return ABM_OK;
 }

@@ -529,7 +529,6 @@ __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<fals
             const int gsz = cnt - p0 < 64u ? (int)(cnt - p0) : 64;
             const int nstream = 64 / gsz;
             const int tl = lane % gsz, sid = lane / gsz;
-            const uint32_t k = p0 + (uint32_t)tl;
             const bool tv = sid < nstream;
             const uint32_t tslot0 = L.gsrc[lb] + p0;
             const uint32_t slot = tslot0 + (tv ? (uint32_t)tl : 0u);
