@@ -159,7 +159,7 @@ struct SweepLds {
     uint32_t gsrc[kNb];                     // global slot start of every staged box
     uint32_t coff[kCore + 1];               // prefix of the target counts of the core boxes
     uint32_t bcnt[kBuckets], boff[kBuckets];
-    uint32_t queue[4][kQueue];
+    uint32_t queue[4][kQueue + 1];          // (+1: a spare slot that lanes without a survivor write)
     uint32_t sh[4];                         // per-wave flags: an active target, a static target
     unsigned long long sh64[4];             // per-wave totals of the table scan
     uint32_t ntask;
@@ -324,20 +324,19 @@ __device__ inline void reach_test(SweepLds<DIAG> &L, uint32_t *qw, uint32_t &qn,
         nb += (other && d2 < L2m) ? 1u : 0u;
         un |= other && d2 >= L2m && d2 < L2p;
     }
+    // every lane stores (a survivor at its queue position, the others in the
+    // spare slot): no branch on the ballot and no exec mask per candidate
     const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-    if (m) {
-        if (hit)
-            qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
-                tq + kk;
-        qn += (uint32_t)__popcll(m);
-        if (qn >= 64) {
-            __builtin_amdgcn_wave_barrier();
-            drain_queue<DIAG>(L, qw, 64u, e, g, kf, gf, L2m, L2p, n3);
-            __builtin_amdgcn_wave_barrier();
-            qn -= 64;
-            if (lane < qn) qw[lane] = qw[64 + lane];
-            __builtin_amdgcn_wave_barrier();
-        }
+    const uint32_t pos = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    qw[hit ? pos : (uint32_t)kQueue] = tq + kk;
+    qn += (uint32_t)__popcll(m);
+    if (qn >= 64) {
+        __builtin_amdgcn_wave_barrier();
+        drain_queue<DIAG>(L, qw, 64u, e, g, kf, gf, L2m, L2p, n3);
+        __builtin_amdgcn_wave_barrier();
+        qn -= 64;
+        if (lane < qn) qw[lane] = qw[64 + lane];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -598,6 +597,8 @@ __device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<fals
                     const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
                     const float sg = owg + cc.w;  // the reach test of pair_math
                     const bool hit = in && d2 < sg * sg;
+                    // (all lanes test one candidate here, so many trips have no
+                    // survivor at all: the append is skipped on those)
                     const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
                     if (m) {
                         if (hit)
