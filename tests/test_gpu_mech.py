@@ -41,19 +41,27 @@ def test_c0_every_iteration_matches_oracle_single_step(abm, detect_static, workl
         st = H.gpu_state(abm, b)
 
 
-@pytest.mark.parametrize("detect_static,workload", [(False, "c0"), (True, "relaxed_lattice"), (False, "dense"),
-                                                     (False, "dense_small"), (False, "packed")])
+@pytest.mark.parametrize("detect_static,workload", [(False, "c0"), (True, "relaxed_lattice"), (False, "crowded"),
+                                                     (True, "crowded"), (False, "dense"), (False, "dense_small"),
+                                                     (False, "packed")])
 def test_production_path_single_step_matches_oracle(abm, detect_static, workload):
     """The launch configuration of the benchmark (no diagnostics: row culling
     and reach tests active) against the oracle, one iteration at a time.  The
     dense workloads overflow the LDS stage of a unit and take the box-wise
     path: about 7 agents per box (one candidate chunk per core box), 19 small
     agents per box (several chunks) and 80 per box (several passes over the
-    targets of a box, about ten chunks, most agents on the FP64 path)."""
+    targets of a box, about ten chunks, most agents on the FP64 path).  The
+    crowded workload (about 4.2 agents per box) sits at the edge of the LDS
+    stage: units on the LDS path next to units too large for it.  With the
+    static skip, a unit that holds a static agent loses the half shell, and
+    its up to nine tasks per target can overflow the task list after the
+    stage and setup (the box-wise path then finishes the unit)."""
     if workload == "c0":
         pos, diam = c0()
     elif workload == "relaxed_lattice":
         pos, diam = inputs.relaxed_lattice(16, seed=2)
+    elif workload == "crowded":
+        pos, diam = inputs.plain(4096, 149.0, seed=9)
     elif workload == "dense":  # twice the density of the uniform workload: more contacts per agent
         pos, diam = inputs.plain(4096, 127.0, seed=9)
     elif workload == "dense_small":
