@@ -68,6 +68,8 @@ typedef struct {
     int64_t *box;                     /* linear box id, x fastest */
     double *sum_abs_fn;               /* sum over contacts of |F_N| */
     double *sum_dfn;                  /* sum over contacts of |dF_N/d delta| */
+    double *sum_fn_d;                 /* sum over contacts of |F_N| / distance (the conditioning of the
+                                         force direction: centre-line error over distance) */
     uint8_t *moved, *grew, *divided, *is_new;
     double grid_lo[3], grid_hi[3], grid_L;
     int64_t grid_dims[3];
@@ -321,7 +323,7 @@ static void sort_by_uid(int64_t *idx, int64_t n, const uint64_t *uid)
 typedef struct {
     double f[3];
     int32_t nbr, contacts, nz;
-    double sum_abs_fn, sum_dfn;
+    double sum_abs_fn, sum_dfn, sum_fn_d;
 } orc_force;
 
 static void agent_force(const orc_state *s, const orc_params *p, int64_t i,
@@ -329,7 +331,7 @@ static void agent_force(const orc_state *s, const orc_params *p, int64_t i,
 {
     double f0 = 0.0, f1 = 0.0, f2 = 0.0;
     int32_t contacts = 0, nz = 0;
-    double sabs = 0.0, sd = 0.0;
+    double sabs = 0.0, sd = 0.0, sfd = 0.0;
     double ri = 0.5 * s->diam[i];
     for (int64_t q = 0; q < nbrs->n; ++q) {
         int64_t j = nbrs->idx[q];
@@ -345,6 +347,7 @@ static void agent_force(const orc_state *s, const orc_params *p, int64_t i,
         sabs += fabs(fn);
         sd += fabs(p->k - p->gamma * sqrt(rbar) / (2.0 * sqrt(delta)));
         if (dist > 0.0) {
+            sfd += fabs(fn) / dist;
             f0 += fn * ddx / dist;
             f1 += fn * ddy / dist;
             f2 += fn * ddz / dist;
@@ -356,6 +359,7 @@ static void agent_force(const orc_state *s, const orc_params *p, int64_t i,
     out->nz = nz;
     out->sum_abs_fn = sabs;
     out->sum_dfn = sd;
+    out->sum_fn_d = sfd;
 }
 
 /* Displacement from the force: no motion unless |F| exceeds the adherence
@@ -428,6 +432,7 @@ int orc_step(orc_state *s, const orc_params *p)
                 s->contacts[i] = -1;
                 s->sum_abs_fn[i] = 0.0;
                 s->sum_dfn[i] = 0.0;
+                s->sum_fn_d[i] = 0.0;
             } else {
                 if (collect_neighbours(s, &g, i, p->brute_force, &nb)) { failed = 1; continue; }
                 sort_by_uid(nb.idx, nb.n, s->uid);
@@ -439,6 +444,7 @@ int orc_step(orc_state *s, const orc_params *p)
                 s->nz[i] = fo.nz;
                 s->sum_abs_fn[i] = fo.sum_abs_fn;
                 s->sum_dfn[i] = fo.sum_dfn;
+                s->sum_fn_d[i] = fo.sum_fn_d;
                 orc_displacement(fo.f, p->adherence, p->dt, p->mass, p->max_disp, d);
             }
             s->dx[i] = d[0]; s->dy[i] = d[1]; s->dz[i] = d[2];
@@ -593,7 +599,7 @@ int orc_step(orc_state *s, const orc_params *p)
  * without changing it (used for sampled checks of large populations). */
 int orc_forces_subset(const orc_state *s, const orc_params *p, int64_t nsel, const int64_t *sel,
                       double *f_out /* nsel x 3 */, int32_t *cnt_out /* nsel x 3: nbr, contacts, nz */,
-                      double *d_out /* nsel x 3 */, double *tol_out /* nsel x 2: sum|F_N|, sum|dF_N/d delta| */)
+                      double *d_out /* nsel x 3 */, double *tol_out /* nsel x 3: sum|F_N|, sum|dF_N/d delta|, sum|F_N|/distance */)
 {
     orc_grid g;
     memset(&g, 0, sizeof g);
@@ -616,8 +622,9 @@ int orc_forces_subset(const orc_state *s, const orc_params *p, int64_t nsel, con
             cnt_out[3 * q] = fo.nbr;
             cnt_out[3 * q + 1] = fo.contacts;
             cnt_out[3 * q + 2] = fo.nz;
-            tol_out[2 * q] = fo.sum_abs_fn;
-            tol_out[2 * q + 1] = fo.sum_dfn;
+            tol_out[3 * q] = fo.sum_abs_fn;
+            tol_out[3 * q + 1] = fo.sum_dfn;
+            tol_out[3 * q + 2] = fo.sum_fn_d;
         }
         free(nb.idx);
     }

@@ -38,7 +38,7 @@ class OrcState(ctypes.Structure):
         ("uid", _u64p), ("is_static", _u8p), ("nz", _i32p),
         ("nbr", _i32p), ("contacts", _i32p),
         ("fx", _dp), ("fy", _dp), ("fz", _dp), ("dx", _dp), ("dy", _dp), ("dz", _dp),
-        ("box", _i64p), ("sum_abs_fn", _dp), ("sum_dfn", _dp),
+        ("box", _i64p), ("sum_abs_fn", _dp), ("sum_dfn", _dp), ("sum_fn_d", _dp),
         ("moved", _u8p), ("grew", _u8p), ("divided", _u8p), ("is_new", _u8p),
         ("grid_lo", ctypes.c_double * 3), ("grid_hi", ctypes.c_double * 3), ("grid_L", ctypes.c_double),
         ("grid_dims", ctypes.c_int64 * 3),
@@ -114,7 +114,7 @@ class OracleSim:
         self.fx, self.fy, self.fz = z(np.float64), z(np.float64), z(np.float64)
         self.dx, self.dy, self.dz = z(np.float64), z(np.float64), z(np.float64)
         self.box = z(np.int64)
-        self.sum_abs_fn, self.sum_dfn = z(np.float64), z(np.float64)
+        self.sum_abs_fn, self.sum_dfn, self.sum_fn_d = z(np.float64), z(np.float64), z(np.float64)
         self.moved, self.grew, self.divided, self.is_new = z(np.uint8), z(np.uint8), z(np.uint8), z(np.uint8)
         self.x[:n], self.y[:n], self.z[:n] = pos[:, 0], pos[:, 1], pos[:, 2]
         self.diam[:n] = np.asarray(diam, dtype=np.float64)
@@ -140,7 +140,7 @@ class OracleSim:
                          ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("fz", ctypes.c_double),
                          ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                          ("box", ctypes.c_int64), ("sum_abs_fn", ctypes.c_double), ("sum_dfn", ctypes.c_double),
-                         ("moved", ctypes.c_uint8), ("grew", ctypes.c_uint8), ("divided", ctypes.c_uint8),
+                         ("sum_fn_d", ctypes.c_double), ("moved", ctypes.c_uint8), ("grew", ctypes.c_uint8), ("divided", ctypes.c_uint8),
                          ("is_new", ctypes.c_uint8)):
             setattr(s, name, _ptr(getattr(self, name), ct))
 
@@ -190,7 +190,7 @@ class OracleSim:
     def forces_subset(self, sel):
         sel = np.ascontiguousarray(sel, dtype=np.int64)
         m = sel.size
-        f = np.zeros((m, 3)); d = np.zeros((m, 3)); tol = np.zeros((m, 2))
+        f = np.zeros((m, 3)); d = np.zeros((m, 3)); tol = np.zeros((m, 3))
         cnt = np.zeros((m, 3), dtype=np.int32)
         rc = lib().orc_forces_subset(ctypes.byref(self.state), ctypes.byref(self.params), m,
                                      _ptr(sel, ctypes.c_int64), _ptr(f, ctypes.c_double), _ptr(cnt, ctypes.c_int32),

@@ -190,7 +190,8 @@ struct Acc {
 // non-zero force and returns the force factor F_N / dist; marks the pair
 // undecidable (unc) when FP32 cannot certify an integer outcome: coincident
 // centres, a distance at the box length, an overlap or a force within its
-// error bound of zero.  ep: error bound of F_N.
+// error bound of zero.  ep: error bound of the pair's force vector
+// F_N (x_i - x_j) / d.
 struct PairOut {
     bool contact, unc;
     bool nz_unc;  // a contact whose force cannot be told from zero in FP32
@@ -217,14 +218,19 @@ __device__ inline PairOut pair_math(float ddx, float ddy, float ddz, float d2, f
     // bound on |fn error|: conditioning of Eq 4.1 times the overlap error,
     // plus FP32 rounding relative to the magnitudes of both terms
     const float ep = (kf + 0.5f * gs * __builtin_amdgcn_rcpf(delta)) * e + (kd + gs) * 0x1.0p-19f;
+    // the force vector adds the error of its direction: the centre line is
+    // known to within e (the coordinates' share of the overlap bound), so the
+    // unit vector to within about e / d (pairs closer than 2e are coincident)
+    const float rd = __builtin_amdgcn_rcpf(dist);
+    const float epv = ep + fabsf(fn) * e * rd;
     // a force within its bound of zero is a tiny, bounded term of the sum;
     // only the non-zero-force count is then uncertain (see commit)
-    const bool big = contact && ep >= 0x1.0p-6f;
+    const bool big = contact && epv >= 0x1.0p-6f;
     o.nz_unc = contact && !big && fabsf(fn) <= ep;
     o.unc = unc || big;
     o.contact = contact && !big;
-    o.f = fn * __builtin_amdgcn_rcpf(dist);
-    o.ep = ep;
+    o.f = fn * rd;
+    o.ep = epv;
     return o;
 }
 

@@ -38,10 +38,12 @@ def oracle_from_state(st, params, cap=None, next_uid=None, iteration=0):
 
 
 def force_tolerance(o, L):
-    """Per-agent bound: 1e-5 relative to sum |F_N| plus the conditioning of
-    Eq 4.1 times the FP32 overlap error bound."""
+    """Per-agent bound: 1e-5 relative to sum |F_N|, plus the FP32 error bound
+    e of the centre distance times the conditioning of the force vector
+    F_N (x_i - x_j) / d: through the overlap, |dF_N/d delta| (Eq 4.1), and
+    through the direction, |F_N| / d (the centre line's error over d)."""
     n = o.n
-    return 1e-5 * o.sum_abs_fn[:n] + E_DELTA_REL * L * o.sum_dfn[:n] + 1e-12
+    return 1e-5 * o.sum_abs_fn[:n] + E_DELTA_REL * L * (o.sum_dfn[:n] + o.sum_fn_d[:n]) + 1e-12
 
 
 def compare_single_step(abm, b, o, sim=0, L=15.0, check_static=True):

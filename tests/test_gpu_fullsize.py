@@ -84,7 +84,7 @@ def _check_step(abm, pop, op, rng, n_regions):
         mv_o = np.any(d != 0, axis=1)
         mv_g = np.any(got != start, axis=1)
         assert np.array_equal(mv_g, mv_o), f"move decisions differ in the cube at {c}"
-        bound = scale * (1e-5 * tol[:, 0] + H.E_DELTA_REL * L * tol[:, 1]) + 1e-12
+        bound = scale * (1e-5 * tol[:, 0] + H.E_DELTA_REL * L * (tol[:, 1] + tol[:, 2])) + 1e-12
         err = np.linalg.norm(got - expect, axis=1)
         ok = err <= bound + 1e-13 * np.abs(expect).max(axis=1)
         assert np.all(ok), f"positions differ in the cube at {c}: worst err/bound {float((err / bound).max())}"

@@ -43,7 +43,7 @@ def test_c0_every_iteration_matches_oracle_single_step(abm, detect_static, workl
 
 @pytest.mark.parametrize("detect_static,workload", [(False, "c0"), (True, "relaxed_lattice"), (False, "crowded"),
                                                      (True, "crowded"), (False, "dense"), (False, "dense_small"),
-                                                     (False, "packed")])
+                                                     (False, "packed"), (False, "coincident")])
 def test_production_path_single_step_matches_oracle(abm, detect_static, workload):
     """The launch configuration of the benchmark (no diagnostics: row culling
     and reach tests active) against the oracle, one iteration at a time.  The
@@ -55,7 +55,10 @@ def test_production_path_single_step_matches_oracle(abm, detect_static, workload
     stage: units on the LDS path next to units too large for it.  With the
     static skip, a unit that holds a static agent loses the half shell, and
     its up to nine tasks per target can overflow the task list after the
-    stage and setup (the box-wise path then finishes the unit)."""
+    stage and setup (the box-wise path then finishes the unit).  The
+    coincident workload puts 32 agents exactly on top of others and 32 at
+    1e-9 um from others: their directions are undecidable in FP32 and go to
+    the FP64 path."""
     if workload == "c0":
         pos, diam = c0()
     elif workload == "relaxed_lattice":
@@ -66,8 +69,13 @@ def test_production_path_single_step_matches_oracle(abm, detect_static, workload
         pos, diam = inputs.plain(4096, 127.0, seed=9)
     elif workload == "dense_small":
         pos, diam = inputs.plain(4096, 90.0, seed=9, dmin=3.0, dmax=5.0)
-    else:
+    elif workload == "packed":
         pos, diam = inputs.plain(4096, 55.0, seed=9)
+    else:  # coincident
+        pos, diam = c0()
+        pos = pos.copy()
+        pos[4000:4032] = pos[0:32]
+        pos[4032:4064] = pos[32:64] + 1e-9
     gp = H.gpu_params(abm, detect_static=detect_static)
     b = abm.Population(gp, pos, diam, capacity=4096, box_capacity=1 << 16)
     op = H.oracle_params(detect_static=detect_static)
