@@ -50,6 +50,14 @@ def test_two_sphere_force_closed_form(d1, d2, dist, expected):
     assert f[0, 1] == 0.0 and f[0, 2] == 0.0
     assert s.contacts[0] == 1 and s.nz[0] == 1 and s.nbr[0] == 1
     assert sim.pair_force(d1 / 2, d2 / 2, d1 / 2 + d2 / 2 - dist) == pytest.approx(expected, rel=1e-14)
+    # the per-agent sums behind the parity tolerances: |F_N|, |dF_N/d delta| (k = 2, gamma = 1
+    # in these rows) and |F_N|/d, the conditioning of the unit vector of Eq 4.2
+    r1, r2 = d1 / 2, d2 / 2
+    delta, rbar = r1 + r2 - dist, r1 * r2 / (r1 + r2)
+    for a in (0, 1):
+        assert s.sum_abs_fn[a] == pytest.approx(abs(expected), rel=1e-14)
+        assert s.sum_dfn[a] == pytest.approx(abs(2.0 - math.sqrt(rbar) / (2.0 * math.sqrt(delta))), rel=1e-14)
+        assert s.sum_fn_d[a] == pytest.approx(abs(expected) / dist, rel=1e-14)
 
 
 def test_force_zero_and_minimum_of_eq_4_1():
@@ -74,6 +82,7 @@ def test_coincident_centres_give_no_force():
     s.step()
     assert np.all(s.force() == 0.0)
     assert s.contacts[0] == 1  # overlapping, but the direction is undefined
+    assert s.sum_fn_d[0] == 0.0 and s.sum_abs_fn[0] > 0.0  # no direction, so no direction error term
 
 
 # --- Supplementary tutorial (ForEachNeighbor): three spheres on a line ----------------
