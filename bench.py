@@ -5,7 +5,9 @@ Workload (default): plain mechanics, 1e8 agents uniform in a cube at 1 agent
 per 1000 um^3, diameters U[10, 15) um, box length 15 um, dt 0.01, k = 2,
 gamma = 1, adherence 1.8, mass 0.1, cap 3 um, Morton re-sort every 10
 iterations; FP32 forces, FP64 positions.  ``--workload relaxed`` runs the
-pre-relaxed lattice (most agents static, static skip on).
+pre-relaxed lattice (most agents static, static skip on); ``spheroid`` grows
+one tumour spheroid from 1,000 cells to about 5e6; ``sweep`` and
+``surrogate`` time the batched parameter sweep and the surrogate screening.
 
 A step is one iteration of the whole hot path (grid build, force sweep,
 displacement, static flags, re-sort when due).  Prints one JSON line with the
@@ -98,8 +100,8 @@ def pmc_summary(args):
     """HBM bytes of one force-sweep launch from the byte counters, each scaled
     by what the same counter reads for a plain copy of known size."""
     fetch, write, cfetch, cwrite = args.pmc_summary
-    f_kib, nf = _counter_per_dispatch(fetch, "k_sweep", "FETCH_SIZE")
-    w_kib, nw = _counter_per_dispatch(write, "k_sweep", "WRITE_SIZE")
+    f_kib, nf = _counter_per_dispatch(fetch, "k_sweep<", "FETCH_SIZE")
+    w_kib, nw = _counter_per_dispatch(write, "k_sweep<", "WRITE_SIZE")
     cf_kib, _ = _counter_per_dispatch(cfetch, "copyBuffer", "FETCH_SIZE")
     cw_kib, _ = _counter_per_dispatch(cwrite, "copyBuffer", "WRITE_SIZE")
     copy_bytes = 2 ** 31
@@ -163,6 +165,74 @@ def bench_sweep(args):
                    "sweep_workgroups": grid},
         "batched_s": t_batch, "per_simulation_s": None if args.batched_only else t_single,
         "speedup_vs_per_simulation": None if args.batched_only else t_single / t_batch,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def lineage_counts(vol, growth, vdiv, iters):
+    """Agent count at every iteration 0..iters.  Growth and division do not
+    depend on positions (a cell grows by its rate below the division volume,
+    else splits into two halves with the same rate), so the count follows from
+    the volumes alone, with the same FP64 operations as the step."""
+    V = np.array(vol, dtype=np.float64)
+    m = np.ones_like(V)
+    out = [float(m.sum())]
+    for _ in range(iters):
+        div = V >= vdiv
+        V = np.where(div, 0.5 * V, V + growth)
+        m = np.where(div, 2.0 * m, m)
+        out.append(float(m.sum()))
+    return np.array(out)
+
+
+def bench_spheroid(args):
+    """Tumour-spheroid growth at scale: 1,000 cells in a 50 um ball grown to
+    about 5e6 agents.  The growth rates are the lognormal draws of the
+    spheroid recipe times a scale factor chosen so that the lineage count
+    reaches about 5e6 at the last iteration (the literal rates give about
+    1.35e3 agents after 600 iterations)."""
+    import torch
+    from paper_2503_10796_amd import abm, inputs
+    abm.lib()
+    S, iters = args.spheroid_scale, args.spheroid_iters
+    pos, diam, vol, growth = inputs.spheroid(1000, seed=3, growth_scale=S)
+    vdiv = inputs.division_volume(12.0)
+    counts = lineage_counts(vol, growth, vdiv, iters)
+    cap = int(1.05 * counts[-1]) + 1024
+    p = abm.params(box_len=0.0, div_vol=vdiv, seed=3, resort_every=args.resort_every, detect_static=False)
+    pop = abm.Population(p, pos, diam, vol=vol, growth=growth, capacity=cap)
+    log(f"[bench] spheroid: growth scale {S}, {iters} iterations, lineage count {int(counts[-1])}, capacity {cap}")
+    torch.cuda.synchronize()
+    chunk = 50
+    marks = []
+    t0 = time.perf_counter()
+    done = 0
+    while done < iters:
+        k = min(chunk, iters - done)
+        pop.step(k)
+        torch.cuda.synchronize()
+        done += k
+        marks.append((done, time.perf_counter() - t0, int(pop.num_agents()[0])))
+        log(f"[bench] iteration {done}: {marks[-1][2]} agents, {marks[-1][1]:.2f} s")
+    elapsed = marks[-1][1]
+    n_end = marks[-1][2]
+    assert n_end == int(counts[-1]), f"agent count {n_end} differs from the lineage count {int(counts[-1])}"
+    updates = float(counts[:iters].sum())
+    c, rg, rm, _ = pop.stats(hist_rmax=400.0)
+    last_ms = (marks[-1][1] - marks[-2][1]) / (marks[-1][0] - marks[-2][0]) * 1e3 if len(marks) > 1 else None
+    out = {
+        "metric": "tumour-spheroid growth: agent updates/s over the whole run",
+        "value": updates / elapsed, "unit": "agent updates/s", "n_gpus": 1, "steps": iters, "warmup": 0,
+        "ms_per_step": elapsed / iters * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"tumour spheroid: 1000 cells in a 50 um ball (seed 3), d = 8 um, lognormal growth "
+                               f"(mean 1 um^3/step, log-sigma 0.2) times {S}, division at 12 um, box = largest "
+                               f"diameter, Morton re-sort every {args.resort_every} iterations, {iters} iterations",
+                   "growth_scale": S, "agents_start": 1000, "agents_end": n_end},
+        "seconds": elapsed,
+        "ms_per_step_last_chunk": last_ms,
+        "progress": [{"iteration": it, "seconds": t, "agents": n} for it, t, n in marks],
+        "r_gyr_um_end": float(rg[0]), "r_max_um_end": float(rm[0]),
     }
     print(json.dumps(out), flush=True)
 
@@ -288,9 +358,14 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--agents", type=int, default=100_000_000)
-    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate"], default="uniform",
+    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate", "spheroid"],
+                    default="uniform",
                     help="uniform / relaxed: mechanics at scale (the headline line); sweep: batched parameter "
-                         "sweep vs the per-simulation path; surrogate: screening speedup and error")
+                         "sweep vs the per-simulation path; surrogate: screening speedup and error; spheroid: "
+                         "one tumour spheroid grown to about 5e6 agents")
+    ap.add_argument("--spheroid-scale", type=float, default=8.0,
+                    help="spheroid: factor on the growth rates (8.0 reaches about 5e6 agents at 600 iterations)")
+    ap.add_argument("--spheroid-iters", type=int, default=600, help="spheroid: iterations")
     ap.add_argument("--sims", type=int, default=256, help="sweep: simulations")
     ap.add_argument("--sweep-iters", type=int, default=300, help="sweep: iterations per simulation")
     ap.add_argument("--batched-only", action="store_true",
@@ -326,6 +401,9 @@ def main():
         return
     if args.workload == "surrogate":
         bench_surrogate(args)
+        return
+    if args.workload == "spheroid":
+        bench_spheroid(args)
         return
     from paper_2503_10796_amd import abm
 

@@ -110,7 +110,9 @@ def compare_positions_single_step(abm, b, o, start_pos, sim=0, L=15.0):
     assert np.array_equal(g_uid[order_g], o.uid[:n][order_o]), "agent sets differ"
     pg = b.query(abm.POS, sim)[order_g]
     po = o.pos()[order_o]
-    p0 = start_pos[order_o]
+    p0 = np.full((n, 3), np.nan)  # daughters of this step have no start position
+    p0[: start_pos.shape[0]] = start_pos
+    p0 = p0[order_o]
     old = o.is_new[:n][order_o] == 0
     moved_g = np.any(pg[old] != p0[old], axis=1)
     moved_o = np.any(po[old] != p0[old], axis=1)

@@ -179,6 +179,47 @@ def test_growth_division_matches_oracle(abm):
     print(f"C2 (reading A) 700 iterations: N={counts_g[-1]}, max position error {err.max():.3e} um", flush=True)
 
 
+def test_spheroid_scale_run_first_100_iterations(abm):
+    """The spheroid of the scale run (growth rates times 8, about 5e6 agents
+    after 600 iterations) in its launch configuration: agent counts equal the
+    lineage count at every iteration; around the first divisions and at
+    iteration 100 (1,927 agents) the oracle, stepped once from the GPU state,
+    gives the same agents, volumes and diameters bit for bit, the same move
+    decisions, and positions within the force bound."""
+    import bench
+    S = 8.0
+    pos, diam, vol, growth = inputs.spheroid(1000, seed=3, growth_scale=S)
+    vdiv = inputs.division_volume(12.0)
+    counts = bench.lineage_counts(vol, growth, vdiv, 100)
+    cap = int(counts[-1]) + 1024
+    gp = abm.params(box_len=0.0, div_vol=vdiv, seed=3, resort_every=10, detect_static=False)
+    op = H.oracle_params(box_len=0.0, div_vol=vdiv, seed=3)
+    b = abm.Population(gp, pos, diam, vol=vol, growth=growth, capacity=cap)
+    first_div = int(np.argmax(counts > 1000))
+    checks = sorted({first_div - 1, first_div, first_div + 5, 60, 99})
+    for it in range(100):
+        if it in checks:
+            st = H.gpu_state(abm, b)
+            _, L0, _ = b.grid()
+            nu = int(st["uid"].max()) + 1
+            o = H.oracle_from_state(st, op, cap=cap, next_uid=nu, iteration=it)
+            b.step(1)
+            o.step(1)
+            _, L1, _ = b.grid()
+            ug = b.query(abm.UID)
+            og, oo = np.argsort(ug), np.argsort(o.uid[:o.n])
+            assert np.array_equal(ug[og], o.uid[:o.n][oo])
+            assert np.array_equal(b.query(abm.VOL)[og], o.vol[:o.n][oo])
+            assert np.array_equal(b.query(abm.DIAM)[og], o.diam[:o.n][oo])
+            H.compare_positions_single_step(abm, b, o, st["pos"], L=max(L0, L1))
+            err = np.abs(b.query(abm.POS)[og] - o.pos()[oo]).max()
+            assert err <= 1e-4, err
+            print(f"iteration {it}: {o.n} agents, max position error {err:.2e} um", flush=True)
+        else:
+            b.step(1)
+        assert int(b.num_agents()[0]) == int(counts[it + 1]), it
+
+
 def test_growth_single_step_parity_after_divisions(abm):
     pos, diam, vol, growth = inputs.spheroid(600, seed=13, growth_scale=30.0)
     vdiv = inputs.division_volume(10.0)
