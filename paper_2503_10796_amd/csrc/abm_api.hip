@@ -63,10 +63,15 @@ struct Layout {
     size_t sims, ctl, tile_begin, btile_begin, utile_begin, a_begin, wblk_begin, bnd, blist;
     size_t pos[2], diam[2], vol[2], growth[2], uid[2], flags[2], nz[2];
     size_t stage8, key, rank, payload, sorted_idx, nbr, contacts, force, disp, boxid;
-    size_t count, box_start, brank, dirty, arrive, dirty_blk, arrive_blk, active_blk, near_blk, tile_sum, tile_off, fix_list, divflag, divrank;
+    size_t count, box_start, brank, dirty, arrive, dirty_blk, arrive_blk, active_blk, near_blk, tile_sum, tile_off, fix_list, dense_list, divflag, divrank;
     size_t stat_part, hist_cnt, stat_out;
     size_t total;
 };
+
+// Items of the box-wise sweep: per core box with targets, at most
+// ceil(targets / 64) pass groups, so over all units at most A / 64 plus the
+// number of non-empty boxes, min(A, B).
+int64_t dense_capacity(int64_t A, int64_t B) { return A / 64 + std::min(A, B) + 64; }
 
 bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L, int64_t &A, int64_t &B,
                  int64_t &SB, int64_t &T, int64_t &BT) {
@@ -125,6 +130,7 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
     L.tile_sum = c.take<uint32_t>(ST);
     L.tile_off = c.take<uint32_t>(ST);
     L.fix_list = c.take<uint32_t>(A);
+    L.dense_list = c.take<uint64_t>(dense_capacity(A, B));
     L.divflag = c.take<uint32_t>(A);
     L.divrank = c.take<uint32_t>(A);
     L.stat_part = c.take<double>(3 * T);
@@ -346,6 +352,8 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     d.tile_sum = (uint32_t *)(w + L.tile_sum);
     d.tile_off = (uint32_t *)(w + L.tile_off);
     d.fix_list = (uint32_t *)(w + L.fix_list);
+    d.dense_list = (uint64_t *)(w + L.dense_list);
+    d.dense_cap = dense_capacity(A, B);
     d.divflag = (uint32_t *)(w + L.divflag);
     d.divrank = (uint32_t *)(w + L.divrank);
     d.stat_part = (double *)(w + L.stat_part);

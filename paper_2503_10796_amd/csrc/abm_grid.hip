@@ -43,6 +43,7 @@ __global__ void k_begin(Dev d) {
         d.ctl->total_tiles = t;
         d.ctl->n_fp64_last = d.ctl->n_fix;
         d.ctl->n_fix = 0;
+        d.ctl->n_dense = 0;
     }
 }
 

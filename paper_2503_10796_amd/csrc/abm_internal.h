@@ -64,6 +64,7 @@ struct alignas(256) Ctl {
     int32_t abort;
     uint32_t n_fix;
     uint32_t n_fp64_last;  // agents the FP64 path decided in the last iteration
+    unsigned long long n_dense;  // (unit, core box, pass group) items queued for the box-wise sweep
     int64_t total_tiles, total_btiles, total_utiles, total_units;
     int32_t resort_now;
     int32_t any_growth;
@@ -102,6 +103,8 @@ struct Dev {
     uint8_t *near_blk;    // a dirty (or arrival) mark in the block or one of its 26 neighbours
     uint32_t *tile_sum, *tile_off;
     uint32_t *fix_list;
+    uint64_t *dense_list;  // box-wise sweep items: unit << 9 | core box << 3 | pass group
+    int64_t dense_cap;     // entries of dense_list
     uint32_t *divflag, *divrank;
     double *stat_part;  // per agent tile: 6 doubles
     unsigned int *hist_cnt;  // n_sims x 32

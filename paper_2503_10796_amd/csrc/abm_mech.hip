@@ -477,179 +477,230 @@ __device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const float
     if (o.unc) atomicOr(&acc[4 * tl + 3], kUncBit);
 }
 
-// Box-wise path of the production sweep.  As in sweep_unit_dense, each wave
-// takes one core box at a time with (target, stream) lanes.  The candidates
-// of all 27 boxes are staged in chunks of up to kDenseChunk per wave, all of
-// a chunk's loads in flight together, and shifted into the frame of the
-// targets' box.  Each lane only tests the pair against its contact reach;
-// survivors go to a per-wave queue and the contact math runs on full 64-pair
-// drains (and on the rest at the end of each chunk), with exact fixed-point
-// LDS accumulators per target.  The LDS tables of the unit path are free here.
-__device__ void sweep_unit_dense_q(const Dev &d, const SimDesc &S, SweepLds<false> &L, int P, int lp, int qx, int qy,
-                                   int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
-    static_assert(4 * kDenseChunk <= kStage + 1, "per wave: a chunk of candidates in the stage");
-    static_assert(offsetof(SweepLds<false>, acm) == offsetof(SweepLds<false>, acc) + sizeof(L.acc) &&
-                      sizeof(L.acc) + sizeof(L.acm) >= 4 * 64 * sizeof(float4) + 4 * kDenseChunk * sizeof(uint32_t),
-                  "per wave: 64 targets and the candidates' slots in the accumulator arrays");
-    static_assert(sizeof(L.task) >= 4 * 64 * 4 * sizeof(unsigned long long), "per wave: 64 target accumulators");
-    static_assert(sizeof(L.tmap) >= 4 * 2 * 28 * sizeof(uint32_t), "per wave: the 27-box prefix and sources");
+// Box-wise path of the production sweep, for units whose region does not fit
+// the LDS stage (or whose task list overflows).  The sweep queues such units
+// as (unit, core box, pass group) items, one per core box with targets and
+// pass group, for k_sweep_dense, so that the boxes of the densest units spread
+// over the whole chip instead of over the four waves of one block.
+// Within an item the lanes hold (target, stream) pairs of one core box over
+// the box's shared candidates.  The candidates of all 27 boxes are staged in
+// chunks of up to kDenseChunk per wave, all of a chunk's loads in flight
+// together, and shifted into the frame of the targets' box.  Each lane only
+// tests the pair against its contact reach; survivors go to a per-wave queue
+// and the contact math runs on full 64-pair drains (and on the rest at the end
+// of each chunk), with exact fixed-point LDS accumulators per target.
+constexpr int kDensePassGroups = 8;  // pass p (64 targets) of a box is in group p % 8
+
+struct DenseWave {
+    float4 buf[kDenseChunk];         // staged candidates, in the frame of the targets' box
+    float4 ob[64];                   // the targets of the pass
+    uint32_t cs[kDenseChunk];        // slots of the staged candidates
+    unsigned long long acc[4 * 64];  // per target: force x, y, z (2^-40 units); counts | error bound << 32
+    uint32_t pre[28];                // prefix of the candidate counts of the 27 boxes (entry 27: total)
+    uint32_t src[27];                // first slot of each of the 27 boxes
+    uint32_t queue[2 * 64];          // survivors: target lane | staged candidate << 6
+};
+
+// The passes of group pg of box (gx, gy, gz): targets pg * 64 .. pg * 64 + 63,
+// then every kDensePassGroups-th block of 64 after them.
+__device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, int P, int lp, int gx, int gy, int gz,
+                                int pg) {
     const int64_t A = d.A;
+    const int lane = threadIdx.x & 63;
+    if (gx >= S.dims[0] || gy >= S.dims[1] || gz >= S.dims[2]) return;  // padding of an edge block
+    const uint32_t m = box_rank(d, S, gx, gy, gz);
+    const uint32_t tbeg = d.box_start[S.sb_off + m];
+    const uint32_t cnt = d.box_start[S.sb_off + m + 1] - tbeg;
+    if (cnt <= (uint32_t)pg * 64u) return;  // no pass in this group
     const float Lf = (float)S.L;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    float4 *buf = L.sp + kDenseChunk * w;                                       // staged candidates
-    float4 *ob = reinterpret_cast<float4 *>(&L.acc[0][0]) + 64 * w;            // the targets of the pass
-    uint32_t *cs = reinterpret_cast<uint32_t *>(reinterpret_cast<float4 *>(&L.acc[0][0]) + 256) + kDenseChunk * w;
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(L.task) + 256 * w;
-    uint32_t *pre = reinterpret_cast<uint32_t *>(L.tmap) + 56 * w;  // 28 prefix entries, then 27 box sources
-    uint32_t *src = pre + 28;
-    uint32_t *qw = L.queue[w];
-    for (int c = w; c < kCore; c += blockDim.x >> 6) {
-        int cx, cy, cz;
-        core_box_coords(c, cx, cy, cz);
-        const int lb = (cx + 1) + kHalo * ((cy + 1) + kHalo * (cz + 1));
-        const uint32_t cnt = L.sbeg[lb + 1] - L.sbeg[lb];
-        if (cnt == 0) continue;
-        const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
-        // prefix of the candidate counts of the 27 boxes (lane b: box b, x fastest)
-        uint32_t nnb = 0, srcb = 0;
-        if (lane < 27) {
-            const int lbb = (cx + lane % 3) + kHalo * ((cy + lane / 3 % 3) + kHalo * (cz + lane / 9));
-            nnb = L.sbeg[lbb + 1] - L.sbeg[lbb];
-            srcb = L.gsrc[lbb];
+    const float e = S.e_delta, g = 2.0f * e;
+    const float kf = (float)S.k, gf = (float)S.gamma;
+    const float L2 = (float)(S.L * S.L);
+    const float G = (float)ldexp(S.L * S.L, -18);
+    const float L2m = L2 - G, L2p = L2 + G;
+    const int64_t lin = linear_box(gx, gy, gz, S.dims);
+    float4 *buf = W.buf, *ob = W.ob;
+    uint32_t *cs = W.cs, *pre = W.pre, *src = W.src, *qw = W.queue;
+    unsigned long long *acc = W.acc;
+    // prefix of the candidate counts of the 27 boxes (lane b: box b, x fastest)
+    uint32_t nnb = 0, srcb = 0;
+    if (lane < 27) {
+        const int bx = gx + lane % 3 - 1, by = gy + lane / 3 % 3 - 1, bz = gz + lane / 9 - 1;
+        if (bx >= 0 && by >= 0 && bz >= 0 && bx < S.dims[0] && by < S.dims[1] && bz < S.dims[2]) {
+            const uint32_t mb = box_rank(d, S, bx, by, bz);
+            srcb = d.box_start[S.sb_off + mb];
+            nnb = d.box_start[S.sb_off + mb + 1] - srcb;
         }
-        uint32_t inc = nnb;
-        for (int off = 1; off < 32; off <<= 1) {
-            const uint32_t o = __shfl_up(inc, off);
-            if (lane >= off) inc += o;
+    }
+    uint32_t inc = nnb;
+    for (int off = 1; off < 32; off <<= 1) {
+        const uint32_t o = __shfl_up(inc, off);
+        if (lane >= off) inc += o;
+    }
+    const uint32_t T = __shfl(inc, 26);  // candidates of the 27 boxes
+    __builtin_amdgcn_wave_barrier();
+    if (lane < 28) pre[lane] = inc - nnb;  // lane 27: T
+    if (lane < 27) src[lane] = srcb;
+    __builtin_amdgcn_wave_barrier();
+    for (uint32_t p0 = (uint32_t)pg * 64u; p0 < cnt; p0 += 64u * (uint32_t)kDensePassGroups) {
+        // gsz targets in this pass, 64 / gsz streams each (the lanes past
+        // gsz * nstream idle); the queue needs no cross-lane sums, so any
+        // target count fills the lanes
+        const int gsz = cnt - p0 < 64u ? (int)(cnt - p0) : 64;
+        const int nstream = 64 / gsz;
+        const int tl = lane % gsz, sid = lane / gsz;
+        const bool tv = sid < nstream;
+        const uint32_t tslot0 = tbeg + p0;
+        const uint32_t slot = tslot0 + (tv ? (uint32_t)tl : 0u);
+        const int64_t i = d.sorted_idx[slot];
+        const uint8_t fl = d.flags[lp][i];
+        const bool stat = tv && S.detect_static && (fl & kStatic);
+        const bool act = tv && !stat;
+        if (stat && sid == 0) skip_static<false>(d, i, P, lp, fl, lin);
+        const float4 own = d.payload[slot];
+        __builtin_amdgcn_wave_barrier();
+        if (sid == 0) {
+            ob[tl] = own;
+            acc[4 * tl] = 0;
+            acc[4 * tl + 1] = 0;
+            acc[4 * tl + 2] = 0;
+            acc[4 * tl + 3] = 0;
         }
-        const uint32_t T = __shfl(inc, 26);  // candidates of the 27 boxes
         __builtin_amdgcn_wave_barrier();
-        if (lane < 28) pre[lane] = inc - nnb;  // lane 27: T
-        if (lane < 27) src[lane] = srcb;
-        __builtin_amdgcn_wave_barrier();
-        for (uint32_t p0 = 0; p0 < cnt;) {
-            // gsz targets in this pass, 64 / gsz streams each (the lanes past
-            // gsz * nstream idle); the queue needs no cross-lane sums, so any
-            // target count fills the lanes
-            const int gsz = cnt - p0 < 64u ? (int)(cnt - p0) : 64;
-            const int nstream = 64 / gsz;
-            const int tl = lane % gsz, sid = lane / gsz;
-            const bool tv = sid < nstream;
-            const uint32_t tslot0 = L.gsrc[lb] + p0;
-            const uint32_t slot = tslot0 + (tv ? (uint32_t)tl : 0u);
-            const int64_t i = d.sorted_idx[slot];
-            const uint8_t fl = d.flags[lp][i];
-            const bool stat = tv && S.detect_static && (fl & kStatic);
-            const bool act = tv && !stat;
-            if (stat && sid == 0) skip_static<false>(d, i, P, lp, fl, lin);
-            const float4 own = d.payload[slot];
-            __builtin_amdgcn_wave_barrier();
-            if (sid == 0) {
-                ob[tl] = own;
-                acc[4 * tl] = 0;
-                acc[4 * tl + 1] = 0;
-                acc[4 * tl + 2] = 0;
-                acc[4 * tl + 3] = 0;
-            }
-            __builtin_amdgcn_wave_barrier();
-            const float owg = own.w + g;
-            uint32_t qn = 0;  // wave-uniform queue fill
-            for (uint32_t cb0 = 0; cb0 < T; cb0 += kDenseChunk) {
-                const uint32_t mc = T - cb0 < (uint32_t)kDenseChunk ? T - cb0 : (uint32_t)kDenseChunk;
-                // stage the chunk (up to three candidates per lane, all loads in
-                // flight together): box and slot first (the slot goes to LDS at
-                // once, the boxes stay packed in one register), then the shift
-                // into the targets' frame (box b is at offset (b % 3 - 1,
-                // b / 3 % 3 - 1, b / 9 - 1) boxes)
-                static_assert(kDenseChunk <= 3 * 64, "three candidates per lane");
-                uint32_t vb = 0;
-                for (int h = 0; h < 3; ++h) {
-                    const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
-                    if (q < mc) {
-                        const uint32_t kk = cb0 + q;
-                        int lo = 0, hi = 27;  // the box of candidate kk: largest b with pre[b] <= kk
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (pre[mid] <= kk) lo = mid; else hi = mid;
-                        }
-                        vb |= (uint32_t)lo << (8 * h);
-                        cs[q] = src[lo] + (kk - pre[lo]);
+        const float owg = own.w + g;
+        uint32_t qn = 0;  // wave-uniform queue fill
+        for (uint32_t cb0 = 0; cb0 < T; cb0 += kDenseChunk) {
+            const uint32_t mc = T - cb0 < (uint32_t)kDenseChunk ? T - cb0 : (uint32_t)kDenseChunk;
+            // stage the chunk (up to three candidates per lane, all loads in
+            // flight together): box and slot first (the slot goes to LDS at
+            // once, the boxes stay packed in one register), then the shift
+            // into the targets' frame (box b is at offset (b % 3 - 1,
+            // b / 3 % 3 - 1, b / 9 - 1) boxes)
+            static_assert(kDenseChunk <= 3 * 64, "three candidates per lane");
+            uint32_t vb = 0;
+            for (int h = 0; h < 3; ++h) {
+                const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
+                if (q < mc) {
+                    const uint32_t kk = cb0 + q;
+                    int lo = 0, hi = 27;  // the box of candidate kk: largest b with pre[b] <= kk
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (pre[mid] <= kk) lo = mid; else hi = mid;
                     }
+                    vb |= (uint32_t)lo << (8 * h);
+                    cs[q] = src[lo] + (kk - pre[lo]);
                 }
-                float4 v[3];
+            }
+            float4 v[3];
 #pragma unroll
-                for (int h = 0; h < 3; ++h) {
-                    const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
-                    if (q < mc) v[h] = d.payload[cs[q]];
-                }
+            for (int h = 0; h < 3; ++h) {
+                const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
+                if (q < mc) v[h] = d.payload[cs[q]];
+            }
 #pragma unroll
-                for (int h = 0; h < 3; ++h) {
-                    const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
-                    if (q < mc) {
-                        const int b = (int)((vb >> (8 * h)) & 0xffu);
-                        float4 cc = v[h];
-                        cc.x += (float)(b % 3 - 1) * Lf;
-                        cc.y += (float)(b / 3 % 3 - 1) * Lf;
-                        cc.z += (float)(b / 9 - 1) * Lf;
-                        buf[q] = cc;
-                    }
-                }
-                __builtin_amdgcn_wave_barrier();
-                for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
-                    const uint32_t j = j0 + (uint32_t)sid;
-                    const bool in = j < mc && act;
-                    const float4 cc = buf[j < mc ? j : 0u];
-                    const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
-                    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                    const float sg = owg + cc.w;  // the reach test of pair_math
-                    const bool hit = in && d2 < sg * sg;
-                    // (all lanes test one candidate here, so many trips have no
-                    // survivor at all: the append is skipped on those)
-                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-                    if (m) {
-                        if (hit)
-                            qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
-                                (uint32_t)tl | (j << 6);
-                        qn += (uint32_t)__popcll(m);
-                        if (qn >= 64) {
-                            __builtin_amdgcn_wave_barrier();
-                            drain_dense(qw, 64u, ob, buf, cs, tslot0, acc, e, g, kf, gf, L2m, L2p);
-                            __builtin_amdgcn_wave_barrier();
-                            qn -= 64;
-                            if ((uint32_t)lane < qn) qw[lane] = qw[64 + lane];
-                            __builtin_amdgcn_wave_barrier();
-                        }
-                    }
-                }
-                if (qn) {  // the chunk is restaged next: drain the rest now
-                    __builtin_amdgcn_wave_barrier();
-                    drain_dense(qw, qn, ob, buf, cs, tslot0, acc, e, g, kf, gf, L2m, L2p);
-                    qn = 0;
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-            p0 += (uint32_t)gsz;
-            if (!act || sid != 0) continue;
-            const unsigned long long am = acc[4 * tl + 3];
-            const uint32_t ac = (uint32_t)am;
-            const int nz_min = (int)(ac & 0xffffu), nz_unc = (int)((ac >> 16) & 0x7fffu);
-            bool unc = (ac & (uint32_t)kUncBit) != 0 || !nz_decided(S, nz_min, nz_unc);
-            if (!unc) {
-                const double fx = (double)(long long)acc[4 * tl] * kFixUnit;
-                const double fy = (double)(long long)acc[4 * tl + 1] * kFixUnit;
-                const double fz = (double)(long long)acc[4 * tl + 2] * kFixUnit;
-                const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
-                const double ebound = (double)(uint32_t)(am >> 32) * 0x1.0p-26 + 1e-9;
-                if (fabs(fnorm - S.adherence) <= ebound) {
-                    unc = true;
-                } else {
-                    const uint32_t m = box_rank(d, S, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz);
-                    commit_agent<false>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
-                                        fz, nz_min + nz_unc, 0, nz_min + nz_unc, m, lin);
+            for (int h = 0; h < 3; ++h) {
+                const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
+                if (q < mc) {
+                    const int b = (int)((vb >> (8 * h)) & 0xffu);
+                    float4 cc = v[h];
+                    cc.x += (float)(b % 3 - 1) * Lf;
+                    cc.y += (float)(b / 3 % 3 - 1) * Lf;
+                    cc.z += (float)(b / 9 - 1) * Lf;
+                    buf[q] = cc;
                 }
             }
-            if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
+            __builtin_amdgcn_wave_barrier();
+            for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
+                const uint32_t j = j0 + (uint32_t)sid;
+                const bool in = j < mc && act;
+                const float4 cc = buf[j < mc ? j : 0u];
+                const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
+                const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                const float sg = owg + cc.w;  // the reach test of pair_math
+                const bool hit = in && d2 < sg * sg;
+                // (all lanes test one candidate here, so many trips have no
+                // survivor at all: the append is skipped on those)
+                const uint64_t mh = __builtin_amdgcn_ballot_w64(hit);
+                if (mh) {
+                    if (hit)
+                        qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(mh >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mh, 0u))] =
+                            (uint32_t)tl | (j << 6);
+                    qn += (uint32_t)__popcll(mh);
+                    if (qn >= 64) {
+                        __builtin_amdgcn_wave_barrier();
+                        drain_dense(qw, 64u, ob, buf, cs, tslot0, acc, e, g, kf, gf, L2m, L2p);
+                        __builtin_amdgcn_wave_barrier();
+                        qn -= 64;
+                        if ((uint32_t)lane < qn) qw[lane] = qw[64 + lane];
+                        __builtin_amdgcn_wave_barrier();
+                    }
+                }
+            }
+            if (qn) {  // the chunk is restaged next: drain the rest now
+                __builtin_amdgcn_wave_barrier();
+                drain_dense(qw, qn, ob, buf, cs, tslot0, acc, e, g, kf, gf, L2m, L2p);
+                qn = 0;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (!act || sid != 0) continue;
+        const unsigned long long am = acc[4 * tl + 3];
+        const uint32_t ac = (uint32_t)am;
+        const int nz_min = (int)(ac & 0xffffu), nz_unc = (int)((ac >> 16) & 0x7fffu);
+        bool unc = (ac & (uint32_t)kUncBit) != 0 || !nz_decided(S, nz_min, nz_unc);
+        if (!unc) {
+            const double fx = (double)(long long)acc[4 * tl] * kFixUnit;
+            const double fy = (double)(long long)acc[4 * tl + 1] * kFixUnit;
+            const double fz = (double)(long long)acc[4 * tl + 2] * kFixUnit;
+            const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
+            const double ebound = (double)(uint32_t)(am >> 32) * 0x1.0p-26 + 1e-9;
+            if (fabs(fnorm - S.adherence) <= ebound) {
+                unc = true;
+            } else {
+                commit_agent<false>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy, fz,
+                                    nz_min + nz_unc, 0, nz_min + nz_unc, m, lin);
+            }
+        }
+        if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
+    }
+}
+
+// Queues the box-wise work of a unit for k_sweep_dense: one item per core box
+// with targets and pass group, ceil(targets / 64) groups at most
+// kDensePassGroups; one atomic per wave.  sbeg: the unit's staged-box prefix
+// (core boxes are the staged boxes 1..4 on every axis).  Every thread of the
+// block calls it.
+__device__ inline void queue_dense_unit(const Dev &d, const uint32_t *sbeg, int64_t u) {
+    const int tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    uint32_t ng = 0;
+    int cb = 0;
+    if (tid < kNb) {
+        const int lx = tid % kHalo, ly = (tid / kHalo) % kHalo, lz = tid / (kHalo * kHalo);
+        if (lx >= 1 && lx <= kBlk && ly >= 1 && ly <= kBlk && lz >= 1 && lz <= kBlk) {
+            cb = (lx - 1) + kBlk * ((ly - 1) + kBlk * (lz - 1));
+            const uint32_t np = (sbeg[tid + 1] - sbeg[tid] + 63u) / 64u;
+            ng = np < (uint32_t)kDensePassGroups ? np : (uint32_t)kDensePassGroups;
+        }
+    }
+    uint32_t x = ng;  // inclusive scan over the wave
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    const uint32_t tot = __shfl(x, 63);
+    if (tot == 0) return;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&d.ctl->n_dense, (unsigned long long)tot);
+    base = __shfl(base, 0);
+    for (uint32_t k = 0; k < ng; ++k) {
+        const unsigned long long q = base + (x - ng) + k;
+        if (q < (unsigned long long)d.dense_cap) {
+            d.dense_list[q] = ((uint64_t)u << 9) | ((uint64_t)cb << 3) | (uint64_t)k;
+        } else {  // cannot happen with the list sized as above; fail the step rather than skip agents
+            atomicOr(&d.ctl->err, kErrGrid);
+            atomicExch(&d.ctl->abort, 1);
         }
     }
 }
@@ -870,9 +921,9 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
         // and a margin of 2^-10 L for the block-relative FP32 coordinates
         const float reach_add = (float)S.rmax + g + (float)ldexp(S.L, -10);
         const bool lds_path = total <= (uint32_t)kStage && nt <= (uint32_t)kMaxT;
-        if (!lds_path) {
+        if (!lds_path) {  // box-wise: in the diagnostic mode here, else queued for k_sweep_dense
             if constexpr (DIAG) sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
-            else sweep_unit_dense_q(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            else queue_dense_unit(d, L.sbeg, u);
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
         }
@@ -973,9 +1024,9 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
             if (tid == 63) L.ntask = x;
         }
         __syncthreads();
-        if (L.ntask > (uint32_t)kTaskCap) {  // rare: more tasks than the list holds
+        if (L.ntask > (uint32_t)kTaskCap) {  // rare: more tasks than the list holds; box-wise as above
             if constexpr (DIAG) sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
-            else sweep_unit_dense_q(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            else queue_dense_unit(d, L.sbeg, u);
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
         }
@@ -1097,6 +1148,37 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
             if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
         }
         __syncthreads();  // the next unit reuses the LDS
+    }
+}
+
+// ------------------------------------------------------------------ box-wise sweep
+// The items the sweep queued, dealt to the waves in order (item q to wave
+// q mod the number of waves, waves numbered XCD by XCD so that the boxes of a
+// unit share an L2).  A box's pass groups are separate items, so the targets
+// of the densest boxes spread over several waves.
+// (sims, wblk, blist: read-only and not aliased, so that their wave-uniform
+// reads are scalar loads)
+__global__ void __launch_bounds__(256)
+    k_sweep_dense(Dev d, const SimDesc *__restrict__ sims, const int64_t *__restrict__ wblk,
+                  const uint32_t *__restrict__ blist) {
+    if (ABM_ABORTED(d)) return;
+    const unsigned long long nq = d.ctl->n_dense;
+    if (nq == 0) return;
+    __shared__ DenseWave W[4];
+    const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
+    const uint32_t w = threadIdx.x >> 6;
+    const unsigned long long n = nq < (unsigned long long)d.dense_cap ? nq : (unsigned long long)d.dense_cap;
+    const unsigned long long nw = 4ull * gridDim.x;  // (gridDim.x: a multiple of 8)
+    const unsigned long long gw = 4ull * ((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3)) + w;
+    for (unsigned long long q = gw; q < n; q += nw) {
+        const uint64_t e = d.dense_list[q];
+        const int64_t u = (int64_t)(e >> 9);
+        const int s = find_sim(wblk, d.n_sims, u);
+        const SimDesc &S = sims[s];
+        int qx, qy, qz, cx, cy, cz;
+        unpack_key(blist[S.b_off + (u - wblk[s])], qx, qy, qz);
+        core_box_coords((int)((e >> 3) & 63u), cx, cy, cz);
+        sweep_box_dense(d, S, W[w], P, lp, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, (int)(e & 7u));
     }
 }
 
@@ -1586,12 +1668,17 @@ __global__ void __launch_bounds__(256) k_static(Dev d, const SimDesc *__restrict
 // ------------------------------------------------------------------ launchers
 void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag, bool any_static) {
     const SimDesc *sims = d.sims;
-    if (diag)
+    if (diag) {
         hipLaunchKernelGGL(k_sweep<true>, dim3(sweep_grid), dim3(256), 0, st, d, sims, d.wblk_begin, d.blist,
                            d.active_blk, 0);
-    else
+    } else {
         hipLaunchKernelGGL(k_sweep<false>, dim3(sweep_grid), dim3(256), 0, st, d, sims, d.wblk_begin, d.blist,
                            d.active_blk, any_static ? 1 : 0);
+        // the units queued for the box-wise path (the kernel returns at once
+        // when there are none)
+        hipLaunchKernelGGL(k_sweep_dense, dim3(1024), dim3(256), 0, st, d, sims, (const int64_t *)d.wblk_begin,
+                           (const uint32_t *)d.blist);
+    }
 }
 
 // Everything of one iteration after the sweep; ends by building the grid of
