@@ -321,11 +321,12 @@ def bench_surrogate(args):
 SWEEP_GRID = {"uniform": 1024, "relaxed": 2048}
 
 
-def mechanics_population(kind, agents, resort_every=10, sweep_grid=None):
+def mechanics_population(kind, agents, resort_every=10, sweep_grid=None, record=False):
     """The mechanics workload at scale, in the launch configuration that is
     timed: (population, agents, description, sweep work groups).  The
     full-size parity tests build their population through this function as
-    well."""
+    well, with record=True (the same kernels also write each agent's force
+    and counts)."""
     from paper_2503_10796_amd import abm, inputs
 
     if kind == "uniform":
@@ -343,7 +344,7 @@ def mechanics_population(kind, agents, resort_every=10, sweep_grid=None):
     n = pos.shape[0]
     dims = side / 15.0 + 4.0
     box_cap = int(1.1 * dims ** 3) + 4096
-    p = abm.params(box_len=15.0, resort_every=resort_every, detect_static=(kind == "relaxed"))
+    p = abm.params(box_len=15.0, resort_every=resort_every, detect_static=(kind == "relaxed"), record=record)
     pop = abm.Population(p, pos, diam, capacity=n, box_capacity=box_cap)
     del pos, diam
     if sweep_grid is None:

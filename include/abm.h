@@ -50,7 +50,11 @@ extern "C" {
 #define ABM_ERR_HIP (-4)       /* HIP runtime failure */
 
 /* flags of abm_params.flags */
-#define ABM_DIAG 1u /* record forces, displacements and neighbour/contact counts */
+#define ABM_DIAG 1u /* diagnostic sweep: every pair within the box length is visited and
+                      neighbours are counted; writes the fields of ABM_RECORD plus NBR_COUNT */
+#define ABM_RECORD 2u /* the production sweep (half shell, reach culling, unit skipping,
+                        box-wise path unchanged) also writes each agent's force, displacement,
+                        contact count and box of the iteration (NBR_COUNT is -1) */
 
 /* Model parameters of one simulation.
  * dt, k, gamma: time step and the constants of Eq 4.1 (k = 2, gamma = 1 in the thesis).
@@ -83,8 +87,14 @@ typedef struct abm_params {
  * DIAM, VOL, GROWTH: double; UID: uint64; STATIC: uint8; NZ, NBR_COUNT,
  * CONTACT_COUNT: int32; BOX: int64 linear box id (x fastest) in the grid of
  * the last iteration.  FORCE, DISP, NBR_COUNT, CONTACT_COUNT and BOX are the
- * values of the last iteration run with ABM_DIAG set (NBR_COUNT and
- * CONTACT_COUNT are -1 and FORCE is 0 for agents skipped as static). */
+ * values of the last iteration run with ABM_DIAG or ABM_RECORD set (NBR_COUNT
+ * and CONTACT_COUNT are -1 and FORCE is 0 for agents skipped as static;
+ * NBR_COUNT is -1 under ABM_RECORD alone).  Under ABM_RECORD without
+ * ABM_DIAG the sweep does not visit aligned 4x4x4 box blocks whose agents
+ * are all static, and the fields of those agents keep older values (their
+ * STATIC flag of the start of the iteration tells them apart).  They are indexed like the state
+ * at the start of that iteration: read them after an iteration without a
+ * Morton re-sort (a re-sort permutes the state, not these fields). */
 enum abm_field {
     ABM_POS = 0, ABM_DIAM = 1, ABM_VOL = 2, ABM_GROWTH = 3, ABM_UID = 4, ABM_STATIC = 5,
     ABM_NZ = 6, ABM_NBR_COUNT = 7, ABM_CONTACT_COUNT = 8, ABM_FORCE = 9, ABM_DISP = 10,

@@ -17,6 +17,7 @@ _FIELD_TYPES = {POS: (np.float64, 3), DIAM: (np.float64, 1), VOL: (np.float64, 1
                 UID: (np.uint64, 1), STATIC: (np.uint8, 1), NZ: (np.int32, 1), NBR_COUNT: (np.int32, 1),
                 CONTACT_COUNT: (np.int32, 1), FORCE: (np.float64, 3), DISP: (np.float64, 3), BOX: (np.int64, 1)}
 DIAG = 1
+RECORD = 2
 
 OK, ERR_ARG, ERR_CAPACITY, ERR_NONFINITE, ERR_HIP = 0, -1, -2, -3, -4
 
@@ -38,9 +39,10 @@ class Params(ctypes.Structure):
 
 
 def params(dt=0.01, k=2.0, gamma=1.0, adherence=1.8, mass=0.1, max_disp=3.0, box_len=15.0, div_vol=0.0,
-           shift_frac=0.125, detect_static=False, resort_every=0, seed=0, sim_id=0, diag=False):
+           shift_frac=0.125, detect_static=False, resort_every=0, seed=0, sim_id=0, diag=False, record=False):
+    flags = (DIAG if diag else 0) | (RECORD if record else 0)
     return Params(dt, k, gamma, adherence, mass, max_disp, box_len, div_vol, shift_frac, int(bool(detect_static)),
-                  int(resort_every), int(seed), int(sim_id), DIAG if diag else 0)
+                  int(resort_every), int(seed), int(sim_id), flags)
 
 
 _lib = None

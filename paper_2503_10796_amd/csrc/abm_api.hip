@@ -110,7 +110,7 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
     L.stage8 = c.take<uint8_t>(A);
     L.key = c.take<uint32_t>(A);
     L.rank = c.take<uint32_t>(A);
-    L.payload = c.take<float4>(A);
+    L.payload = c.take<Pay>(A);
     L.sorted_idx = c.take<uint32_t>(A);
     L.nbr = c.take<int32_t>(A);
     L.contacts = c.take<int32_t>(A);
@@ -332,7 +332,7 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     d.stage8 = (uint8_t *)(w + L.stage8);
     d.key = (uint32_t *)(w + L.key);
     d.rank = (uint32_t *)(w + L.rank);
-    d.payload = (float4 *)(w + L.payload);
+    d.payload = (Pay *)(w + L.payload);
     d.sorted_idx = (uint32_t *)(w + L.sorted_idx);
     d.nbr = (int32_t *)(w + L.nbr);
     d.contacts = (int32_t *)(w + L.contacts);

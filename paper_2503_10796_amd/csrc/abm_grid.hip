@@ -165,9 +165,9 @@ __global__ void k_grid(Dev d) {
         S.nboxes = nb;
         S.nblocks = nbl;
         S.remap = (S.dims[0] != S.dims_prev[0] || S.dims[1] != S.dims_prev[1] || S.dims[2] != S.dims_prev[2]) ? 1 : 0;
-        // bound on the FP32 error of an overlap computed from block-relative
-        // coordinates (|x| < 3L): about 17 units of 2^-24 L, taken with margin
-        S.e_delta = (float)ldexp(L, -18);
+        // Eq 4.1 in units of U = L 2^-kFixBits: F_N = kU delta_U - gU sqrt(rbar_U delta_U)
+        S.kU = (float)(S.k * ldexp(L, -kFixBits));
+        S.gU = (float)(S.gamma * ldexp(L, -kFixBits));
         S.rmax = 0.5 * dec_double(e[6]);
     }
     __syncthreads();
@@ -378,11 +378,11 @@ __global__ void __launch_bounds__(256) k_scatter(Dev d, const SimDesc *__restric
         unpack_key(d.key[i], bx, by, bz);
         uint32_t m = box_rank(d, S, bx, by, bz);
         uint32_t slot = d.box_start[S.sb_off + m] + d.rank[i];
-        float4 p;
-        p.x = rel_coord(d.pos[P][i], S.lo[0], S.L, bx);
-        p.y = rel_coord(d.pos[P][A + i], S.lo[1], S.L, by);
-        p.z = rel_coord(d.pos[P][2 * A + i], S.lo[2], S.L, bz);
-        p.w = (float)(0.5 * d.diam[lp][i]);
+        Pay p;
+        p.x = fix_coord(d.pos[P][i], S.lo[0], S.L, bx);
+        p.y = fix_coord(d.pos[P][A + i], S.lo[1], S.L, by);
+        p.z = fix_coord(d.pos[P][2 * A + i], S.lo[2], S.L, bz);
+        p.r = fix_radius(d.diam[lp][i], S.L);
         d.payload[slot] = p;
         d.sorted_idx[slot] = (uint32_t)i;
     }

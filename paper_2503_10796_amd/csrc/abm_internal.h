@@ -26,6 +26,15 @@ constexpr uint8_t kBufDiff = 2;
 constexpr uint8_t kMoved = 4, kGrew = 8, kDivided = 16, kNew = 32;
 constexpr uint8_t kChgMask = kMoved | kGrew | kDivided | kNew;
 
+// Sweep payload of one agent: its centre relative to the origin of its grid
+// box in fixed point, units of U = L 2^-kFixBits (exact integer offsets
+// between boxes), and its radius in units of U (FP32).
+constexpr int kFixBits = 28;
+struct alignas(16) Pay {
+    int32_t x, y, z;
+    float r;
+};
+
 // error bits (SimDesc::err, Ctl::err)
 constexpr int kErrCapacity = 1, kErrNonfinite = 2, kErrGrid = 4;
 
@@ -51,7 +60,7 @@ struct alignas(256) SimDesc {
     int64_t nblocks;       // aligned 4x4x4 box blocks (sweep work units)
     double rmax;           // largest agent radius at the start of the iteration
     unsigned int nonfinite;
-    float e_delta;  // bound on the FP32 error of an overlap in this grid
+    float kU, gU;  // k U and gamma U (U = L 2^-kFixBits in um): Eq 4.1 with lengths in units of U
 };
 
 constexpr int kBndSlots = 64;  // spread of the bounds atomics (slots per simulation)
@@ -89,7 +98,7 @@ struct Dev {
     uint8_t *flags[2], *nz[2];
     uint8_t *stage8;  // byte staging for host transfers (free between steps)
     uint32_t *key, *rank;
-    float4 *payload;
+    Pay *payload;
     uint32_t *sorted_idx;
     int32_t *nbr, *contacts;
     double *force, *disp;  // 3*A interleaved
@@ -157,12 +166,17 @@ __device__ inline int64_t linear_box(int bx, int by, int bz, const int32_t dims[
     return (int64_t)bx + (int64_t)dims[0] * ((int64_t)by + (int64_t)dims[1] * (int64_t)bz);
 }
 
-// Box-relative FP32 coordinate of an agent (shared by the scatter and sweep,
-// so that an agent's own payload and its view of itself are bitwise equal).
-__device__ inline float rel_coord(double v, double lo, double L, int b) {
-    double origin = lo + (double)b * L;
-    return (float)(v - origin);
+// Payload coordinate of an agent: its offset from the origin of its box in
+// units of U = L 2^-kFixBits, rounded to the nearest integer (in [0, 2^28]
+// for an agent inside its box).  The FP64 offset and the division by L are
+// exact to about 2^-52 relative; the rounding to an integer is the only
+// error of note (at most U/2).
+__device__ inline int32_t fix_coord(double v, double lo, double L, int b) {
+    const double origin = lo + (double)b * L;
+    return (int32_t)rint(ldexp((v - origin) / L, kFixBits));
 }
+// Radius of an agent of diameter dm in units of U (FP32, relative error 2^-24).
+__device__ inline float fix_radius(double dm, double L) { return (float)ldexp(0.5 * dm / L, kFixBits); }
 
 // Error message of the last failed call on this thread (abm_last_error).
 void clear_error();

@@ -25,12 +25,28 @@
 
 namespace abm {
 
-constexpr double kFixMagic = 6144.0;  // 1.5 * 2^12: fma(a, b, M) rounds a*b to 2^-40
-constexpr double kFixUnit = 0x1.0p-40;
+// Force sums are exact fixed-point integers in units of 2^-34: fma(a, b, M)
+// with M = 1.5 * 2^18 rounds a*b (|a*b| < 2^17) to a multiple of 2^-34, and
+// the bits of the result minus those of M are that multiple.
+constexpr double kFixMagic = 393216.0;
+constexpr double kFixUnit = 0x1.0p-34;
+// Lengths in the sweep are in units of U = L 2^-kFixBits (payload coordinates,
+// radii).  In these units the box length and its square are powers of two.
+constexpr int32_t kUnitL = 1 << kFixBits;               // L
+constexpr float kUnitLf = (float)(1 << kFixBits);
+constexpr double kL2U = 0x1.0p56;                        // L^2
+// Band around L^2 where the neighbour test is left to FP64: the quantised
+// centres are within sqrt(3) U of the true ones, so d^2 moves by at most
+// 2 L sqrt(3) U + 3 U^2 < 2^30 U^2 near d = L (plus both sides' FP64 rounding).
+constexpr double kNbrBand = 0x1.0p30 + 64.0;
+// The FP32 reach test keeps every pair with d < r_i + r_j + kReach (U units,
+// 2^-18 L): it covers the FP32 rounding of the squared distance (about 2^-22
+// relative), the quantisation of the centres and the radii.
+constexpr float kReach = 1024.0f;
 constexpr int kHalo = kBlk + 2;              // 6
 constexpr int kNb = kHalo * kHalo * kHalo;   // 216 staged boxes
 constexpr int kCore = kBlk * kBlk * kBlk;    // 64 target boxes
-constexpr int kStage = 928;                  // staged agents (14.5 KB of float4)
+constexpr int kStage = 928;                  // staged agents (14.5 KB of payload)
 static_assert(kStage >= 4 * 64, "the dense path uses 64 staged entries per wave of a 256-thread block");
 
 __device__ inline unsigned long long fixbits(double v) { return (unsigned long long)__double_as_longlong(v); }
@@ -61,7 +77,9 @@ __device__ inline bool displacement64(double fx, double fy, double fz, const Sim
 }
 
 // Writes the outcome of one agent's mechanics (shared by sweep and fixup).
-// m: Morton rank of the agent's box; lin: its linear id (diagnostics).
+// m: Morton rank of the agent's box; lin: its linear id (recorded fields).
+// With DIAG or the ABM_RECORD flag of the simulation, the force, displacement,
+// contact count and box are recorded (the neighbour count only with DIAG).
 template <bool DIAG>
 __device__ inline void commit_agent(const Dev &d, const SimDesc &S, int64_t i, int P, int lp, uint8_t fl, double x,
                                     double y, double z, double fx, double fy, double fz, int nz, int nbr,
@@ -86,8 +104,8 @@ __device__ inline void commit_agent(const Dev &d, const SimDesc &S, int64_t i, i
         }
         d.flags[lp][i] = fl;
     }
-    if (DIAG) {
-        d.nbr[i] = nbr;
+    if (DIAG || (S.flags & ABM_RECORD)) {
+        d.nbr[i] = DIAG ? nbr : -1;
         d.contacts[i] = contacts;
         d.force[3 * i] = fx;
         d.force[3 * i + 1] = fy;
@@ -101,7 +119,7 @@ __device__ inline void commit_agent(const Dev &d, const SimDesc &S, int64_t i, i
 
 // A static agent: no force, no motion, non-zero-force count kept (Sec 5.5).
 template <bool DIAG>
-__device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8_t fl, int64_t lin) {
+__device__ inline void skip_static(const Dev &d, const SimDesc &S, int64_t i, int P, int lp, uint8_t fl, int64_t lin) {
     const int64_t A = d.A;
     if (fl & kBufDiff) {
         d.pos[1 - P][i] = d.pos[P][i];
@@ -109,7 +127,7 @@ __device__ inline void skip_static(const Dev &d, int64_t i, int P, int lp, uint8
         d.pos[1 - P][2 * A + i] = d.pos[P][2 * A + i];
     }
     if (fl & (kBufDiff | kChgMask)) d.flags[lp][i] = fl & (uint8_t) ~(kBufDiff | kChgMask);
-    if (DIAG) {
+    if (DIAG || (S.flags & ABM_RECORD)) {
         d.nbr[i] = -1;
         d.contacts[i] = -1;
         for (int a = 0; a < 3; ++a) {
@@ -142,18 +160,29 @@ constexpr int kTaskCap = 2048;  // tasks per unit on the LDS path (about 7.5 per
 constexpr int kBuckets = 64;    // task lengths 1..63, longer rows share the last bucket
 constexpr int kQueue = 128;     // per-wave survivor queue (entries: target << 20 | target's staged
                                 // index << 10 | candidate's staged index)
-constexpr unsigned long long kUncBit = 0x80000000ull;  // acm: the target needs the FP64 path
-constexpr unsigned long long kNzUncOne = 0x10000ull;   // acm bits 16..30: contacts whose force may be zero
 constexpr uint16_t kNoTarget = 0xffff;
+// Accumulator words of a target on the LDS path.  acc[0..2]: the force
+// components as 52-bit two's complement fixed point (2^-34 units, |F| < 2^17)
+// with a count in the top 12 bits: contacts (x word) and pairs FP32 could not
+// decide (y word).  Both fields are linear, so any order of additions gives
+// the same words.  At most kStage - 1 pairs per target keep every field in
+// range (forces of at most 64 per pair, counts below 4096).
+constexpr int kCntShift = 52;
+constexpr unsigned long long kCnt1 = 1ull << kCntShift;
+__device__ inline long long fix_field(unsigned long long w) { return (long long)(w << 12) >> 12; }
+__device__ inline uint32_t cnt_field(unsigned long long w, long long f) {
+    return (uint32_t)((w - (unsigned long long)f) >> kCntShift);
+}
+// acm: the pairs' force error bounds (2^-28 units, rounded up) << 32 | lower
+// bounds of their |F_N| (2^-17 units, each at most 32): below 2^32 each for
+// kStage - 1 pairs.
 
 template <bool DIAG>
 struct SweepLds {
-    float4 sp[kStage + 1];                  // staged payload, block-relative coordinates (one
+    Pay sp[kStage + 1];                     // staged payload, relative to the region centre (one
                                             // entry past the largest stage: read ahead, unused)
-    unsigned long long acc[3][kMaxT];       // force sums, 2^-40 units (two's complement)
-    unsigned long long acm[kMaxT];          // contacts with a certain non-zero force (bits 0..15),
-                                            // contacts whose force may be zero (16..30), kUncBit,
-                                            // FP32 error bound of the sum in 2^-26 units (32..63)
+    unsigned long long acc[3][kMaxT];       // force x | contacts, force y | undecided pairs, force z
+    unsigned long long acm[kMaxT];          // error bound << 32 | lower bound of sum |F_N|
     uint32_t anbr[DIAG ? kMaxT : 1];        // neighbours within the box length
     uint32_t sbeg[kNb + 1];                 // exclusive prefix of the staged box counts
     uint32_t gsrc[kNb];                     // global slot start of every staged box
@@ -175,160 +204,182 @@ struct SweepLds {
 static_assert(sizeof(SweepLds<false>) <= 40960, "four blocks of 256 threads per CU");
 static_assert(kStage < 1024 && kMaxT < 512, "queue and task entries: 9-bit target, 10-bit staged indices");
 static_assert(kNb <= 256 && kStage <= 4 * kTaskCap, "the stage map: one byte per staged agent in the task list");
+static_assert(kStage < 4096, "count fields of the accumulator words");
 
-// Per-target accumulator of the global-memory path.
+// Per-target accumulator of the global-memory path (diagnostic box-wise sweep).
 struct Acc {
-    unsigned long long ax, ay, az;  // force components in 2^-40 units, plus nfix * magic bits (mod 2^64)
-    uint32_t eacc;                  // error bound in 2^-26 units (rounded up per pair)
-    int contacts, nz, nbr, nfix;
-    int nz_unc;                     // contacts whose force may be zero
-    bool unc;                       // an integer outcome is not decidable in FP32
+    unsigned long long ax, ay, az;  // force components in 2^-34 units, plus nfix * magic bits (mod 2^64)
+    unsigned long long eacc, sacc;  // error bound (2^-28 units), lower bound of sum |F_N| (2^-17 units)
+    int contacts, nbr, nfix;
+    int unc;                        // pairs whose integer outcome FP32 cannot decide
 };
 
-// Contact math of one pair in FP32 (target minus candidate = (ddx,ddy,ddz),
-// squared length d2, radii ri, rj).  Decides contact (overlap > 0) and
-// non-zero force and returns the force factor F_N / dist; marks the pair
-// undecidable (unc) when FP32 cannot certify an integer outcome: coincident
-// centres, a distance at the box length, an overlap or a force within its
-// error bound of zero.  ep: error bound of the pair's force vector
-// F_N (x_i - x_j) / d.
+// Contact math of one pair (Eq 4.1-4.2).  (dx, dy, dz): target minus candidate
+// centre, exact integers in units of U = L 2^-kFixBits held in doubles; d2:
+// their squared length (FP64); ri, rj: radii in units of U (FP32).
+//   overlap   delta = r_i + r_j - d = ((r_i + r_j)^2 - d^2) / (r_i + r_j + d):
+//             the numerator in FP64 (no cancellation error), the rest in FP32
+//             (at most 3.75 * 2^-23 relative with one-ulp sqrt and rcp), plus
+//             the quantisation of the inputs (centres within U/2 per axis,
+//             radii within 2^-24 relative):
+//             e = 1.74 U + 1.01 * 2^-24 (r_i + r_j) + 2^-21 |delta| bounds it
+//   force     F_N = k delta - gamma sqrt(rbar delta) in FP32 (kU = k U,
+//             gU = gamma U: lengths in units of U), factor F_N / d
+// Certain outcomes: contact iff delta > 4e (below, the pair is undecided);
+// a neighbour within the box length iff d^2 < L^2 - band.  The pair is
+// undecided (the target goes to the FP64 path) when the overlap is within
+// 4e of zero, d^2 is within the band of L^2, the centres (nearly) coincide,
+// its force cannot be told from zero (so the non-zero-force count is exact),
+// or its error bound or force is too large for the accumulator words.
+//   ep        bound on the error of the pair's force vector: the overlap
+//             error times a bound of |dF_N/d delta| = |k - h(delta)| over
+//             [delta - e, delta + e], h = gamma sqrt(rbar) / (2 sqrt(delta)):
+//             |k - h| + 0.16 h with delta > 4e (h grows by at most
+//             sqrt(4/3) there); the FP32 rounding of Eq 4.1 (k delta to 2
+//             ulp, the square-root term to 8.5 ulp with the radii's
+//             quantisation in rbar, the difference to one); the error of the
+//             unit vector times |F_N| (2 sqrt(3) U / d from the quantised
+//             centres, 5.5 ulp from the distance, rcp and product); and the
+//             fixed-point rounding of the sum.
 struct PairOut {
-    bool contact, unc;
-    bool nz_unc;  // a contact whose force cannot be told from zero in FP32
-    float f, ep;
+    bool contact;  // a certain contact with a certain non-zero force
+    bool unc;      // an integer outcome is not decidable here
+    float f;       // F_N / d (force per unit U)
+    uint32_t eu;   // ep in 2^-28 units, rounded up (contacts only)
+    uint32_t su;   // lower bound of |F_N|, at most 32, in 2^-17 units (contacts only)
 };
-__device__ inline PairOut pair_math(float ddx, float ddy, float ddz, float d2, float ri, float rj, float e, float g,
-                                    float kf, float gf, float L2m, float L2p, bool valid) {
+__device__ inline PairOut pair_math(double dx, double dy, double dz, double d2, float ri, float rj, float kU, float gU,
+                                    bool valid) {
     PairOut o;
-    const float sr = ri + rj;
-    const float sg = (ri + g) + rj;  // the same rounding as the reach test of the sweep
-    bool cand = valid && d2 < sg * sg;
-    const bool beyond = d2 >= L2m;  // only when the box length is below the largest diameter
-    bool unc = cand && beyond && d2 < L2p;
-    unc |= cand && d2 < g * g;  // (near-)coincident centres: direction left to FP64
-    cand = cand && !beyond && d2 >= g * g;
-    const float dist = __builtin_amdgcn_sqrtf(d2);
-    const float delta = sr - dist;
-    unc |= cand && delta <= e && delta >= -e;
-    bool contact = cand && delta > e;
-    const float rbar = ri * rj * __builtin_amdgcn_rcpf(sr);
+    const double sr = (double)ri + (double)rj;  // exact
+    const double num = fma(sr, sr, -d2);        // (r_i + r_j)^2 - d^2, one rounding
+    const float dist = __builtin_amdgcn_sqrtf((float)d2);
+    const float srf = (float)sr;
+    const float delta = (float)num * __builtin_amdgcn_rcpf(srf + dist);
+    const float e = 1.74f + srf * 0x1.02p-24f + fabsf(delta) * 0x1.0p-21f;
+    const bool near = valid && delta > -e;  // possibly a contact
+    const bool beyond = d2 >= kL2U - kNbrBand;  // (only when the box is shorter than r_i + r_j)
+    bool unc = near && beyond && d2 < kL2U + kNbrBand;
+    const bool coinc = d2 < 64.0;  // centres within 8 U: the direction is left to FP64
+    const bool cand = near && !beyond && !coinc;
+    unc |= near && !beyond && coinc;
+    unc |= cand && delta <= 4.0f * e;
+    const bool contact = cand && delta > 4.0f * e;
+    const float rbar = ri * rj * __builtin_amdgcn_rcpf(srf);
     const float sq = __builtin_amdgcn_sqrtf(fmaxf(rbar * delta, 0.0f));
-    const float kd = kf * delta, gs = gf * sq;
+    const float kd = kU * delta, gs = gU * sq;
     const float fn = kd - gs;
-    // bound on |fn error|: conditioning of Eq 4.1 times the overlap error,
-    // plus FP32 rounding relative to the magnitudes of both terms
-    const float ep = (kf + 0.5f * gs * __builtin_amdgcn_rcpf(delta)) * e + (kd + gs) * 0x1.0p-19f;
-    // the force vector adds the error of its direction: the centre line is
-    // known to within e (the coordinates' share of the overlap bound), so the
-    // unit vector to within about e / d (pairs closer than 2e are coincident)
     const float rd = __builtin_amdgcn_rcpf(dist);
-    const float epv = ep + fabsf(fn) * e * rd;
-    // a force within its bound of zero is a tiny, bounded term of the sum;
-    // only the non-zero-force count is then uncertain (see commit)
-    const bool big = contact && epv >= 0x1.0p-6f;
-    o.nz_unc = contact && !big && fabsf(fn) <= ep;
-    o.unc = unc || big;
-    o.contact = contact && !big;
+    const float afn = fabsf(fn);
+    const float hg = 0.5f * gs * __builtin_amdgcn_rcpf(delta);  // gamma sqrt(rbar) / (2 sqrt(delta))
+    const float ep = (fabsf(kU - hg) + 0.16f * hg) * e + (3.0f * kd + 9.0f * gs) * 0x1.0p-24f +
+                     afn * (3.5f * rd + 0x1.8p-22f) + 0x1.0p-33f;
+    const bool bad = contact && !(ep < 0x1.0p-6f && afn <= 64.0f && afn > ep);
+    o.unc = unc || bad;
+    o.contact = contact && !bad;
     o.f = fn * rd;
-    o.ep = epv;
+    o.eu = o.contact ? (uint32_t)ceilf(ep * 0x1.0p28f) : 0u;
+    o.su = o.contact ? (uint32_t)(fminf(afn - ep, 32.0f) * 0x1.0p17f) : 0u;
     return o;
 }
 
-// One candidate pair in FP32 box-relative coordinates (global-memory path).
-// (qx,qy,qz) = target coordinate minus the box offset of the candidate's box.
+// Force contribution of a pair in the fixed-point units of the sums.
+__device__ inline unsigned long long fix_term(float f, double dd) {
+    return fixbits(fma((double)f, dd, kFixMagic)) - fixbits(kFixMagic);
+}
+
+// One candidate pair of the diagnostic box-wise path: the target's payload
+// (qx, qy, qz: already shifted into the frame of the candidate's box), the
+// candidate's payload c.
 template <bool DIAG>
-__device__ inline void pair_fp32(Acc &a, float qx, float qy, float qz, float ri, float4 c, float e, float g, float kf,
-                                 float gf, float L2m, float L2p) {
-    const float ddx = qx - c.x, ddy = qy - c.y, ddz = qz - c.z;
-    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+__device__ inline void pair_acc(Acc &a, int32_t qx, int32_t qy, int32_t qz, float ri, Pay c, float kU, float gU) {
+    const double dx = (double)(qx - c.x), dy = (double)(qy - c.y), dz = (double)(qz - c.z);
+    const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
     if (DIAG) {
-        if (d2 < L2m) ++a.nbr;
-        else if (d2 < L2p) a.unc = true;
+        if (d2 < kL2U - kNbrBand) ++a.nbr;
+        else if (d2 < kL2U + kNbrBand) ++a.unc;
     }
-    const PairOut o = pair_math(ddx, ddy, ddz, d2, ri, c.w, e, g, kf, gf, L2m, L2p, true);
-    a.unc |= o.unc || (DIAG && o.nz_unc);
+    const PairOut o = pair_math(dx, dy, dz, d2, ri, c.r, kU, gU, true);
+    a.unc += o.unc ? 1 : 0;
     if (o.contact) {
         ++a.contacts;
-        if (o.nz_unc) ++a.nz_unc; else ++a.nz;
         const double f = (double)o.f;
-        a.ax += fixbits(fma(f, (double)ddx, kFixMagic));
-        a.ay += fixbits(fma(f, (double)ddy, kFixMagic));
-        a.az += fixbits(fma(f, (double)ddz, kFixMagic));
+        a.ax += fixbits(fma(f, dx, kFixMagic));
+        a.ay += fixbits(fma(f, dy, kFixMagic));
+        a.az += fixbits(fma(f, dz, kFixMagic));
         ++a.nfix;
-        a.eacc += (uint32_t)ceilf(o.ep * 0x1.0p26f);
+        a.eacc += o.eu;
+        a.sacc += o.su;
     }
 }
 
-// The non-zero-force count of a target: nz_min contacts with a certain
-// non-zero force and nz_unc whose FP32 force cannot be told from zero.  The
-// count feeds only the static rule (at most one non-zero force, Sec 5.5);
-// where that test cannot flip, the uncertain contacts count as non-zero (an
-// FP64 force of exactly zero would need the two terms of Eq 4.1 to round to
-// the same double).  Otherwise the target takes the FP64 path.
-__device__ inline bool nz_decided(const SimDesc &S, int nz_min, int nz_unc) {
-    return !S.detect_static || nz_unc == 0 || nz_min >= 2 || nz_min + nz_unc <= 1;
+// Whether a target's FP32 result is certified: its force within 1e-5 of the
+// sum of |F_N| of its contacts (the error bound e_sum against the lower bound
+// s_sum of that sum; the oracle's own FP64 rounding is far below the margin)
+// and its move decision (|F| > a) outside the error bound.
+__device__ inline bool fp32_certified(const SimDesc &S, double fx, double fy, double fz, double e_sum, double s_sum) {
+    if (!(e_sum <= 0.99999e-5 * s_sum)) return false;
+    const double fnorm = sqrt(fma(fz, fz, fma(fy, fy, fx * fx)));
+    return fabs(fnorm - S.adherence) > e_sum + 0x1.0p-40 * (1.0 + S.adherence);
 }
 
 // Drains `cnt` (<= 64) queued pairs of this wave (lane l takes entry l).
 // With the half shell (n3), a pair of two targets is drained once and adds
-// the opposite force (exact in fixed point) and the same counts to the
-// candidate's accumulators.
+// the opposite force (exact in fixed point) and the same counts and bounds to
+// the candidate's accumulators.
 template <bool DIAG>
-__device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32_t cnt, float e, float g, float kf,
-                                   float gf, float L2m, float L2p, bool n3) {
+__device__ inline void drain_queue(SweepLds<DIAG> &L, const uint32_t *qw, uint32_t cnt, float kU, float gU, bool n3) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t ent = lane < cnt ? qw[lane] : 0u;
     const uint32_t t = ent >> 20, self = (ent >> 10) & 1023u, q = ent & 1023u;
     const bool valid = lane < cnt && q != self;
-    const float4 own = L.sp[self];
-    const float4 c = L.sp[q];
-    const float ddx = own.x - c.x, ddy = own.y - c.y, ddz = own.z - c.z;
-    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-    const PairOut o = pair_math(ddx, ddy, ddz, d2, own.w, c.w, e, g, kf, gf, L2m, L2p, valid);
+    const Pay own = L.sp[self];
+    const Pay c = L.sp[q];
+    const double dx = (double)(own.x - c.x), dy = (double)(own.y - c.y), dz = (double)(own.z - c.z);
+    const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const PairOut o = pair_math(dx, dy, dz, d2, own.r, c.r, kU, gU, valid);
     const uint32_t tq = n3 ? L.tmap[q] : kNoTarget;
-    if (o.contact) {
-        const double f = (double)o.f;
-        const unsigned long long mb = fixbits(kFixMagic);
-        const unsigned long long fx = fixbits(fma(f, (double)ddx, kFixMagic)) - mb;
-        const unsigned long long fy = fixbits(fma(f, (double)ddy, kFixMagic)) - mb;
-        const unsigned long long fz = fixbits(fma(f, (double)ddz, kFixMagic)) - mb;
-        const unsigned long long cm =
-            (o.nz_unc ? kNzUncOne : 1ull) | ((unsigned long long)(uint32_t)ceilf(o.ep * 0x1.0p26f) << 32);
-        atomicAdd(&L.acc[0][t], fx);
-        atomicAdd(&L.acc[1][t], fy);
+    if (o.contact || o.unc) {
+        const unsigned long long fx = o.contact ? fix_term(o.f, dx) : 0ull;
+        const unsigned long long fy = o.contact ? fix_term(o.f, dy) : 0ull;
+        const unsigned long long fz = o.contact ? fix_term(o.f, dz) : 0ull;
+        const unsigned long long cx = o.contact ? kCnt1 : 0ull, cy = o.unc ? kCnt1 : 0ull;
+        const unsigned long long cm = ((unsigned long long)o.eu << 32) | o.su;
+        atomicAdd(&L.acc[0][t], fx + cx);
+        atomicAdd(&L.acc[1][t], fy + cy);
         atomicAdd(&L.acc[2][t], fz);
         atomicAdd(&L.acm[t], cm);
         if (tq != kNoTarget) {
-            atomicAdd(&L.acc[0][tq], 0ull - fx);
-            atomicAdd(&L.acc[1][tq], 0ull - fy);
+            atomicAdd(&L.acc[0][tq], (0ull - fx) + cx);
+            atomicAdd(&L.acc[1][tq], (0ull - fy) + cy);
             atomicAdd(&L.acc[2][tq], 0ull - fz);
             atomicAdd(&L.acm[tq], cm);
         }
     }
-    if (o.unc || (DIAG && o.nz_unc)) {
-        atomicOr(&L.acm[t], kUncBit);
-        if (tq != kNoTarget) atomicOr(&L.acm[tq], kUncBit);
-    }
 }
 
 // Reach test of candidate kk of a lane's task (staged payload c, staged index
-// b0 + kk) against the lane's target; survivors go to the wave's queue, which
-// is drained whenever it holds 64 pairs (qn: wave-uniform fill).  CHECK: some
-// lane's task may have fewer than kk + 1 candidates.
+// b0 + kk) against the lane's target: FP32 squared distance from the exact
+// integer offset, against (r_i + kReach + r_j)^2.  Survivors go to the wave's
+// queue, which is drained whenever it holds 64 pairs (qn: wave-uniform
+// fill).  CHECK: some lane's task may have fewer than kk + 1 candidates.
+// DIAG also counts the neighbours within the box length (FP32 test with a
+// band of 2^-18 L^2 around L^2; inside it the target goes to the FP64 path).
+constexpr float kL2f = 0x1.0p56f, kL2Bandf = 0x1.0p38f;
 template <bool DIAG, bool CHECK>
-__device__ inline void reach_test(SweepLds<DIAG> &L, uint32_t *qw, uint32_t &qn, float4 own, float owg, float4 c,
+__device__ inline void reach_test(SweepLds<DIAG> &L, uint32_t *qw, uint32_t &qn, Pay own, float owg, Pay c,
                                   uint32_t kk, uint32_t len, uint32_t tq, uint32_t self, uint32_t b0, uint32_t &nb,
-                                  bool &un, float e, float g, float kf, float gf, float L2m, float L2p, bool n3) {
+                                  bool &un, float kU, float gU, bool n3) {
     const uint32_t lane = threadIdx.x & 63;
     const bool in = !CHECK || kk < len;
-    const float ddx = own.x - c.x, ddy = own.y - c.y, ddz = own.z - c.z;
+    const float ddx = (float)(own.x - c.x), ddy = (float)(own.y - c.y), ddz = (float)(own.z - c.z);
     const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-    const float sg = owg + c.w;
+    const float sg = owg + c.r;
     const bool hit = in && d2 < sg * sg;
     if (DIAG) {
         const bool other = in && b0 + kk != self;
-        nb += (other && d2 < L2m) ? 1u : 0u;
-        un |= other && d2 >= L2m && d2 < L2p;
+        nb += (other && d2 < kL2f - kL2Bandf) ? 1u : 0u;
+        un |= other && d2 >= kL2f - kL2Bandf && d2 < kL2f + kL2Bandf;
     }
     // every lane stores (a survivor at its queue position, the others in the
     // spare slot): no branch on the ballot and no exec mask per candidate
@@ -338,7 +389,7 @@ __device__ inline void reach_test(SweepLds<DIAG> &L, uint32_t *qw, uint32_t &qn,
     qn += (uint32_t)__popcll(m);
     if (qn >= 64) {
         __builtin_amdgcn_wave_barrier();
-        drain_queue<DIAG>(L, qw, 64u, e, g, kf, gf, L2m, L2p, n3);
+        drain_queue<DIAG>(L, qw, 64u, kU, gU, n3);
         __builtin_amdgcn_wave_barrier();
         qn -= 64;
         if (lane < qn) qw[lane] = qw[64 + lane];
@@ -358,19 +409,20 @@ __device__ inline int task_row(int cx, int cy, int cz, int r) {
 
 // Rows of a target's 27-box neighbourhood that can hold a pair within reach
 // (bits 3r..3r+2 per row r: row used, its left box, its right box).  `reach`
-// bounds the pair's contact distance plus the guard band, with a margin for
-// the FP32 block-relative coordinates: a box whose distance from the target
+// bounds the pair's contact distance plus the reach guard, with a margin for
+// the FP32 face distances (U units): a box whose distance from the target
 // exceeds it cannot hold a pair that the sweep keeps.  With DIAG every box is
 // visited (all neighbours within the box length are counted).
 template <bool DIAG>
-__device__ inline uint32_t row_mask(float4 own, int cx, int cy, int cz, float Lf, float reach_add) {
+__device__ inline uint32_t row_mask(Pay own, int cx, int cy, int cz, float reach_add) {
     if (DIAG) return 0x7ffffffu;
-    const float reach = own.w + reach_add;
+    const float reach = own.r + reach_add;
     const float r2 = reach * reach;
-    // distances to the faces of the target box (local box c+1 spans [(c-2)L, (c-1)L))
-    const float fx0 = own.x - (float)(cx - 2) * Lf, fx1 = Lf - fx0;
-    const float fy0 = own.y - (float)(cy - 2) * Lf, fy1 = Lf - fy0;
-    const float fz0 = own.z - (float)(cz - 2) * Lf, fz1 = Lf - fz0;
+    // distances to the faces of the target box (local box c+1 spans [(c-2)L, (c-1)L)),
+    // exact integers up to the FP32 rounding
+    const float fx0 = (float)(own.x - (cx - 2) * kUnitL), fx1 = kUnitLf - fx0;
+    const float fy0 = (float)(own.y - (cy - 2) * kUnitL), fy1 = kUnitLf - fy0;
+    const float fz0 = (float)(own.z - (cz - 2) * kUnitL), fz1 = kUnitLf - fz0;
     uint32_t m = 0;
     for (int r = 0; r < 9; ++r) {
         const int dy = r % 3 - 1, dz = r / 3 - 1;
@@ -435,46 +487,50 @@ __device__ inline void acc_reduce_streams(Acc &a, int g) {
         a.ay += __shfl_xor(a.ay, off);
         a.az += __shfl_xor(a.az, off);
         a.eacc += __shfl_xor(a.eacc, off);
+        a.sacc += __shfl_xor(a.sacc, off);
         a.contacts += __shfl_xor(a.contacts, off);
-        a.nz += __shfl_xor(a.nz, off);
         a.nbr += __shfl_xor(a.nbr, off);
         a.nfix += __shfl_xor(a.nfix, off);
-        a.nz_unc += __shfl_xor(a.nz_unc, off);
-        a.unc = (__shfl_xor((int)a.unc, off) | (int)a.unc) != 0;
+        a.unc += __shfl_xor(a.unc, off);
     }
 }
 
 // Box-wise path of the production sweep: candidates per wave and chunk.
 constexpr int kDenseChunk = 192;
+// Candidates per box (its 27-box neighbourhood) beyond which the box-wise
+// path leaves the box's targets to the FP64 path: below it the packed error
+// and force-sum words of a target cannot overflow.
+constexpr uint32_t kDenseMaxCand = 16000;
+// Accumulator words per target on the box-wise path: force x, y, z (2^-34
+// units, full 64-bit words), contacts | undecided pairs << 32, error bound
+// (2^-24 units, rounded up) << 32 | lower bound of sum |F_N| (2^-12 units).
+constexpr int kDenseWords = 5;
 
 // Drain of the box-wise path: lane l takes queue entry l (target lane |
 // candidate index in the staged chunk << 6) and adds the pair's contact
-// force and counts to the target's LDS accumulators (force x, y, z; counts |
-// error bound << 32).  Candidates are staged in the frame of the targets' box;
-// cs holds their slots (the target of lane tl has slot tslot0 + tl: a target
-// is not its own candidate).
-__device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const float4 *ob, const float4 *buf,
-                                   const uint32_t *cs, uint32_t tslot0, unsigned long long *acc, float e, float g,
-                                   float kf, float gf, float L2m, float L2p) {
+// force, counts and bounds to the target's LDS accumulators.  Candidates are
+// staged in the frame of the targets' box; cs holds their slots (the target
+// of lane tl has slot tslot0 + tl: a target is not its own candidate).
+__device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const Pay *ob, const Pay *buf, const uint32_t *cs,
+                                   uint32_t tslot0, unsigned long long *acc, float kU, float gU) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t ent = lane < cnt ? qw[lane] : 0u;
     const uint32_t tl = ent & 63u, j = ent >> 6;
     const bool valid = lane < cnt && cs[j] != tslot0 + tl;
-    const float4 own = ob[tl];
-    const float4 c = buf[j];
-    const float ddx = own.x - c.x, ddy = own.y - c.y, ddz = own.z - c.z;
-    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-    const PairOut o = pair_math(ddx, ddy, ddz, d2, own.w, c.w, e, g, kf, gf, L2m, L2p, valid);
+    const Pay own = ob[tl];
+    const Pay c = buf[j];
+    const double dx = (double)(own.x - c.x), dy = (double)(own.y - c.y), dz = (double)(own.z - c.z);
+    const double d2 = fma(dz, dz, fma(dy, dy, dx * dx));
+    const PairOut o = pair_math(dx, dy, dz, d2, own.r, c.r, kU, gU, valid);
+    unsigned long long *a = acc + kDenseWords * tl;
     if (o.contact) {
-        const double f = (double)o.f;
-        const unsigned long long mb = fixbits(kFixMagic);
-        atomicAdd(&acc[4 * tl], fixbits(fma(f, (double)ddx, kFixMagic)) - mb);
-        atomicAdd(&acc[4 * tl + 1], fixbits(fma(f, (double)ddy, kFixMagic)) - mb);
-        atomicAdd(&acc[4 * tl + 2], fixbits(fma(f, (double)ddz, kFixMagic)) - mb);
-        atomicAdd(&acc[4 * tl + 3], (o.nz_unc ? kNzUncOne : 1ull) |
-                                        ((unsigned long long)(uint32_t)ceilf(o.ep * 0x1.0p26f) << 32));
+        atomicAdd(&a[0], fix_term(o.f, dx));
+        atomicAdd(&a[1], fix_term(o.f, dy));
+        atomicAdd(&a[2], fix_term(o.f, dz));
+        atomicAdd(&a[3], 1ull);
+        atomicAdd(&a[4], ((unsigned long long)((o.eu + 15u) >> 4) << 32) | (o.su >> 5));
     }
-    if (o.unc) atomicOr(&acc[4 * tl + 3], kUncBit);
+    if (o.unc) atomicAdd(&a[3], 1ull << 32);
 }
 
 // Box-wise path of the production sweep, for units whose region does not fit
@@ -492,13 +548,13 @@ __device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const float
 constexpr int kDensePassGroups = 8;  // pass p (64 targets) of a box is in group p % 8
 
 struct DenseWave {
-    float4 buf[kDenseChunk];         // staged candidates, in the frame of the targets' box
-    float4 ob[64];                   // the targets of the pass
-    uint32_t cs[kDenseChunk];        // slots of the staged candidates
-    unsigned long long acc[4 * 64];  // per target: force x, y, z (2^-40 units); counts | error bound << 32
-    uint32_t pre[28];                // prefix of the candidate counts of the 27 boxes (entry 27: total)
-    uint32_t src[27];                // first slot of each of the 27 boxes
-    uint32_t queue[2 * 64];          // survivors: target lane | staged candidate << 6
+    Pay buf[kDenseChunk];                      // staged candidates, in the frame of the targets' box
+    Pay ob[64];                                // the targets of the pass
+    uint32_t cs[kDenseChunk];                  // slots of the staged candidates
+    unsigned long long acc[kDenseWords * 64];  // per target, see kDenseWords
+    uint32_t pre[28];                          // prefix of the candidate counts of the 27 boxes (entry 27: total)
+    uint32_t src[27];                          // first slot of each of the 27 boxes
+    uint32_t queue[2 * 64];                    // survivors: target lane | staged candidate << 6
 };
 
 // The passes of group pg of box (gx, gy, gz): targets pg * 64 .. pg * 64 + 63,
@@ -512,14 +568,9 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
     const uint32_t tbeg = d.box_start[S.sb_off + m];
     const uint32_t cnt = d.box_start[S.sb_off + m + 1] - tbeg;
     if (cnt <= (uint32_t)pg * 64u) return;  // no pass in this group
-    const float Lf = (float)S.L;
-    const float e = S.e_delta, g = 2.0f * e;
-    const float kf = (float)S.k, gf = (float)S.gamma;
-    const float L2 = (float)(S.L * S.L);
-    const float G = (float)ldexp(S.L * S.L, -18);
-    const float L2m = L2 - G, L2p = L2 + G;
+    const float kU = S.kU, gU = S.gU;
     const int64_t lin = linear_box(gx, gy, gz, S.dims);
-    float4 *buf = W.buf, *ob = W.ob;
+    Pay *buf = W.buf, *ob = W.ob;
     uint32_t *cs = W.cs, *pre = W.pre, *src = W.src, *qw = W.queue;
     unsigned long long *acc = W.acc;
     // prefix of the candidate counts of the 27 boxes (lane b: box b, x fastest)
@@ -538,6 +589,7 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
         if (lane >= off) inc += o;
     }
     const uint32_t T = __shfl(inc, 26);  // candidates of the 27 boxes
+    const bool huge = T > kDenseMaxCand;  // (wave-uniform) every target goes to the FP64 path
     __builtin_amdgcn_wave_barrier();
     if (lane < 28) pre[lane] = inc - nnb;  // lane 27: T
     if (lane < 27) src[lane] = srcb;
@@ -556,18 +608,19 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
         const uint8_t fl = d.flags[lp][i];
         const bool stat = tv && S.detect_static && (fl & kStatic);
         const bool act = tv && !stat;
-        if (stat && sid == 0) skip_static<false>(d, i, P, lp, fl, lin);
-        const float4 own = d.payload[slot];
+        if (stat && sid == 0) skip_static<false>(d, S, i, P, lp, fl, lin);
+        if (huge) {
+            if (act && sid == 0) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
+            continue;
+        }
+        const Pay own = d.payload[slot];
         __builtin_amdgcn_wave_barrier();
         if (sid == 0) {
             ob[tl] = own;
-            acc[4 * tl] = 0;
-            acc[4 * tl + 1] = 0;
-            acc[4 * tl + 2] = 0;
-            acc[4 * tl + 3] = 0;
+            for (int w = 0; w < kDenseWords; ++w) acc[kDenseWords * tl + w] = 0;
         }
         __builtin_amdgcn_wave_barrier();
-        const float owg = own.w + g;
+        const float owg = own.r + kReach;
         uint32_t qn = 0;  // wave-uniform queue fill
         for (uint32_t cb0 = 0; cb0 < T; cb0 += kDenseChunk) {
             const uint32_t mc = T - cb0 < (uint32_t)kDenseChunk ? T - cb0 : (uint32_t)kDenseChunk;
@@ -575,7 +628,7 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
             // flight together): box and slot first (the slot goes to LDS at
             // once, the boxes stay packed in one register), then the shift
             // into the targets' frame (box b is at offset (b % 3 - 1,
-            // b / 3 % 3 - 1, b / 9 - 1) boxes)
+            // b / 3 % 3 - 1, b / 9 - 1) boxes: exact integer multiples of L)
             static_assert(kDenseChunk <= 3 * 64, "three candidates per lane");
             uint32_t vb = 0;
             for (int h = 0; h < 3; ++h) {
@@ -591,7 +644,7 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
                     cs[q] = src[lo] + (kk - pre[lo]);
                 }
             }
-            float4 v[3];
+            Pay v[3];
 #pragma unroll
             for (int h = 0; h < 3; ++h) {
                 const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
@@ -602,10 +655,10 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
                 const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
                 if (q < mc) {
                     const int b = (int)((vb >> (8 * h)) & 0xffu);
-                    float4 cc = v[h];
-                    cc.x += (float)(b % 3 - 1) * Lf;
-                    cc.y += (float)(b / 3 % 3 - 1) * Lf;
-                    cc.z += (float)(b / 9 - 1) * Lf;
+                    Pay cc = v[h];
+                    cc.x += (b % 3 - 1) * kUnitL;
+                    cc.y += (b / 3 % 3 - 1) * kUnitL;
+                    cc.z += (b / 9 - 1) * kUnitL;
                     buf[q] = cc;
                 }
             }
@@ -613,10 +666,10 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
             for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
                 const uint32_t j = j0 + (uint32_t)sid;
                 const bool in = j < mc && act;
-                const float4 cc = buf[j < mc ? j : 0u];
-                const float ddx = own.x - cc.x, ddy = own.y - cc.y, ddz = own.z - cc.z;
+                const Pay cc = buf[j < mc ? j : 0u];
+                const float ddx = (float)(own.x - cc.x), ddy = (float)(own.y - cc.y), ddz = (float)(own.z - cc.z);
                 const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                const float sg = owg + cc.w;  // the reach test of pair_math
+                const float sg = owg + cc.r;
                 const bool hit = in && d2 < sg * sg;
                 // (all lanes test one candidate here, so many trips have no
                 // survivor at all: the append is skipped on those)
@@ -629,7 +682,7 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
                     qn += (uint32_t)__popcll(mh);
                     if (qn >= 64) {
                         __builtin_amdgcn_wave_barrier();
-                        drain_dense(qw, 64u, ob, buf, cs, tslot0, acc, e, g, kf, gf, L2m, L2p);
+                        drain_dense(qw, 64u, ob, buf, cs, tslot0, acc, kU, gU);
                         __builtin_amdgcn_wave_barrier();
                         qn -= 64;
                         if ((uint32_t)lane < qn) qw[lane] = qw[64 + lane];
@@ -639,28 +692,25 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
             }
             if (qn) {  // the chunk is restaged next: drain the rest now
                 __builtin_amdgcn_wave_barrier();
-                drain_dense(qw, qn, ob, buf, cs, tslot0, acc, e, g, kf, gf, L2m, L2p);
+                drain_dense(qw, qn, ob, buf, cs, tslot0, acc, kU, gU);
                 qn = 0;
             }
             __builtin_amdgcn_wave_barrier();
         }
         if (!act || sid != 0) continue;
-        const unsigned long long am = acc[4 * tl + 3];
-        const uint32_t ac = (uint32_t)am;
-        const int nz_min = (int)(ac & 0xffffu), nz_unc = (int)((ac >> 16) & 0x7fffu);
-        bool unc = (ac & (uint32_t)kUncBit) != 0 || !nz_decided(S, nz_min, nz_unc);
+        const unsigned long long *a = acc + kDenseWords * tl;
+        const unsigned long long ac = a[3], am = a[4];
+        bool unc = (ac >> 32) != 0;
         if (!unc) {
-            const double fx = (double)(long long)acc[4 * tl] * kFixUnit;
-            const double fy = (double)(long long)acc[4 * tl + 1] * kFixUnit;
-            const double fz = (double)(long long)acc[4 * tl + 2] * kFixUnit;
-            const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
-            const double ebound = (double)(uint32_t)(am >> 32) * 0x1.0p-26 + 1e-9;
-            if (fabs(fnorm - S.adherence) <= ebound) {
-                unc = true;
-            } else {
+            const double fx = (double)(long long)a[0] * kFixUnit;
+            const double fy = (double)(long long)a[1] * kFixUnit;
+            const double fz = (double)(long long)a[2] * kFixUnit;
+            const int nc = (int)(uint32_t)ac;
+            if (fp32_certified(S, fx, fy, fz, (double)(am >> 32) * 0x1.0p-24, (double)(uint32_t)am * 0x1.0p-12))
                 commit_agent<false>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy, fz,
-                                    nz_min + nz_unc, 0, nz_min + nz_unc, m, lin);
-            }
+                                    nc, 0, nc, m, lin);
+            else
+                unc = true;
         }
         if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
     }
@@ -716,11 +766,11 @@ __device__ inline void queue_dense_unit(const Dev &d, const uint32_t *sbeg, int6
 // staged in the wave's slice of the LDS stage.
 template <bool DIAG>
 __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> &L, int P, int lp, int qx, int qy,
-                                 int qz, float e, float g, float kf, float gf, float L2m, float L2p) {
+                                 int qz) {
     const int64_t A = d.A;
-    const float Lf = (float)S.L;
+    const float kU = S.kU, gU = S.gU;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    float4 *buf = L.sp + 64 * w;  // the LDS stage is free on this path: 64 candidates per wave
+    Pay *buf = L.sp + 64 * w;  // the LDS stage is free on this path: 64 candidates per wave
     for (int c = w; c < kCore; c += blockDim.x >> 6) {
         int cx, cy, cz;
         core_box_coords(c, cx, cy, cz);
@@ -742,17 +792,18 @@ __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> 
             const uint8_t fl = d.flags[lp][i];
             const bool stat = tv && S.detect_static && (fl & kStatic);
             const bool act = tv && !stat;
-            if (stat && sid == 0) skip_static<DIAG>(d, i, P, lp, fl, lin);
-            Acc a = {0, 0, 0, 0u, 0, 0, 0, 0, 0, false};
-            const float4 own = d.payload[slot];
+            if (stat && sid == 0) skip_static<DIAG>(d, S, i, P, lp, fl, lin);
+            Acc a = {0ull, 0ull, 0ull, 0ull, 0ull, 0, 0, 0, 0};
+            const Pay own = d.payload[slot];
             for (int oz = -1; oz <= 1; ++oz)
                 for (int oy = -1; oy <= 1; ++oy) {
                     const int row = cx + kHalo * ((cy + 1 + oy) + kHalo * (cz + 1 + oz));
-                    const float qy2 = own.y - (float)oy * Lf;
-                    const float qz2 = own.z - (float)oz * Lf;
+                    // the target in the frame of the candidate's box (exact integers)
+                    const int32_t qy2 = own.y - oy * kUnitL;
+                    const int32_t qz2 = own.z - oz * kUnitL;
                     for (int ox = -1; ox <= 1; ++ox) {
                         const int lbb = row + ox + 1;
-                        const float qx2 = own.x - (float)ox * Lf;
+                        const int32_t qx2 = own.x - ox * kUnitL;
                         const uint32_t b0 = L.gsrc[lbb], nn = L.sbeg[lbb + 1] - L.sbeg[lbb];
                         // the box's candidates 64 at a time: one coalesced load
                         // per chunk into this wave's LDS slice, then broadcast reads
@@ -764,9 +815,8 @@ __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> 
                             for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
                                 const uint32_t j = j0 + (uint32_t)sid;
                                 const bool in = j < mc && act;
-                                const float4 cc = buf[j < mc ? j : 0u];
-                                if (in && b0 + c0 + j != slot)
-                                    pair_fp32<DIAG>(a, qx2, qy2, qz2, own.w, cc, e, g, kf, gf, L2m, L2p);
+                                const Pay cc = buf[j < mc ? j : 0u];
+                                if (in && b0 + c0 + j != slot) pair_acc<DIAG>(a, qx2, qy2, qz2, own.r, cc, kU, gU);
                             }
                         }
                     }
@@ -774,20 +824,18 @@ __device__ void sweep_unit_dense(const Dev &d, const SimDesc &S, SweepLds<DIAG> 
             acc_reduce_streams(a, gsz);
             p0 += (uint32_t)gsz;
             if (!act || sid != 0) continue;
-            bool unc = a.unc || !nz_decided(S, a.nz, a.nz_unc);
+            bool unc = a.unc != 0;
             if (!unc) {
                 const unsigned long long mb = (unsigned long long)a.nfix * fixbits(kFixMagic);
                 const double fx = (double)(long long)(a.ax - mb) * kFixUnit;
                 const double fy = (double)(long long)(a.ay - mb) * kFixUnit;
                 const double fz = (double)(long long)(a.az - mb) * kFixUnit;
-                const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
-                const double ebound = (double)a.eacc * 0x1.0p-26 + 1e-9;
-                if (fabs(fnorm - S.adherence) <= ebound) {
-                    unc = true;
-                } else {
+                if (fp32_certified(S, fx, fy, fz, (double)a.eacc * 0x1.0p-28, (double)a.sacc * 0x1.0p-17)) {
                     const uint32_t m = box_rank(d, S, qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz);
                     commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
-                                       fz, a.nz + a.nz_unc, a.nbr, a.contacts, m, lin);
+                                       fz, a.contacts, a.nbr, a.contacts, m, lin);
+                } else {
+                    unc = true;
                 }
             }
             if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
@@ -911,18 +959,13 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
             nt = (uint32_t)(tot >> 32);
         }
         __syncthreads();
-        const float Lf = (float)S.L;
-        const float e = S.e_delta, g = 2.0f * e;
-        const float kf = (float)S.k, gf = (float)S.gamma;
-        const float L2 = (float)(S.L * S.L);
-        const float G = (float)ldexp(S.L * S.L, -18);
-        const float L2m = L2 - G, L2p = L2 + G;
-        // largest reach beyond the target radius: largest radius, guard band
-        // and a margin of 2^-10 L for the block-relative FP32 coordinates
-        const float reach_add = (float)S.rmax + g + (float)ldexp(S.L, -10);
+        const float kU = S.kU, gU = S.gU;
+        // largest reach beyond the target radius (U units): largest radius,
+        // reach guard and a margin of 2^-10 L for the FP32 face distances
+        const float reach_add = (float)ldexp(S.rmax / S.L, kFixBits) + kReach + (float)(1 << (kFixBits - 10));
         const bool lds_path = total <= (uint32_t)kStage && nt <= (uint32_t)kMaxT;
         if (!lds_path) {  // box-wise: in the diagnostic mode here, else queued for k_sweep_dense
-            if constexpr (DIAG) sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            if constexpr (DIAG) sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz);
             else queue_dense_unit(d, L.sbeg, u);
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
@@ -936,7 +979,7 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
         for (uint32_t k = tid; k < total; k += blockDim.x) {
             const int lo = smap[k];
             const uint32_t kb = k - L.sbeg[lo];
-            float4 c = d.payload[L.gsrc[lo] + kb];
+            Pay c = d.payload[L.gsrc[lo] + kb];
             const int lx = lo % kHalo, ly = (lo / kHalo) % kHalo, lz = lo / (kHalo * kHalo);
             uint16_t tm = kNoTarget;
             if (lx >= 1 && lx <= kBlk && ly >= 1 && ly <= kBlk && lz >= 1 && lz <= kBlk) {
@@ -948,7 +991,7 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
                     const int64_t i = ia;
                     const uint8_t fl = d.flags[lp][i];
                     if (fl & kStatic) {
-                        skip_static<DIAG>(d, i, P, lp, fl,
+                        skip_static<DIAG>(d, S, i, P, lp, fl,
                                           linear_box(qx * kBlk + lx - 1, qy * kBlk + ly - 1, qz * kBlk + lz - 1,
                                                      S.dims));
                         stat = true;
@@ -966,9 +1009,10 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
                 if (DIAG) L.anbr[t] = 0;
                 if (!stat) tm = (uint16_t)t;
             }
-            c.x += (float)(lx - 3) * Lf;
-            c.y += (float)(ly - 3) * Lf;
-            c.z += (float)(lz - 3) * Lf;
+            // relative to the region centre: exact integer shifts, |x| <= 3L
+            c.x += (lx - 3) * kUnitL;
+            c.y += (ly - 3) * kUnitL;
+            c.z += (lz - 3) * kUnitL;
             L.sp[k] = c;
             L.tmap[k] = tm;
         }
@@ -1000,7 +1044,7 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
             if (self == kNoTarget) continue;
             int cx, cy, cz;
             core_box_coords(L.tbox[t], cx, cy, cz);
-            const uint32_t rows = row_mask<DIAG>(L.sp[self], cx, cy, cz, Lf, reach_add);
+            const uint32_t rows = row_mask<DIAG>(L.sp[self], cx, cy, cz, reach_add);
 #pragma unroll
             for (int r = 0; r < kRows; ++r) {
                 uint32_t b0, len;
@@ -1025,7 +1069,7 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
         }
         __syncthreads();
         if (L.ntask > (uint32_t)kTaskCap) {  // rare: more tasks than the list holds; box-wise as above
-            if constexpr (DIAG) sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz, e, g, kf, gf, L2m, L2p);
+            if constexpr (DIAG) sweep_unit_dense<DIAG>(d, S, L, P, lp, qx, qy, qz);
             else queue_dense_unit(d, L.sbeg, u);
             __syncthreads();  // the next unit reuses the LDS tables
             continue;
@@ -1057,8 +1101,8 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
                 const uint32_t b0 = (tk >> 9) & 1023u;
                 const uint32_t len = tv ? tk >> 19 : 0u;
                 const uint32_t self = L.tself[t];
-                const float4 own = L.sp[self];
-                const float owg = own.w + g;
+                const Pay own = L.sp[self];
+                const float owg = own.r + kReach;
                 const uint32_t tq = (t << 20) | (self << 10) | b0;  // + kk: b0 + kk < kStage
                 uint32_t nb = 0;
                 bool un = false;
@@ -1081,38 +1125,36 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
                 // end read clamped indices and are masked
                 uint32_t kk = 0;
                 if (minlen >= 2) {
-                    const float4 *row = L.sp + b0;
-                    float4 ca = row[0];
+                    const Pay *row = L.sp + b0;
+                    Pay ca = row[0];
                     for (; kk + 1u < minlen; kk += 2) {
-                        const float4 cb = row[kk + 1u];
-                        reach_test<DIAG, false>(L, qw, qn, own, owg, ca, kk, len, tq, self, b0, nb, un, e, g, kf, gf,
-                                                L2m, L2p, n3);
+                        const Pay cb = row[kk + 1u];
+                        reach_test<DIAG, false>(L, qw, qn, own, owg, ca, kk, len, tq, self, b0, nb, un, kU, gU, n3);
                         ca = row[kk + 2u];
-                        reach_test<DIAG, false>(L, qw, qn, own, owg, cb, kk + 1u, len, tq, self, b0, nb, un, e, g, kf,
-                                                gf, L2m, L2p, n3);
+                        reach_test<DIAG, false>(L, qw, qn, own, owg, cb, kk + 1u, len, tq, self, b0, nb, un, kU, gU,
+                                                n3);
                     }
                 }
                 if (kk < maxlen) {
                     const uint32_t last = (uint32_t)kStage - 1u;
-                    float4 ca = L.sp[min(b0 + kk, last)];
+                    Pay ca = L.sp[min(b0 + kk, last)];
                     for (; kk < maxlen; kk += 2) {
-                        const float4 cb = L.sp[min(b0 + kk + 1u, last)];
-                        reach_test<DIAG, true>(L, qw, qn, own, owg, ca, kk, len, tq, self, b0, nb, un, e, g, kf, gf,
-                                               L2m, L2p, n3);
+                        const Pay cb = L.sp[min(b0 + kk + 1u, last)];
+                        reach_test<DIAG, true>(L, qw, qn, own, owg, ca, kk, len, tq, self, b0, nb, un, kU, gU, n3);
                         ca = L.sp[min(b0 + kk + 2u, last)];
                         if (kk + 1u < maxlen)
-                            reach_test<DIAG, true>(L, qw, qn, own, owg, cb, kk + 1u, len, tq, self, b0, nb, un, e, g,
-                                                   kf, gf, L2m, L2p, n3);
+                            reach_test<DIAG, true>(L, qw, qn, own, owg, cb, kk + 1u, len, tq, self, b0, nb, un, kU,
+                                                   gU, n3);
                     }
                 }
                 if (DIAG && tv) {
                     atomicAdd(&L.anbr[t], nb);
-                    if (un) atomicOr(&L.acm[t], kUncBit);
+                    if (un) atomicAdd(&L.acc[1][t], kCnt1);
                 }
             }
             if (qn) {
                 __builtin_amdgcn_wave_barrier();
-                drain_queue<DIAG>(L, qw, qn, e, g, kf, gf, L2m, L2p, n3);
+                drain_queue<DIAG>(L, qw, qn, kU, gU, n3);
             }
         }
         __syncthreads();
@@ -1124,25 +1166,21 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
             core_box_coords(c, cx, cy, cz);
             const int64_t i = L.tidx[t];
             const int64_t lin = linear_box(qx * kBlk + cx, qy * kBlk + cy, qz * kBlk + cz, S.dims);
-            const unsigned long long acm = L.acm[t];
-            const uint32_t ac = (uint32_t)acm;
-            const int nz_min = (int)(ac & 0xffffu), nz_unc = (int)((ac >> 16) & 0x7fffu);
-            bool unc = (ac & (uint32_t)kUncBit) != 0 || !nz_decided(S, nz_min, nz_unc);
+            const unsigned long long w0 = L.acc[0][t], w1 = L.acc[1][t], w2 = L.acc[2][t], wm = L.acm[t];
+            const long long fxi = fix_field(w0), fyi = fix_field(w1), fzi = fix_field(w2);
+            bool unc = cnt_field(w1, fyi) != 0;
             if (!unc) {
-                const double fx = (double)(long long)L.acc[0][t] * kFixUnit;
-                const double fy = (double)(long long)L.acc[1][t] * kFixUnit;
-                const double fz = (double)(long long)L.acc[2][t] * kFixUnit;
-                const double fnorm = sqrt(fx * fx + fy * fy + fz * fz);
-                const double ebound = (double)(uint32_t)(acm >> 32) * 0x1.0p-26 + 1e-9;
-                if (fabs(fnorm - S.adherence) <= ebound) {
-                    unc = true;
-                } else {
-                    const int nzc = nz_min + nz_unc;
+                const double fx = (double)fxi * kFixUnit, fy = (double)fyi * kFixUnit, fz = (double)fzi * kFixUnit;
+                if (fp32_certified(S, fx, fy, fz, (double)(uint32_t)(wm >> 32) * 0x1.0p-28,
+                                   (double)(uint32_t)wm * 0x1.0p-17)) {
+                    const int nc = (int)cnt_field(w0, fxi);
                     // box slot: the unit's block has Morton rank u - wblk_begin (its blist entry)
                     const uint32_t m = (uint32_t)(u - wblk[s]) * 64u + local_morton(cx, cy, cz);
                     const uint8_t fl = d.flags[lp][i];
                     commit_agent<DIAG>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy,
-                                       fz, nzc, DIAG ? (int)L.anbr[t] : 0, nzc, m, lin);
+                                       fz, nc, DIAG ? (int)L.anbr[t] : 0, nc, m, lin);
+                } else {
+                    unc = true;
                 }
             }
             if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;

@@ -9,7 +9,14 @@ contact of an agent inside an inner cube therefore lies inside that cube
 grown by L on each side, and the oracle is given only the grown cube.  The
 oracle's own grid over that sub-population differs from the GPU's, but the
 set of touching pairs, hence the force (Eq 4.1-4.2) and the displacement,
-does not depend on where the boxes fall."""
+does not depend on where the boxes fall.
+
+The population records each agent's force, contact count and displacement
+(ABM_RECORD: the same kernels, which also write these fields), so forces and
+counts are compared agent by agent at the parity tolerance: per agent within
+1e-5 of the sum of |F_N| of its contacts, contact and non-zero-force counts
+exact, the same move decisions and positions within dt/m times the force
+tolerance."""
 import time
 
 import numpy as np
@@ -56,9 +63,14 @@ def _check_step(abm, pop, op, rng, n_regions):
     pos0 = pop.query(abm.POS)
     diam0 = pop.query(abm.DIAM)
     uid0 = pop.query(abm.UID).astype(np.int64)
+    stat0 = pop.query(abm.STATIC)
     pop.step(1)
+    # recorded fields are indexed like the state at the start of the step
+    f_rec = pop.query(abm.FORCE)
+    c_rec = pop.query(abm.CONTACT_COUNT)
     pos1 = pop.query(abm.POS)
     uid1 = pop.query(abm.UID).astype(np.int64)
+    nz1 = pop.query(abm.NZ)
     n = pos0.shape[0]
     assert pos1.shape[0] == n
     # no growth here: the uids stay a permutation of 0..n-1
@@ -68,7 +80,7 @@ def _check_step(abm, pop, op, rng, n_regions):
     lo, hi = pos0.min(axis=0), pos0.max(axis=0)
     scale = op.dt / op.mass
     checked = moved = 0
-    worst = 0.0
+    worst = worst_f = 0.0
     for c in _centres(lo, hi, rng, n_regions):
         cand = np.nonzero(np.abs(pos0[:, 0] - c[0]) < HALF + L + 0.5)[0]
         grown = cand[np.all(np.abs(pos0[cand] - c) < HALF + L + 0.5, axis=1)]
@@ -77,21 +89,37 @@ def _check_step(abm, pop, op, rng, n_regions):
         if inner.size == 0:
             continue
         o = osim.OracleSim(p_sub, diam0[grown], op, uid=uid0[grown])
-        _, _, d, tol = o.forces_subset(inner)
+        f_o, cnt_o, d, tol = o.forces_subset(inner)
+        g_idx = grown[inner]
+        # agents flagged static are skipped (force not computed, Sec 5.5); the
+        # sweep does not visit units that hold only such agents, so their
+        # recorded fields are older values: compare the others
+        skip = stat0[g_idx] != 0
+        assert np.all(skip[c_rec[g_idx] < 0]), "an agent recorded as skipped is not flagged static"
+        act = ~skip
+        ftol = 1e-5 * tol[:, 0] + 1e-12
+        ferr = np.linalg.norm(f_rec[g_idx] - f_o, axis=1)
+        assert np.all(ferr[act] <= ftol[act]), f"forces differ in the cube at {c}: worst {float((ferr / ftol)[act].max())}"
+        assert np.array_equal(c_rec[g_idx][act], cnt_o[act, 1]), f"contact counts differ in the cube at {c}"
+        assert np.array_equal(nz1[inv[uid0[g_idx]]][act], np.minimum(cnt_o[act, 2], 255)), "nz counts differ"
         start = p_sub[inner]
-        expect = start + d
-        got = pos1[inv[uid0[grown][inner]]]
-        mv_o = np.any(d != 0, axis=1)
+        expect = start + np.where(act[:, None], d, 0.0)
+        got = pos1[inv[uid0[g_idx]]]
+        mv_o = np.any(expect != start, axis=1)
         mv_g = np.any(got != start, axis=1)
-        assert np.array_equal(mv_g, mv_o), f"move decisions differ in the cube at {c}"
-        bound = scale * (1e-5 * tol[:, 0] + H.E_DELTA_REL * L * (tol[:, 1] + tol[:, 2])) + 1e-12
-        err = np.linalg.norm(got - expect, axis=1)
-        ok = err <= bound + 1e-13 * np.abs(expect).max(axis=1)
-        assert np.all(ok), f"positions differ in the cube at {c}: worst err/bound {float((err / bound).max())}"
+        # threshold ties (|F| within 1e-6 sum |F_N| of the adherence) may go either way
+        tie = act & (np.abs(np.linalg.norm(f_o, axis=1) - op.adherence) <= 1e-6 * tol[:, 0])
+        assert np.array_equal(mv_g[~tie], mv_o[~tie]), f"move decisions differ in the cube at {c}"
+        bound = 2.0 * scale * ftol + 1e-13 * np.abs(expect).max(axis=1)
+        err = np.where(tie, 0.0, np.linalg.norm(got - expect, axis=1))
+        assert np.all(err <= bound), f"positions differ in the cube at {c}: worst err/bound {float((err / bound).max())}"
         checked += inner.size
         moved += int(mv_o.sum())
         worst = max(worst, float((err / bound).max()))
-    _say(f"  checked {checked} agents ({moved} moved), worst err/bound {worst:.3g}, "
+        if act.any():
+            worst_f = max(worst_f, float((ferr / ftol)[act].max()))
+    _say(f"  checked {checked} agents ({moved} moved), worst force err/tol {worst_f:.3g}, "
+         f"worst position err/bound {worst:.3g}, FP64 path {pop.fp64_agents()} agents, "
          f"{time.perf_counter() - t0:.1f} s")
     assert checked > 1000
     return moved
@@ -101,7 +129,7 @@ def _check_step(abm, pop, op, rng, n_regions):
 @pytest.mark.parametrize("kind", ["uniform", "relaxed"])
 def test_full_size_sampled_agents_match_oracle(abm, kind):
     t0 = time.perf_counter()
-    pop, n, _, _ = bench.mechanics_population(kind, N_AGENTS)
+    pop, n, _, _ = bench.mechanics_population(kind, N_AGENTS, record=True)
     _say(f"[{kind}] {n} agents uploaded in {time.perf_counter() - t0:.1f} s")
     op = H.oracle_params(detect_static=(kind == "relaxed"))
     rng = np.random.default_rng(11)

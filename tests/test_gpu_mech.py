@@ -45,8 +45,11 @@ def test_c0_every_iteration_matches_oracle_single_step(abm, detect_static, workl
                                                      (True, "crowded"), (False, "dense"), (False, "dense_small"),
                                                      (False, "packed"), (False, "coincident")])
 def test_production_path_single_step_matches_oracle(abm, detect_static, workload):
-    """The launch configuration of the benchmark (no diagnostics: row culling
-    and reach tests active) against the oracle, one iteration at a time.  The
+    """The launch configuration of the benchmark (no diagnostics: half shell,
+    row culling, reach tests and unit skipping active; ABM_RECORD only adds
+    the writes of each agent's force, counts and displacement) against the
+    oracle, one iteration at a time, agent by agent: counts exact, forces
+    within 1e-5 of the sum of |F_N|, move decisions and positions.  The
     dense workloads overflow the LDS stage of a unit and take the box-wise
     path: about 7 agents per box (one candidate chunk per core box), 19 small
     agents per box (several chunks) and 80 per box (several passes over the
@@ -76,7 +79,7 @@ def test_production_path_single_step_matches_oracle(abm, detect_static, workload
         pos = pos.copy()
         pos[4000:4032] = pos[0:32]
         pos[4032:4064] = pos[32:64] + 1e-9
-    gp = H.gpu_params(abm, detect_static=detect_static)
+    gp = H.gpu_params(abm, detect_static=detect_static, record=True)
     b = abm.Population(gp, pos, diam, capacity=4096, box_capacity=1 << 16)
     op = H.oracle_params(detect_static=detect_static)
     st = H.gpu_state(abm, b)
@@ -84,7 +87,7 @@ def test_production_path_single_step_matches_oracle(abm, detect_static, workload
         o = H.oracle_from_state(st, op, iteration=it)
         b.step(1)
         o.step(1)
-        res = H.compare_positions_single_step(abm, b, o, st["pos"])
+        res = H.compare_single_step(abm, b, o, check_static=detect_static, check_nbr=False)
         print(f"iter {it}: {res}", flush=True)
         st = H.gpu_state(abm, b)
 
@@ -107,7 +110,7 @@ def test_c0_trajectory_error_and_determinism(abm):
     disp = np.linalg.norm(po - pos, axis=1)
     print(f"C0 10-iteration trajectory: max {err.max():.3e} um, rms {np.sqrt((err**2).mean()):.3e} um, "
           f"normwise rel displacement error {np.linalg.norm(pg - po) / np.linalg.norm(po - pos):.3e}", flush=True)
-    assert np.linalg.norm(pg - po) / np.linalg.norm(po - pos) < 1e-3
+    assert np.linalg.norm(pg - po) / np.linalg.norm(po - pos) < 1e-5
 
 
 @pytest.mark.parametrize("workload", ["c0", "relaxed_lattice"])
@@ -192,7 +195,7 @@ def test_spheroid_scale_run_first_100_iterations(abm):
     vdiv = inputs.division_volume(12.0)
     counts = bench.lineage_counts(vol, growth, vdiv, 100)
     cap = int(counts[-1]) + 1024
-    gp = abm.params(box_len=0.0, div_vol=vdiv, seed=3, resort_every=10, detect_static=False)
+    gp = abm.params(box_len=0.0, div_vol=vdiv, seed=3, resort_every=10, detect_static=False, record=True)
     op = H.oracle_params(box_len=0.0, div_vol=vdiv, seed=3)
     b = abm.Population(gp, pos, diam, vol=vol, growth=growth, capacity=cap)
     first_div = int(np.argmax(counts > 1000))
@@ -200,18 +203,20 @@ def test_spheroid_scale_run_first_100_iterations(abm):
     for it in range(100):
         if it in checks:
             st = H.gpu_state(abm, b)
-            _, L0, _ = b.grid()
             nu = int(st["uid"].max()) + 1
             o = H.oracle_from_state(st, op, cap=cap, next_uid=nu, iteration=it)
             b.step(1)
             o.step(1)
-            _, L1, _ = b.grid()
             ug = b.query(abm.UID)
             og, oo = np.argsort(ug), np.argsort(o.uid[:o.n])
             assert np.array_equal(ug[og], o.uid[:o.n][oo])
             assert np.array_equal(b.query(abm.VOL)[og], o.vol[:o.n][oo])
             assert np.array_equal(b.query(abm.DIAM)[og], o.diam[:o.n][oo])
-            H.compare_positions_single_step(abm, b, o, st["pos"], L=max(L0, L1))
+            if (it + 1) % 10:  # the recorded fields follow the storage order of a step without a re-sort
+                res = H.compare_single_step(abm, b, o, check_static=False, check_nbr=False)
+                print(f"iteration {it}: {res}", flush=True)
+            else:
+                H.compare_positions_single_step(abm, b, o, st["pos"])
             err = np.abs(b.query(abm.POS)[og] - o.pos()[oo]).max()
             assert err <= 1e-4, err
             print(f"iteration {it}: {o.n} agents, max position error {err:.2e} um", flush=True)
@@ -234,8 +239,8 @@ def test_growth_single_step_parity_after_divisions(abm):
     o = H.oracle_from_state(st, op, cap=8192, next_uid=nu, iteration=12)
     b.step(1)
     o.step(1)
-    lo, L, dims = b.grid()
-    H.compare_single_step(abm, b, o, L=L, check_static=False)
+    res = H.compare_single_step(abm, b, o, check_static=False)
+    print(res, flush=True)
 
 
 def test_resort_keeps_results_and_orders_by_morton(abm):
