@@ -342,7 +342,9 @@ void forward(abm_mlp *h, int B) {
         GemmArgs g{};
         g.M = B;
         g.N = Ls.out[l];
-        g.K = Ls.ldk[l];
+        // the input is zero padded to ldk[0]; hidden activations are rows of
+        // out[l - 1] (the tile reads zeros past K)
+        g.K = l == 0 ? Ls.ldk[0] : Ls.in[l];
         g.A = h->hbf[l];
         g.lda = l == 0 ? Ls.ldk[0] : Ls.out[l - 1];
         g.transA = 0;
