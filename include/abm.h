@@ -234,6 +234,20 @@ int abm_mlp_grads(abm_mlp *m, const float *x, const float *y, int batch, float *
 /* Forward pass: y = MLP(x) for a batch (device FP32). */
 int abm_mlp_infer(abm_mlp *m, const float *x, float *y, int batch);
 
+/* The forward pass of abm_mlp_infer (the same kernels and arithmetic, so the
+ * same y bit for bit) for callers that cannot allocate: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  It calls no
+ * allocating routine: its activations go to a fixed device array of 12 MiB
+ * inside the library, which every GPU the library runs on holds until the
+ * process ends.  Limits: batch 1..4096 and input and hidden widths up to 512
+ * (ABM_ERR_ARG beyond them; max_batch of the handle does not apply).  The
+ * first call on a device looks up that device's copy of the array with the
+ * device current, so call it with the handle's device current.  All calls on
+ * one GPU share the array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * x: batch x dims[0], y: batch x dims[last], device FP32, on the handle's stream. */
+int abm_mlp_infer_noalloc(abm_mlp *m, const float *x, float *y, int batch);
+
 /* Copy the FP32 master parameters out of / into the handle (device FP32). */
 int abm_mlp_get_params(abm_mlp *m, float *dst, size_t n);
 int abm_mlp_set_params(abm_mlp *m, const float *src, size_t n);

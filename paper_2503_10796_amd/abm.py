@@ -93,6 +93,7 @@ def lib():
         L.abm_mlp_train_step.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_float, _fp]
         L.abm_mlp_grads.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, _fp]
         L.abm_mlp_infer.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+        L.abm_mlp_infer_noalloc.argtypes = [_vp, _vp, _vp, ctypes.c_int]
         L.abm_mlp_get_params.argtypes = [_vp, _vp, ctypes.c_size_t]
         L.abm_mlp_set_params.argtypes = [_vp, _vp, ctypes.c_size_t]
         L.abm_mlp_num_params.restype = ctypes.c_size_t
@@ -347,6 +348,14 @@ class Mlp:
         y = out if out is not None else torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device="cuda")
         check(lib().abm_mlp_infer(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), x.shape[0]))
         return y
+
+    def infer_noalloc(self, x, out):
+        """The forward pass through abm_mlp_infer_noalloc: x and out are
+        device FP32 tensors the caller allocated (batch x dims[0], batch x
+        dims[-1]); the library allocates nothing."""
+        check(lib().abm_mlp_infer_noalloc(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          x.shape[0]))
+        return out
 
     def get_params(self):
         torch = _torch()

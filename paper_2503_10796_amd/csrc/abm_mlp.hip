@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 
 #include "abm_device.h"
@@ -31,7 +32,7 @@ constexpr int kMaxLayers = 8;
 constexpr int kBM = 64, kBN = 64, kBK = 32;  // GEMM block tile; 4 waves of 32 x 32
 constexpr int kLdsK = kBK + 8;               // padded LDS row (bf16 elements, 80 bytes)
 
-enum GemmMode { kFwdHidden = 0, kFwdOut = 1, kBwdInput = 2, kBwdWeight = 3 };
+enum GemmMode { kFwdHidden = 0, kFwdOut = 1, kBwdInput = 2, kBwdWeight = 3, kFwdHiddenAct = 4 };
 
 struct GemmArgs {
     int M, N, K;
@@ -113,6 +114,9 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
                         g.outb[(size_t)m * g.ldob + n] = (__bf16)gelu(z);
                         break;
                     }
+                    case kFwdHiddenAct:  // inference: the BF16 activation only
+                        g.outb[(size_t)m * g.ldob + n] = (__bf16)gelu(v + g.bias[n]);
+                        break;
                     case kFwdOut:
                         g.outf[(size_t)m * g.ldo + n] = v + g.bias[n];
                         break;
@@ -539,5 +543,85 @@ extern "C" int abm_mlp_destroy(abm_mlp *m) {
     clear_error();
     if (!m) return set_error(ABM_ERR_ARG, "null handle");
     delete m;
+    return ABM_OK;
+}
+
+// ------------------------------------------------------------------ inference without allocation
+// abm_mlp_infer_noalloc: the forward pass of abm_mlp_infer with its
+// activations in a file-scope device array instead of the handle's
+// workspace.  Layout of the array: the BF16 input [B x ldk0], then two BF16
+// activation buffers [B x width] used in turn by the hidden layers; the output
+// layer writes the caller's y.  Each GPU holds its own copy of the array
+// until the process ends, and every call on that GPU shares it.
+namespace {
+constexpr int kNoAllocMaxBatch = 4096;
+constexpr int kNoAllocMaxWidth = 512;  // input width (padded) and hidden widths
+constexpr size_t kNoAllocActBytes = (size_t)kNoAllocMaxBatch * kNoAllocMaxWidth * sizeof(__bf16);
+constexpr size_t kNoAllocBytes = 3 * kNoAllocActBytes;  // 12 MiB
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kNoAllocMaxDevices];  // device address of `scratch` on each device (null: not looked up)
+
+// Device address of the array on the current device, looked up once per
+// device with that device current.
+int noalloc_scratch(char **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(ABM_ERR_HIP, hipGetErrorString(e));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return set_error(ABM_ERR_ARG, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return set_error(ABM_ERR_HIP, "hipGetSymbolAddress of the inference scratch failed");
+        g_scratch_ptr[dev] = (char *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ABM_OK;
+}
+}  // namespace
+
+extern "C" int abm_mlp_infer_noalloc(abm_mlp *m, const float *x, float *y, int batch) {
+    clear_error();
+    if (!m || !x || !y) return set_error(ABM_ERR_ARG, "null argument");
+    if (batch <= 0 || batch > kNoAllocMaxBatch) return set_error(ABM_ERR_ARG, "batch outside 1..4096");
+    const Layers &Ls = m->Ls;
+    if (Ls.ldk[0] > kNoAllocMaxWidth) return set_error(ABM_ERR_ARG, "input width beyond 512");
+    for (int l = 0; l + 1 < Ls.nl; ++l)
+        if (Ls.out[l] > kNoAllocMaxWidth) return set_error(ABM_ERR_ARG, "hidden width beyond 512");
+    char *base = nullptr;
+    int rc = noalloc_scratch(&base);
+    if (rc) return rc;
+    __bf16 *in = (__bf16 *)base;
+    __bf16 *act[2] = {(__bf16 *)(base + kNoAllocActBytes), (__bf16 *)(base + 2 * kNoAllocActBytes)};
+    hipStream_t s = m->stream;
+    hipLaunchKernelGGL(k_to_bf16, dim3(std::min(4096, (batch * Ls.ldk[0] + 255) / 256)), dim3(256), 0, s, x, in, batch,
+                       Ls.in[0], Ls.ldk[0]);
+    for (int l = 0; l < Ls.nl; ++l) {
+        const bool last = l == Ls.nl - 1;
+        GemmArgs g{};
+        g.M = batch;
+        g.N = Ls.out[l];
+        g.K = l == 0 ? Ls.ldk[0] : Ls.in[l];
+        g.A = l == 0 ? in : act[(l - 1) & 1];
+        g.lda = l == 0 ? Ls.ldk[0] : Ls.out[l - 1];
+        g.transA = 0;
+        g.B = m->wbf + Ls.wbf_off[l];
+        g.ldb = Ls.ldk[l];
+        g.transB = 1;
+        g.mode = last ? kFwdOut : kFwdHiddenAct;
+        g.bias = m->theta + Ls.boff[l];
+        g.outf = last ? y : nullptr;
+        g.ldo = Ls.out[l];
+        g.outb = last ? nullptr : act[l & 1];
+        g.ldob = Ls.out[l];
+        gemm(s, g);
+    }
+    MLPCHK(hipGetLastError());
     return ABM_OK;
 }
