@@ -130,9 +130,12 @@ int abm_batch_create(int n_sims, const abm_params *per_sim, const int64_t *n0, c
                      void *workspace, size_t ws_bytes, void *hip_stream, abm_batch **out);
 
 /* Restore per-agent static flags and non-zero-force counts, the next uid and
- * the iteration counter of every simulation (checkpoint resume).  is_static
- * (uint8) and nz (int32) are sum(n) arrays in the creation order; next_uid
- * has n_sims entries.  Must be called right after abm_batch_create. */
+ * the iteration counter of every simulation (checkpoint resume: query a
+ * running batch, create a new one from the queried arrays, restore).
+ * is_static (uint8) and nz (int32) are sum(n) arrays in the creation order;
+ * next_uid has n_sims entries; any of the three may be NULL.  Only valid
+ * right after abm_batch_create, before any step, tune or other restore
+ * (ABM_ERR_ARG otherwise: the state is no longer in creation order). */
 int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const int32_t *nz, const uint64_t *next_uid,
                       int64_t iteration, int on_device);
 

@@ -219,6 +219,7 @@ struct abm_batch {
     int resort_every = 0;
     hipGraphExec_t exec[3][2] = {};  // [part][diag], see capture()
     bool grid_valid = false;         // grid of the current state is built
+    bool fresh = true;               // nothing has run since create (restore is allowed)
     bool timing = false;             // bracket every sweep with events
     std::vector<hipEvent_t> ev;      // event pairs of the last step
     double sweep_ms = 0.0;
@@ -484,6 +485,10 @@ extern "C" int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const i
                                  int64_t iteration, int on_device) {
     g_err.clear();
     if (!b) return fail(ABM_ERR_ARG, "null handle");
+    // the arrays are in creation order: only the untouched state of a new
+    // handle is in that order (a step, the tuner or a restore re-sorts or
+    // changes it)
+    if (!b->fresh) return fail(ABM_ERR_ARG, "restore must directly follow abm_batch_create");
     std::vector<SimDesc> sims;
     int rc = read_sims(b, sims);
     if (rc) return rc;
@@ -512,8 +517,12 @@ extern "C" int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const i
         }
         if (next_uid) {
             uint64_t nu;
-            if (on_device) HIPCHK(hipMemcpy(&nu, next_uid + s, sizeof nu, hipMemcpyDeviceToHost));
-            else nu = next_uid[s];
+            if (on_device) {
+                HIPCHK(hipMemcpyAsync(&nu, next_uid + s, sizeof nu, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+            } else {
+                nu = next_uid[s];
+            }
             if ((int64_t)nu > sims[s].cap) return fail(ABM_ERR_ARG, "next_uid above capacity");
             sims[s].next_uid = (int64_t)nu;
         }
@@ -527,6 +536,7 @@ extern "C" int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const i
     c.iter = iteration;
     HIPCHK(hipMemcpyAsync(b->d.ctl, &c, sizeof c, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
+    b->fresh = false;
     return ABM_OK;
 }
 
@@ -580,6 +590,7 @@ static bool any_diag(const abm_batch *b) {
 // first, and puts agents into Morton order when re-sorting is on; so does the
 // tuner before it replays iterations.
 static int ensure_grid(abm_batch *b) {
+    b->fresh = false;
     if (b->grid_valid) return ABM_OK;
     b->d.resort_every = b->resort_every;
     launch_grid_build(b->d, b->stream, b->grid_agents, b->grid_boxes, b->any_static);

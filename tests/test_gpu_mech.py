@@ -356,3 +356,62 @@ def test_direction_and_cube_root_match_oracle(abm):
         assert np.allclose(p[i], pos[i] - shift * dirv, rtol=0, atol=1e-12)
         assert np.allclose(p[n + i], pos[i] + shift * dirv, rtol=0, atol=1e-12)
         assert d[i] == osim.diameter_from_volume(0.5 * vol[i]) and d[n + i] == d[i]
+
+
+@pytest.mark.parametrize("workload", ["relaxed_lattice", "spheroid"])
+def test_checkpoint_resume_is_bitwise(abm, workload):
+    """Checkpoint and resume (P17): 10 iterations equal 5 iterations, a query
+    of the state, a new population created from it and restored (static
+    flags, non-zero-force counts, next uid, iteration), then 5 iterations --
+    bit for bit, with the static skip, re-sorts and divisions on."""
+    if workload == "relaxed_lattice":
+        pos, diam = inputs.relaxed_lattice(16, seed=2)
+        vol = growth = None
+        gp = H.gpu_params(abm, detect_static=True, resort_every=3)
+        cap = pos.shape[0]
+    else:
+        pos, diam, vol, growth = inputs.spheroid(800, seed=31, growth_scale=25.0)
+        gp = H.gpu_params(abm, box_len=0.0, div_vol=inputs.division_volume(10.0), seed=9, detect_static=True,
+                          resort_every=3)
+        cap = 8192
+    a = abm.Population(gp, pos, diam, vol=vol, growth=growth, capacity=cap, box_capacity=1 << 16)
+    a.step(5)
+    st = H.gpu_state(abm, a)
+    nu = int(st["uid"].max()) + 1
+    b = abm.Population(gp, st["pos"], st["diam"], vol=st["vol"], growth=st["growth"], uid=st["uid"], capacity=cap,
+                       box_capacity=1 << 16)
+    b.restore(is_static=st["static"], nz=st["nz"], next_uid=np.array([nu], dtype=np.uint64), iteration=5)
+    with pytest.raises(abm.AbmError) as e:  # only right after create
+        b.restore(is_static=st["static"], iteration=5)
+    assert e.value.code == abm.ERR_ARG
+    a.step(5)
+    b.step(5)
+    assert int(a.num_agents()[0]) == int(b.num_agents()[0])
+    ua, ub = a.query(abm.UID), b.query(abm.UID)
+    oa, ob = np.argsort(ua), np.argsort(ub)
+    assert np.array_equal(ua[oa], ub[ob])
+    for f in (abm.POS, abm.DIAM, abm.VOL, abm.GROWTH, abm.STATIC, abm.NZ):
+        assert np.array_equal(a.query(f)[oa], b.query(f)[ob]), f
+    if workload == "spheroid":
+        assert int(a.num_agents()[0]) > 800
+    else:
+        assert int(a.query(abm.STATIC).sum()) > 3000
+
+
+def test_nonfinite_device_input_fails_the_step(abm):
+    """Device-resident input with a NaN position: the host cannot check it at
+    creation, so the bounds kernel flags it on the device and the step
+    returns ABM_ERR_NONFINITE with the state left as it was."""
+    import torch
+    pos, diam = inputs.plain(512, 80.0, seed=4)
+    pos = pos.copy()
+    pos[100, 2] = np.inf
+    tp = torch.as_tensor(pos, device="cuda")
+    td = torch.as_tensor(diam, device="cuda")
+    b = abm.Population(H.gpu_params(abm), tp, td, capacity=512, box_capacity=1 << 14)
+    with pytest.raises(abm.AbmError) as e:
+        b.step(1)
+    assert e.value.code == abm.ERR_NONFINITE
+    assert int(b.num_agents()[0]) == 512
+    q = b.query(abm.POS)
+    assert np.isinf(q).sum() == 1
