@@ -1,10 +1,10 @@
 """GPU surrogate MLP (BF16 matrix-core kernels through the C ABI) against the FP64 oracle.
 
-Tolerances follow from the arithmetic: the GEMM operands are rounded to BF16
-(unit roundoff 2^-9) and accumulated in FP32, so each layer's output carries a
-relative error of a few 2^-9; over the four layers of the forward pass and the
-chained products of the backward pass this stays below 3e-2 (forward) and 5e-2
-(gradients) normwise, with the gradient direction kept (cosine >= 0.998).
+Tolerances: the GEMM operands are rounded to BF16 (unit roundoff 2^-9) and
+accumulated in FP32, so each layer's output carries a relative error of a few
+2^-9 that partly averages out over the 256-term sums.  The parity bar for the
+gradients is per tensor at most 2e-2 normwise relative with cosine at least
+0.999, and the forward pass at most 2e-2 normwise (measured: 2-6e-3).
 """
 import numpy as np
 import pytest
@@ -59,7 +59,7 @@ def test_forward_matches_oracle(abm, n):
     yo, _ = omlp.forward(theta, x.astype(np.float64))
     e = rel(yg, yo)
     print(f"batch {n}: forward normwise relative error {e:.3e}", flush=True)
-    assert e < 3e-2
+    assert e < 2e-2
 
 
 @pytest.mark.parametrize("n", [37, 256, 1024])
@@ -78,7 +78,8 @@ def test_gradients_match_oracle(abm, n):
         eW, eb = rel(gW, oW), rel(gb, ob)
         cW = cosine(gW.ravel(), oW.ravel())
         print(f"batch {n} layer {li}: dW rel {eW:.3e} cos {cW:.6f}, db rel {eb:.3e}", flush=True)
-        assert eW < 5e-2 and eb < 5e-2 and cW > 0.998
+        cb = cosine(gb, ob)
+        assert eW <= 2e-2 and eb <= 2e-2 and cW >= 0.999 and cb >= 0.999
     assert cosine(g, go) > 0.999
 
 

@@ -403,3 +403,27 @@ def test_mlp_gelu_and_adam_definitions():
     opt = mlp.Adam(np.zeros(3), lr=1e-3)
     th = opt.step(np.array([0.5, -2.0, 1e-3]))
     assert np.allclose(th, -1e-3 * np.sign([0.5, -2.0, 1e-3]), rtol=1e-4)
+
+
+def test_mlp_forward_on_a_network_computed_by_hand():
+    """A 2 -> 3 -> 2 -> 2 network whose value follows by hand.  Hidden
+    pre-activations sit at +-12 or beyond, where GELU(z) = z Phi(z) is z or 0
+    to below 1e-20, except one unit at exactly 2.5, where GELU(2.5) = 2.5
+    Phi(2.5) with Phi(2.5) = 0.99379033467422384 from the standard normal
+    table.  Rows of W are output units ([out, in] layout) and the output layer
+    is linear: the second output is -10, which a GELU there would turn into
+    about -7.6e-23.  A transposed W, a dropped bias or a GELU on the output
+    layer fails this pin."""
+    dims = (2, 3, 2, 2)
+    W1 = np.array([[4.0, 2.0], [-3.0, 1.0], [5.0, 0.0]]); b1 = np.array([6.0, -5.0, -7.5])
+    W2 = np.array([[1.0, 0.0, 0.0], [0.0, 7.0, 1.0]]); b2 = np.array([0.0, 10.0])
+    W3 = np.array([[0.5, 3.0], [-1.0, 0.0]]); b3 = np.array([-10.0, 2.0])
+    theta = mlp.flatten([(W1, b1), (W2, b2), (W3, b3)])
+    x = np.array([[2.0, -1.0]])
+    # z1 = (12, -12, 2.5) -> h1 = (12, 0, 2.5 Phi(2.5)); z2 = (12, 10 + h1[2]) -> h2 = z2;
+    # y = (0.5 * 12 + 3 * (10 + 2.5 Phi(2.5)) - 10, -12 + 2)
+    phi_2_5 = 0.99379033467422384
+    expect = np.array([[26.0 + 7.5 * phi_2_5, -10.0]])
+    y, _ = mlp.forward(theta, x, dims)
+    assert np.allclose(y, expect, rtol=1e-14, atol=1e-14)
+    assert mlp.n_params(dims) == theta.size == 6 + 3 + 6 + 2 + 4 + 2
