@@ -32,10 +32,10 @@ class SweepConfig:
     def state(self, s):
         return inputs.spheroid(int(self.n0[s]), seed=self.seed * 100003 + s, growth_scale=float(self.gscale[s]))
 
-    def params(self, s, resort_every=10):
+    def params(self, s, resort_every=10, record=False):
         return abm.params(box_len=0.0, div_vol=inputs.division_volume(float(self.d_div[s])),
                           adherence=float(self.adherence[s]), detect_static=True, resort_every=resort_every,
-                          seed=self.seed, sim_id=s)
+                          seed=self.seed, sim_id=s, record=record)
 
     def counts(self, s, vol, growth):
         """Agent count of simulation s at every iteration 0..iters.  Growth and
@@ -57,13 +57,14 @@ class SweepConfig:
         return int(1.1 * self.counts(s, vol, growth)[-1]) + 1024
 
 
-def build_batch(cfg, sims=None, resort_every=10):
-    """One Batch holding the given simulations (all by default)."""
+def build_batch(cfg, sims=None, resort_every=10, record=False):
+    """One Batch holding the given simulations (all by default); record=True
+    makes the kernels also write each agent's force and counts (ABM_RECORD)."""
     sims = list(range(cfg.n_sims)) if sims is None else list(sims)
     states = [cfg.state(s) for s in sims]
     caps = [cfg.capacity(s, st[2], st[3]) for s, st in zip(sims, states)]
     bcaps = [3 * c + 65536 for c in caps]
-    b = abm.Batch([cfg.params(s, resort_every) for s in sims], [st[0].shape[0] for st in states],
+    b = abm.Batch([cfg.params(s, resort_every, record) for s in sims], [st[0].shape[0] for st in states],
                   np.concatenate([st[0] for st in states]), np.concatenate([st[1] for st in states]),
                   vol=np.concatenate([st[2] for st in states]), growth=np.concatenate([st[3] for st in states]),
                   capacity=caps, box_capacity=bcaps)

@@ -57,3 +57,42 @@ def test_histograms_match_the_oracle_statistics(mods):
         assert np.allclose(c[s], oc, rtol=0, atol=1e-12)
         assert rg[s] == pytest.approx(org, rel=1e-13)
         assert np.allclose(h[s], oh, rtol=1e-6)
+
+
+def test_tuned_batch_extremes_match_the_oracle(mods):
+    """Simulations of the seed-4 sweep at its extremes -- division diameters
+    near 6 um (burst divisions at the start, about 70 agents per box), the
+    lowest and highest adherence, the fastest growth -- in one tuned batch in
+    the sweep's launch configuration (static skip, re-sort every 10).  At
+    iterations 0, 1, 2 (divisions), 10 (after a re-sort) and 30 every
+    simulation is stepped once by the oracle from its GPU state and compared
+    agent by agent: same agents, volumes and diameters bit for bit, contact
+    and non-zero-force counts exact, forces within 1e-5 of the sum of |F_N|,
+    move decisions, positions and static flags (Algorithm 2, Eq 4.1-4.2)."""
+    abm, sweep = mods
+    from tests import helpers as H
+    cfg = sweep.SweepConfig(256, seed=4, iters=31)
+    sims = [73, 24, 218, 201, 148, 143]  # d_div 6.04 / 6.08, adherence 0.904 / 2.689 / 2.695, growth scale 1.5
+    b, states, caps = sweep.build_batch(cfg, sims, record=True)
+    b.tune(2)
+    checks = {0, 1, 2, 10, 30}
+    for it in range(31):
+        if it not in checks:
+            b.step(1)
+            continue
+        snaps = [H.gpu_state(abm, b, k) for k in range(len(sims))]
+        b.step(1)
+        for k, s in enumerate(sims):
+            st = snaps[k]
+            op = H.oracle_params(box_len=0.0, div_vol=sweep.inputs.division_volume(float(cfg.d_div[s])),
+                                 adherence=float(cfg.adherence[s]), detect_static=True, seed=cfg.seed, sim_id=s)
+            nu = int(st["uid"].max()) + 1
+            o = H.oracle_from_state(st, op, cap=caps[k], next_uid=nu, iteration=it)
+            o.step(1)
+            ug = b.query(abm.UID, k)
+            og, oo = np.argsort(ug), np.argsort(o.uid[:o.n])
+            assert np.array_equal(ug[og], o.uid[:o.n][oo]), (s, it)
+            assert np.array_equal(b.query(abm.VOL, k)[og], o.vol[:o.n][oo]), (s, it)
+            assert np.array_equal(b.query(abm.DIAM, k)[og], o.diam[:o.n][oo]), (s, it)
+            res = H.compare_single_step(abm, b, o, sim=k, check_static=True, check_nbr=False)
+            print(f"sim {s} iteration {it}: {o.n} agents, {res}", flush=True)
