@@ -145,7 +145,7 @@ def bench_sweep(args):
     updates = float(counts[:, :cfg.iters].sum())
     log(f"[bench] sweep inputs and exact agent counts in {time.perf_counter() - t_gen:.1f} s; "
         f"{int(counts[:, 0].sum())} agents at the start, {int(counts[:, -1].sum())} at the end")
-    _, t_batch, n_end, grid = sweep.run_batched(cfg, record=False, tune=True, log=log)
+    _, t_batch, n_end, sched = sweep.run_batched(cfg, record=False, tune=True, log=log)
     assert np.array_equal(n_end, counts[:, -1].astype(np.int64)), "agent counts differ from the lineage count"
     if args.batched_only:
         t_single = float("nan")
@@ -162,7 +162,7 @@ def bench_sweep(args):
                                f"scale [0.5,1.5], division diameter [6,18] um, adherence [0.9,2.7]; initial counts "
                                f"log-uniform [1e3,5e4]; {cfg.iters} iterations",
                    "agents_start": int(counts[:, 0].sum()), "agents_end": int(counts[:, -1].sum()),
-                   "sweep_workgroups": grid},
+                   "schedule": sched},
         "batched_s": t_batch, "per_simulation_s": None if args.batched_only else t_single,
         "speedup_vs_per_simulation": None if args.batched_only else t_single / t_batch,
     }

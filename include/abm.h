@@ -172,13 +172,24 @@ int abm_batch_stats(abm_batch *b, double hist_rmax, double *centroid, double *r_
 /* Histograms only, to host or device memory (n_sims x 32 floats). */
 int abm_batch_hist(abm_batch *b, double hist_rmax, float *out, int out_on_device);
 
-/* Autotune the launch schedule (the number of persistent workgroups of the
- * force sweep, and the Morton re-sort period when simulation 0 sets
- * resort_every < 0) by timing n_trial_iters iterations per candidate from a
- * snapshot of the state; the batch is restored afterwards, so results are
- * unchanged.  This call allocates (and frees) one snapshot of the workspace.
- * Writes the chosen workgroup count to *grid_out (may be NULL). */
+/* Autotune the launch schedule of the batch by timing candidates from a
+ * snapshot of the state, one stage after the other: the persistent work
+ * groups of the unit sweep (512..4096), the work groups and waves per work
+ * group of the box-wise sweep (512..4096 x 2 or 4 waves), and, when some
+ * simulation sets resort_every < 0, the Morton re-sort period (5, 10 or 20
+ * iterations, each timed over 20 iterations so that its re-sorts count;
+ * Sec 5.4.2, Fig 5.14).  Stages 1-2 time n_trial_iters iterations per
+ * candidate.  The batch is restored afterwards, so results are unchanged.
+ * This call allocates (and frees) one snapshot of the workspace.  Writes the
+ * chosen sweep work-group count to *grid_out (may be NULL); the whole
+ * schedule is read with abm_batch_schedule.  (The sweep's work unit, an
+ * aligned 4x4x4 block of boxes, is fixed: the box-slot layout is built on it.) */
 int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out);
+
+/* The launch schedule in use: unit-sweep work groups, box-wise work groups
+ * and waves per work group, Morton re-sort period (0 = never).  Any pointer
+ * may be NULL. */
+int abm_batch_schedule(abm_batch *b, int *sweep_grid, int *dense_grid, int *dense_waves, int *resort_every);
 
 /* Set the number of persistent workgroups of the force sweep (a multiple of
  * 8, one share per XCD; default 2048). */

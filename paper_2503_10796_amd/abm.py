@@ -63,6 +63,7 @@ def lib():
         L.abm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Params), _i64p, _vp, _vp, _vp, _vp, _vp,
                                        ctypes.c_int, _i64p, _i64p, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
         L.abm_batch_restore.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int]
+        L.abm_batch_schedule.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int)] * 4
         L.abm_batch_step.argtypes = [_vp, ctypes.c_int]
         L.abm_batch_num_agents.argtypes = [_vp, _i64p]
         L.abm_batch_fp64_agents.argtypes = [_vp, _i64p]
@@ -236,6 +237,13 @@ class Batch:
         b = ctypes.c_int(0)
         check(lib().abm_batch_tune(self.h, int(n_trial_iters), ctypes.byref(b)))
         return b.value
+
+    def schedule(self):
+        """The launch schedule in use: dict of sweep_grid, dense_grid,
+        dense_waves, resort_every."""
+        v = [ctypes.c_int(0) for _ in range(4)]
+        check(lib().abm_batch_schedule(self.h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("sweep_grid", "dense_grid", "dense_waves", "resort_every"), (x.value for x in v)))
 
     def set_sweep_grid(self, workgroups):
         check(lib().abm_batch_set_sweep_grid(self.h, int(workgroups)))

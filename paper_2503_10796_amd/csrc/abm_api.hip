@@ -213,7 +213,7 @@ struct abm_batch {
     hipStream_t cap_stream = nullptr;  // private stream used only to capture the graph
     std::vector<SimDesc> host_sims;
     int64_t A = 0, T = 0, BT = 0;
-    int sweep_grid = 2048;  // persistent workgroups of the force sweep (multiple of 8)
+    Sched sched;            // launch schedule of the force sweep (autotuned)
     int grid_agents = 2048, grid_boxes = 2048;
     bool any_growth = false, any_static = false;
     int resort_every = 0;
@@ -245,10 +245,10 @@ static int capture(abm_batch *b, int part, int diag) {
     b->d.resort_every = b->resort_every;
     bool resort = b->resort_every > 0;
     if (part == 0)
-        launch_iteration(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, b->sweep_grid, diag != 0, b->any_growth,
+        launch_iteration(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, b->sched, diag != 0, b->any_growth,
                          b->any_static, resort);
     else if (part == 1)
-        launch_sweep(b->d, b->cap_stream, b->sweep_grid, diag != 0, b->any_static);
+        launch_sweep(b->d, b->cap_stream, b->sched, diag != 0, b->any_static);
     else
         launch_after_sweep(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, diag != 0, b->any_growth, b->any_static,
                            resort);
@@ -788,18 +788,41 @@ extern "C" int abm_batch_set_sweep_grid(abm_batch *b, int workgroups) {
     g_err.clear();
     if (!b || workgroups < 8 || workgroups > 65536 || workgroups % 8)
         return fail(ABM_ERR_ARG, "workgroups must be a multiple of 8 in [8, 65536]");
-    if (workgroups != b->sweep_grid) {
-        b->sweep_grid = workgroups;
+    if (workgroups != b->sched.sweep_grid) {
+        b->sched.sweep_grid = workgroups;
         destroy_graphs(b);
     }
+    return ABM_OK;
+}
+
+// One trial of the tuner: from the snapshot, the current schedule replays
+// one warm-up iteration and then `iters` timed iterations.  Returns the
+// milliseconds, or a negative value when the trial aborted (a capacity error:
+// the schedule is then not taken).
+static int tune_trial(abm_batch *b, void *snap, size_t bytes, int iters, hipEvent_t e0, hipEvent_t e1, float *ms) {
+    hipStream_t st = b->stream;
+    destroy_graphs(b);
+    int rc = capture(b, 0, 0);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(b->ws, snap, bytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipGraphLaunch(b->exec[0][0], st));  // warm-up
+    HIPCHK(hipEventRecord(e0, st));
+    for (int it = 0; it < iters; ++it) HIPCHK(hipGraphLaunch(b->exec[0][0], st));
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(ms, e0, e1));
+    Ctl c;
+    rc = read_ctl(b, c);
+    if (rc) return rc;
+    if (c.abort) *ms = -1.0f;
     return ABM_OK;
 }
 
 extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out) {
     g_err.clear();
     if (!b || n_trial_iters < 1) return fail(ABM_ERR_ARG, "bad arguments");
-    int rc0 = ensure_grid(b);  // the trials replay iterations, which need the grid
-    if (rc0) return rc0;
+    int rc = ensure_grid(b);  // the trials replay iterations, which need the grid
+    if (rc) return rc;
     // snapshot of the whole workspace so that trials leave the batch unchanged
     void *snap = nullptr;
     size_t bytes = b->L.total - 256;
@@ -810,47 +833,48 @@ extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out) {
         (void)hipFree(snap);
         return fail(ABM_ERR_HIP, "snapshot copy failed: %s", hipGetErrorString(e));
     }
-    const int grids[4] = {512, 1024, 2048, 4096};
-    const int resorts[4] = {0, 5, 10, 20};
     bool tune_resort = false;
     for (auto &S : b->host_sims) tune_resort |= S.resort_every < 0;
-    int best_grid = b->sweep_grid, best_resort = b->resort_every;
-    float best = 1e30f;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    int rc = ABM_OK;
     if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
         rc = fail(ABM_ERR_HIP, "event creation failed: %s", hipGetErrorString(e));
-    // the first failing call of a trial ends the tuning (the batch is restored below)
-#define TUNECHK(expr)                                                                             \
-    if ((e = (expr)) != hipSuccess) {                                                             \
-        rc = fail(ABM_ERR_HIP, "autotuner: %s: %s", #expr, hipGetErrorString(e));                \
-        break;                                                                                    \
+    Sched best = b->sched;
+    int best_resort = b->resort_every;
+    // stage 1: persistent work groups of the unit sweep
+    float best_ms = 1e30f;
+    const int grids[4] = {512, 1024, 2048, 4096};
+    for (int k = 0; k < 4 && rc == ABM_OK; ++k) {
+        b->sched = best;
+        b->sched.sweep_grid = grids[k];
+        float ms;
+        if ((rc = tune_trial(b, snap, bytes, n_trial_iters, e0, e1, &ms))) break;
+        if (ms >= 0.0f && ms < best_ms) best_ms = ms, best.sweep_grid = grids[k];
     }
-    for (int bi = 0; bi < 4 && rc == ABM_OK; ++bi) {
-        for (int ri = 0; ri < (tune_resort ? 4 : 1) && rc == ABM_OK; ++ri) {
-            b->sweep_grid = grids[bi];
-            if (tune_resort) b->resort_every = resorts[ri];
-            destroy_graphs(b);
-            if ((rc = capture(b, 0, 0))) break;
-            TUNECHK(hipMemcpyAsync(b->ws, snap, bytes, hipMemcpyDeviceToDevice, st));
-            TUNECHK(hipGraphLaunch(b->exec[0][0], st));  // warm-up
-            TUNECHK(hipEventRecord(e0, st));
-            for (int it = 0; it < n_trial_iters && e == hipSuccess; ++it) e = hipGraphLaunch(b->exec[0][0], st);
-            TUNECHK(e);
-            TUNECHK(hipEventRecord(e1, st));
-            TUNECHK(hipEventSynchronize(e1));
-            float ms = 0.0f;
-            TUNECHK(hipEventElapsedTime(&ms, e0, e1));
-            Ctl c;
-            if ((rc = read_ctl(b, c))) break;
-            if (!c.abort && ms < best) {
-                best = ms;
-                best_grid = grids[bi];
-                best_resort = b->resort_every;
-            }
+    // stage 2: work groups and waves per work group of the box-wise sweep
+    const int dense[6][2] = {{512, 4}, {1024, 4}, {2048, 4}, {1024, 2}, {2048, 2}, {4096, 2}};
+    best_ms = 1e30f;
+    Sched base = best;
+    for (int k = 0; k < 6 && rc == ABM_OK; ++k) {
+        b->sched = base;
+        b->sched.dense_grid = dense[k][0];
+        b->sched.dense_waves = dense[k][1];
+        float ms;
+        if ((rc = tune_trial(b, snap, bytes, n_trial_iters, e0, e1, &ms))) break;
+        if (ms >= 0.0f && ms < best_ms) best_ms = ms, best.dense_grid = dense[k][0], best.dense_waves = dense[k][1];
+    }
+    // stage 3 (on request): the Morton re-sort period, each candidate timed
+    // over 20 iterations so that its re-sorts are part of the time
+    if (tune_resort) {
+        const int resorts[3] = {5, 10, 20};
+        best_ms = 1e30f;
+        b->sched = best;
+        for (int k = 0; k < 3 && rc == ABM_OK; ++k) {
+            b->resort_every = resorts[k];
+            float ms;
+            if ((rc = tune_trial(b, snap, bytes, n_trial_iters > 20 ? n_trial_iters : 20, e0, e1, &ms))) break;
+            if (ms >= 0.0f && ms < best_ms) best_ms = ms, best_resort = resorts[k];
         }
     }
-#undef TUNECHK
     // restore the batch as it was before the trials
     if ((e = hipMemcpyAsync(b->ws, snap, bytes, hipMemcpyDeviceToDevice, st)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
@@ -859,11 +883,21 @@ extern "C" int abm_batch_tune(abm_batch *b, int n_trial_iters, int *grid_out) {
     (void)hipFree(snap);  // teardown: nothing to recover
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (rc) return rc;
-    b->sweep_grid = best_grid;
+    b->sched = best;
     b->resort_every = best_resort;
     destroy_graphs(b);
-    if (grid_out) *grid_out = best_grid;
+    if (rc) return rc;
+    if (grid_out) *grid_out = best.sweep_grid;
+    return ABM_OK;
+}
+
+extern "C" int abm_batch_schedule(abm_batch *b, int *sweep_grid, int *dense_grid, int *dense_waves, int *resort_every) {
+    g_err.clear();
+    if (!b) return fail(ABM_ERR_ARG, "null handle");
+    if (sweep_grid) *sweep_grid = b->sched.sweep_grid;
+    if (dense_grid) *dense_grid = b->sched.dense_grid;
+    if (dense_waves) *dense_waves = b->sched.dense_waves;
+    if (resort_every) *resort_every = b->resort_every;
     return ABM_OK;
 }
 

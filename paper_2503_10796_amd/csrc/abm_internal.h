@@ -182,11 +182,20 @@ __device__ inline float fix_radius(double dm, double L) { return (float)ldexp(0.
 void clear_error();
 int set_error(int code, const char *msg);
 
+// Launch schedule of the force sweep (picked by the autotuner): persistent
+// work groups of the unit sweep, and work groups and waves per work group of
+// the box-wise sweep (multiples of 8 work groups: one share per XCD).
+struct Sched {
+    int sweep_grid = 2048;
+    int dense_grid = 1024;
+    int dense_waves = 4;  // 2 or 4
+};
+
 // Host-side launch helpers implemented in the .hip files.
-void launch_iteration(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, int sweep_grid, bool diag,
+void launch_iteration(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, const Sched &sc, bool diag,
                       bool any_growth, bool any_static, bool resort);
 void launch_grid_build(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool any_static);
-void launch_sweep(const Dev &d, hipStream_t s, int sweep_grid, bool diag, bool any_static);
+void launch_sweep(const Dev &d, hipStream_t s, const Sched &sc, bool diag, bool any_static);
 void launch_after_sweep(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool diag, bool any_growth,
                         bool any_static, bool resort);
 void launch_resort(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool force, bool any_static);

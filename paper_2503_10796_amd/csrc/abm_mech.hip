@@ -1196,18 +1196,20 @@ __global__ void __launch_bounds__(256, 4)  // 4 blocks per CU: at most 128 VGPRs
 // of the densest boxes spread over several waves.
 // (sims, wblk, blist: read-only and not aliased, so that their wave-uniform
 // reads are scalar loads)
-__global__ void __launch_bounds__(256)
+// NW waves per work group (a schedule parameter: the waves are independent).
+template <int NW>
+__global__ void __launch_bounds__(64 * NW)
     k_sweep_dense(Dev d, const SimDesc *__restrict__ sims, const int64_t *__restrict__ wblk,
                   const uint32_t *__restrict__ blist) {
     if (ABM_ABORTED(d)) return;
     const unsigned long long nq = d.ctl->n_dense;
     if (nq == 0) return;
-    __shared__ DenseWave W[4];
+    __shared__ DenseWave W[NW];
     const int P = d.ctl->pos_par, lp = d.ctl->lay_par;
     const uint32_t w = threadIdx.x >> 6;
     const unsigned long long n = nq < (unsigned long long)d.dense_cap ? nq : (unsigned long long)d.dense_cap;
-    const unsigned long long nw = 4ull * gridDim.x;  // (gridDim.x: a multiple of 8)
-    const unsigned long long gw = 4ull * ((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3)) + w;
+    const unsigned long long nw = (unsigned long long)NW * gridDim.x;  // (gridDim.x: a multiple of 8)
+    const unsigned long long gw = (unsigned long long)NW * ((blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3)) + w;
     for (unsigned long long q = gw; q < n; q += nw) {
         const uint64_t e = d.dense_list[q];
         const int64_t u = (int64_t)(e >> 9);
@@ -1704,18 +1706,22 @@ __global__ void __launch_bounds__(256) k_static(Dev d, const SimDesc *__restrict
 }
 
 // ------------------------------------------------------------------ launchers
-void launch_sweep(const Dev &d, hipStream_t st, int sweep_grid, bool diag, bool any_static) {
+void launch_sweep(const Dev &d, hipStream_t st, const Sched &sc, bool diag, bool any_static) {
     const SimDesc *sims = d.sims;
     if (diag) {
-        hipLaunchKernelGGL(k_sweep<true>, dim3(sweep_grid), dim3(256), 0, st, d, sims, d.wblk_begin, d.blist,
+        hipLaunchKernelGGL(k_sweep<true>, dim3(sc.sweep_grid), dim3(256), 0, st, d, sims, d.wblk_begin, d.blist,
                            d.active_blk, 0);
     } else {
-        hipLaunchKernelGGL(k_sweep<false>, dim3(sweep_grid), dim3(256), 0, st, d, sims, d.wblk_begin, d.blist,
+        hipLaunchKernelGGL(k_sweep<false>, dim3(sc.sweep_grid), dim3(256), 0, st, d, sims, d.wblk_begin, d.blist,
                            d.active_blk, any_static ? 1 : 0);
         // the units queued for the box-wise path (the kernel returns at once
         // when there are none)
-        hipLaunchKernelGGL(k_sweep_dense, dim3(1024), dim3(256), 0, st, d, sims, (const int64_t *)d.wblk_begin,
-                           (const uint32_t *)d.blist);
+        if (sc.dense_waves == 2)
+            hipLaunchKernelGGL(k_sweep_dense<2>, dim3(sc.dense_grid), dim3(128), 0, st, d, sims,
+                               (const int64_t *)d.wblk_begin, (const uint32_t *)d.blist);
+        else
+            hipLaunchKernelGGL(k_sweep_dense<4>, dim3(sc.dense_grid), dim3(256), 0, st, d, sims,
+                               (const int64_t *)d.wblk_begin, (const uint32_t *)d.blist);
     }
 }
 
@@ -1747,9 +1753,9 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
 }
 
 // One iteration on the grid built at the end of the previous one.
-void launch_iteration(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, int sweep_grid, bool diag,
+void launch_iteration(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, const Sched &sc, bool diag,
                       bool any_growth, bool any_static, bool resort) {
-    launch_sweep(d, st, sweep_grid, diag, any_static);
+    launch_sweep(d, st, sc, diag, any_static);
     launch_after_sweep(d, st, grid_agents, grid_boxes, diag, any_growth, any_static, resort);
 }
 

@@ -75,12 +75,16 @@ def run_batched(cfg, record=True, tune=True, log=None, sims=None, iters=None):
     """Runs the sweep (or the listed simulations) batched for `iters`
     iterations (cfg.iters by default); returns (histograms [iters+1, n, 32] or
     None, seconds for the iterations, agents per simulation at the end,
-    chosen workgroups)."""
+    launch schedule).  With tune=True the autotuner picks the schedule,
+    including the Morton re-sort period; else the re-sort runs every 10
+    iterations."""
     import torch
     iters = cfg.iters if iters is None else iters
     sims = list(range(cfg.n_sims)) if sims is None else list(sims)
-    b, _, _ = build_batch(cfg, sims)
-    grid = b.tune(3) if tune else None
+    b, _, _ = build_batch(cfg, sims, resort_every=-1 if tune else 10)
+    if tune:
+        b.tune(3)
+    grid = b.schedule()
     torch.cuda.synchronize()
     hist = torch.zeros((iters + 1, len(sims), 32), dtype=torch.float32, device="cuda") if record else None
     if record:
@@ -97,7 +101,7 @@ def run_batched(cfg, record=True, tune=True, log=None, sims=None, iters=None):
     n_end = b.num_agents()
     if log:
         log(f"[sweep] {len(sims)} simulations x {iters} its batched in {dt:.3f} s, "
-            f"{int(n_end.sum())} agents at the end, sweep workgroups {grid}")
+            f"{int(n_end.sum())} agents at the end, schedule {grid}")
     out = hist.cpu().numpy() if record else None
     b.close()
     return out, dt, n_end, grid

@@ -96,3 +96,26 @@ def test_tuned_batch_extremes_match_the_oracle(mods):
             assert np.array_equal(b.query(abm.DIAM, k)[og], o.diam[:o.n][oo]), (s, it)
             res = H.compare_single_step(abm, b, o, sim=k, check_static=True, check_nbr=False)
             print(f"sim {s} iteration {it}: {o.n} agents, {res}", flush=True)
+
+
+def test_tuner_picks_every_schedule_parameter(mods):
+    """The tuner picks the unit-sweep work groups, the box-wise work groups
+    and waves per work group, and (when asked with a negative period) the
+    re-sort period from its candidate sets, and leaves the state unchanged."""
+    abm, sweep = mods
+    cfg = sweep.SweepConfig(256, seed=4, iters=12)
+    sims = [73, 24, 5, 6, 7, 8]
+    b, _, _ = sweep.build_batch(cfg, sims, resort_every=-1)
+    ref, _, _ = sweep.build_batch(cfg, sims, resort_every=10)
+    b.tune(2)
+    sc = b.schedule()
+    print(sc, flush=True)
+    assert sc["sweep_grid"] in (512, 1024, 2048, 4096)
+    assert (sc["dense_grid"], sc["dense_waves"]) in ((512, 4), (1024, 4), (2048, 4), (1024, 2), (2048, 2), (4096, 2))
+    assert sc["resort_every"] in (5, 10, 20)
+    b.step(cfg.iters)
+    ref.step(cfg.iters)
+    for k in range(len(sims)):
+        ub, ur = b.query(abm.UID, k), ref.query(abm.UID, k)
+        assert np.array_equal(np.sort(ub), np.sort(ur))
+        assert np.array_equal(b.query(abm.POS, k)[np.argsort(ub)], ref.query(abm.POS, k)[np.argsort(ur)])
