@@ -21,7 +21,12 @@
  *   - force threshold that must be exceeded to move the agent and the
  *     four static-agent conditions                                 (Sec 5.5)
  *   - maximum displacement parameter and the cell mass        (Tutorial E.15)
- *   - grow-or-divide cell rule                                   (Algorithm 2)
+ *   - cell behaviour: Brownian step, apoptosis after a minimum age
+ *     with a death probability, grow or divide with a division
+ *     probability                                  (Algorithm 2, Table 4.2)
+ *   - removals take effect at the start of the next iteration     (Sec 5.2.1)
+ *   - removals do not end the static state of neighbours, which
+ *     condition (iv) makes safe                                    (Sec 5.5)
  *   - Morton order with x in the lowest bit                  (Sec 5.4.2, Fig 5.4)
  *   - counter-based generator for per-agent randomness            (Sec 7.1.4)
  * Readings where the thesis is silent (force direction, radii, threshold
@@ -53,6 +58,13 @@ typedef struct {
     uint64_t seed;
     uint32_t sim_id;
     uint32_t pad;
+    /* Algorithm 2 cell behaviour (Table 4.2): Brownian step length per
+       iteration (0: off), death probability per iteration for cells of at
+       least min_age iterations (0: off), division probability per iteration
+       once the division volume is reached (1: always) */
+    double brownian_rate, death_prob, division_prob;
+    int32_t min_age;
+    int32_t pad2;
 } orc_params;
 
 typedef struct {
@@ -73,6 +85,8 @@ typedef struct {
     uint8_t *moved, *grew, *divided, *is_new;
     double grid_lo[3], grid_hi[3], grid_L;
     int64_t grid_dims[3];
+    int32_t *age;      /* iterations since the cell was created (Algorithm 2) */
+    int64_t n_removed; /* agents the last step removed */
 } orc_state;
 
 /* ------------------------------------------------------------------------ */
@@ -142,6 +156,54 @@ void orc_direction(uint64_t seed, uint32_t sim_id, uint64_t uid, uint64_t iter, 
     u[0] = rho * cos(phi);
     u[1] = rho * sin(phi);
     u[2] = zc;
+}
+
+/* Per-agent random words of Algorithm 2: Philox4x32-10 with counter (uid
+ * low, uid high, iteration, simulation) and key (seed low XOR tag, seed
+ * high), one tag per purpose, so that every draw is a pure function of the
+ * agent and the iteration.  A word w gives the uniform (w + 1/2) 2^-32 in
+ * the open interval (0, 1) (exact in double). */
+#define ORC_TAG_BROWNIAN 0x42524f57u
+#define ORC_TAG_DEATH 0x44454154u
+#define ORC_TAG_DIVISION 0x44495650u
+
+void orc_draw(uint64_t seed, uint32_t tag, uint32_t sim_id, uint64_t uid, uint64_t iter, uint32_t out[4])
+{
+    uint32_t ctr[4] = {(uint32_t)uid, (uint32_t)(uid >> 32), (uint32_t)iter, sim_id};
+    uint32_t key[2] = {(uint32_t)seed ^ tag, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+static double uniform_open(uint32_t w) { return ((double)w + 0.5) * 0x1.0p-32; }
+
+/* Algorithm 2, lines 1-3: a vector of three uniforms in (-1, 1), divided by
+ * its Euclidean norm, times the displacement rate.  (The normalised cube
+ * vector is what the algorithm computes; it is not uniform on the sphere.) */
+void orc_brownian(uint64_t seed, uint32_t sim_id, uint64_t uid, uint64_t iter, double rate, double d[3])
+{
+    uint32_t o[4];
+    orc_draw(seed, ORC_TAG_BROWNIAN, sim_id, uid, iter, o);
+    double v[3];
+    for (int a = 0; a < 3; ++a) v[a] = 2.0 * uniform_open(o[a]) - 1.0;
+    double norm = sqrt(fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0])));
+    for (int a = 0; a < 3; ++a) d[a] = (v[a] / norm) * rate;
+}
+
+/* Algorithm 2, line 4: removal of a cell of at least min_age iterations. */
+int orc_dies(const orc_params *p, uint64_t uid, uint64_t iter, int32_t age)
+{
+    if (!(p->death_prob > 0.0) || age < p->min_age) return 0;
+    uint32_t o[4];
+    orc_draw(p->seed, ORC_TAG_DEATH, p->sim_id, uid, iter, o);
+    return uniform_open(o[0]) < p->death_prob;
+}
+
+/* Algorithm 2, line 11: the division draw of a cell at the division size. */
+int orc_divides(const orc_params *p, uint64_t uid, uint64_t iter)
+{
+    uint32_t o[4];
+    orc_draw(p->seed, ORC_TAG_DIVISION, p->sim_id, uid, iter, o);
+    return uniform_open(o[0]) < p->division_prob;
 }
 
 /* Diameter of a sphere of volume V: the double nearest to cbrt(6V/pi), with
@@ -395,14 +457,30 @@ static double box_length(const orc_state *s, const orc_params *p)
 int orc_step(orc_state *s, const orc_params *p)
 {
     const int64_t n = s->n;
+    s->n_removed = 0;
     if (n <= 0) { s->iter += 1; return 0; }
+    /* with Brownian motion every cell moves every iteration: no cell can be
+       static, and the combination is refused */
+    if (p->detect_static && p->brownian_rate > 0.0) return -3;
 
-    /* growth/division decision first, so that a capacity overflow leaves the
-       state untouched */
-    int64_t ndiv = 0;
-    if (p->div_vol > 0.0)
-        for (int64_t i = 0; i < n; ++i) if (s->vol[i] >= p->div_vol) ndiv += 1;
-    if (n + ndiv > s->cap) return -2;
+    /* the decisions of Algorithm 2 from the start-of-iteration state, first,
+       so that a capacity overflow leaves the state untouched: removal
+       (line 4), then, for the cells that stay, division (lines 9-12: grow
+       below the division volume, else divide with the division
+       probability) */
+    uint8_t *dies = (uint8_t *)calloc((size_t)n, 1);
+    uint8_t *divs = (uint8_t *)calloc((size_t)n, 1);
+    if (!dies || !divs) { free(dies); free(divs); return -1; }
+    int64_t ndiv = 0, ndead = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        dies[i] = (uint8_t)orc_dies(p, s->uid[i], (uint64_t)s->iter, s->age[i]);
+        ndead += dies[i];
+        if (!dies[i] && p->div_vol > 0.0 && s->vol[i] >= p->div_vol && orc_divides(p, s->uid[i], (uint64_t)s->iter)) {
+            divs[i] = 1;
+            ndiv += 1;
+        }
+    }
+    if (n + ndiv > s->cap) { free(dies); free(divs); return -2; }
 
     orc_grid g;
     memset(&g, 0, sizeof g);
@@ -414,7 +492,7 @@ int orc_step(orc_state *s, const orc_params *p)
     double *nx = (double *)malloc(sizeof(double) * (size_t)n);
     double *ny = (double *)malloc(sizeof(double) * (size_t)n);
     double *nzp = (double *)malloc(sizeof(double) * (size_t)n);
-    if (!nx || !ny || !nzp) { free(nx); free(ny); free(nzp); grid_free(&g); return -1; }
+    if (!nx || !ny || !nzp) { free(nx); free(ny); free(nzp); grid_free(&g); free(dies); free(divs); return -1; }
 
     int failed = 0;
     /* mechanics: every agent reads only the start-of-iteration state */
@@ -448,23 +526,27 @@ int orc_step(orc_state *s, const orc_params *p)
                 orc_displacement(fo.f, p->adherence, p->dt, p->mass, p->max_disp, d);
             }
             s->dx[i] = d[0]; s->dy[i] = d[1]; s->dz[i] = d[2];
-            nx[i] = s->x[i] + d[0];
-            ny[i] = s->y[i] + d[1];
-            nzp[i] = s->z[i] + d[2];
-            s->moved[i] = (d[0] != 0.0 || d[1] != 0.0 || d[2] != 0.0);
+            /* Algorithm 2, lines 1-3: the Brownian step, then the mechanical
+               displacement: x' = (x + b) + d */
+            double b[3] = {0.0, 0.0, 0.0};
+            if (p->brownian_rate > 0.0) orc_brownian(p->seed, p->sim_id, s->uid[i], (uint64_t)s->iter, p->brownian_rate, b);
+            nx[i] = (s->x[i] + b[0]) + d[0];
+            ny[i] = (s->y[i] + b[1]) + d[1];
+            nzp[i] = (s->z[i] + b[2]) + d[2];
+            s->moved[i] = (nx[i] != s->x[i] || ny[i] != s->y[i] || nzp[i] != s->z[i]);
             s->grew[i] = 0;
             s->divided[i] = 0;
             s->is_new[i] = 0;
         }
         free(nb.idx);
     }
-    if (failed) { free(nx); free(ny); free(nzp); grid_free(&g); return -1; }
+    if (failed) { free(nx); free(ny); free(nzp); grid_free(&g); free(dies); free(divs); return -1; }
 
     /* start-of-iteration positions are kept for the static rule */
     double *sx = (double *)malloc(sizeof(double) * (size_t)n);
     double *sy = (double *)malloc(sizeof(double) * (size_t)n);
     double *sz = (double *)malloc(sizeof(double) * (size_t)n);
-    if (!sx || !sy || !sz) { free(sx); free(sy); free(sz); free(nx); free(ny); free(nzp); grid_free(&g); return -1; }
+    if (!sx || !sy || !sz) { free(sx); free(sy); free(sz); free(nx); free(ny); free(nzp); grid_free(&g); free(dies); free(divs); return -1; }
     memcpy(sx, s->x, sizeof(double) * (size_t)n);
     memcpy(sy, s->y, sizeof(double) * (size_t)n);
     memcpy(sz, s->z, sizeof(double) * (size_t)n);
@@ -474,22 +556,29 @@ int orc_step(orc_state *s, const orc_params *p)
     memcpy(s->z, nzp, sizeof(double) * (size_t)n);
     free(nx); free(ny); free(nzp);
 
+    /* Algorithm 2, line 8: the cells that stay age by one iteration */
+    for (int64_t i = 0; i < n; ++i)
+        if (!dies[i]) s->age[i] += 1;
+
     /* growth or division (Algorithm 2, grow branch and divide branch), from
        the start-of-iteration volume, applied to the committed position.
        Daughter uids: next_uid + rank of the mother's uid among this
-       iteration's dividers. */
+       iteration's dividers; a daughter starts at age 0 and the mother keeps
+       her age.  A cell at the division volume whose division draw fails
+       neither grows nor divides. */
     int64_t m = n;
     if (p->div_vol > 0.0) {
         int64_t *dividers = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ndiv > 0 ? ndiv : 1));
-        if (!dividers) { free(sx); free(sy); free(sz); grid_free(&g); return -1; }
+        if (!dividers) { free(sx); free(sy); free(sz); grid_free(&g); free(dies); free(divs); return -1; }
         int64_t q = 0;
         for (int64_t i = 0; i < n; ++i) {
-            if (s->vol[i] >= p->div_vol) {
-                dividers[q++] = i;
-            } else {
+            if (dies[i]) continue;
+            if (s->vol[i] < p->div_vol) {
                 s->vol[i] = s->vol[i] + s->growth[i];
                 s->diam[i] = orc_diameter_from_volume(s->vol[i]);
                 s->grew[i] = 1;
+            } else if (divs[i]) {
+                dividers[q++] = i;
             }
         }
         g_sort_uid = s->uid;
@@ -523,6 +612,7 @@ int orc_step(orc_state *s, const orc_params *p)
             s->grew[j] = 0;
             s->divided[j] = 0;
             s->is_new[j] = 1;
+            s->age[j] = 0;
         }
         free(dividers);
         m = n + ndiv;
@@ -533,6 +623,11 @@ int orc_step(orc_state *s, const orc_params *p)
        at most one non-zero neighbour force, and no changed agent within the
        interaction radius L at its start or its committed position.  A
        changed agent moved, grew, divided or is new. */
+    /* a removed cell is no change for its neighbours (Sec 5.5: condition
+       (iv) lets cells be removed without ending the static state around
+       them) */
+    for (int64_t i = 0; i < n; ++i)
+        if (dies[i]) s->moved[i] = s->grew[i] = s->divided[i] = 0;
     if (p->detect_static) {
         int64_t nchg = 0;
         for (int64_t j = 0; j < m; ++j)
@@ -542,7 +637,7 @@ int orc_step(orc_state *s, const orc_params *p)
         double *py = (double *)malloc(sizeof(double) * (size_t)cap2);
         double *pz = (double *)malloc(sizeof(double) * (size_t)cap2);
         int64_t *owner = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap2);
-        if (!px || !py || !pz || !owner) { free(px); free(py); free(pz); free(owner); free(sx); free(sy); free(sz); grid_free(&g); return -1; }
+        if (!px || !py || !pz || !owner) { free(px); free(py); free(pz); free(owner); free(sx); free(sy); free(sz); grid_free(&g); free(dies); free(divs); return -1; }
         int64_t np = 0;
         for (int64_t j = 0; j < m; ++j) {
             if (!(s->moved[j] || s->grew[j] || s->divided[j] || s->is_new[j])) continue;
@@ -556,7 +651,7 @@ int orc_step(orc_state *s, const orc_params *p)
         cg.L = g.L;
         memcpy(cg.dims, g.dims, sizeof g.dims);
         cg.nboxes = g.nboxes;
-        if (grid_bin(&cg, np, px, py, pz)) { grid_free(&cg); free(px); free(py); free(pz); free(owner); free(sx); free(sy); free(sz); grid_free(&g); return -1; }
+        if (grid_bin(&cg, np, px, py, pz)) { grid_free(&cg); free(px); free(py); free(pz); free(owner); free(sx); free(sy); free(sz); grid_free(&g); free(dies); free(divs); return -1; }
         const double L2 = g.L * g.L;
         for (int64_t i = 0; i < m; ++i) {
             int st = !(s->moved[i] || s->grew[i] || s->divided[i] || s->is_new[i]) && s->nz[i] <= 1;
@@ -588,9 +683,35 @@ int orc_step(orc_state *s, const orc_params *p)
         for (int64_t i = 0; i < m; ++i) s->is_static[i] = 0;
     }
 
+    /* removals (Algorithm 2, line 5) take effect for the next iteration: the
+       cells that stay keep their order (daughters, never removed in the
+       iteration that creates them, follow) */
+    if (ndead > 0) {
+        int64_t w = 0;
+        for (int64_t i = 0; i < m; ++i) {
+            if (i < n && dies[i]) continue;
+            if (w != i) {
+                s->x[w] = s->x[i]; s->y[w] = s->y[i]; s->z[w] = s->z[i];
+                s->diam[w] = s->diam[i]; s->vol[w] = s->vol[i]; s->growth[w] = s->growth[i];
+                s->uid[w] = s->uid[i]; s->is_static[w] = s->is_static[i]; s->nz[w] = s->nz[i];
+                s->age[w] = s->age[i];
+                s->nbr[w] = s->nbr[i]; s->contacts[w] = s->contacts[i];
+                s->fx[w] = s->fx[i]; s->fy[w] = s->fy[i]; s->fz[w] = s->fz[i];
+                s->dx[w] = s->dx[i]; s->dy[w] = s->dy[i]; s->dz[w] = s->dz[i];
+                s->box[w] = s->box[i];
+                s->sum_abs_fn[w] = s->sum_abs_fn[i]; s->sum_dfn[w] = s->sum_dfn[i]; s->sum_fn_d[w] = s->sum_fn_d[i];
+                s->moved[w] = s->moved[i]; s->grew[w] = s->grew[i]; s->divided[w] = s->divided[i];
+                s->is_new[w] = s->is_new[i];
+            }
+            ++w;
+        }
+        m = w;
+    }
+    free(dies); free(divs);
     free(sx); free(sy); free(sz);
     grid_free(&g);
     s->n = m;
+    s->n_removed = ndead;
     s->iter += 1;
     return 0;
 }

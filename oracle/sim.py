@@ -28,6 +28,8 @@ class OrcParams(ctypes.Structure):
         ("box_len", ctypes.c_double), ("div_vol", ctypes.c_double), ("shift_frac", ctypes.c_double),
         ("detect_static", ctypes.c_int32), ("brute_force", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("sim_id", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+        ("brownian_rate", ctypes.c_double), ("death_prob", ctypes.c_double), ("division_prob", ctypes.c_double),
+        ("min_age", ctypes.c_int32), ("pad2", ctypes.c_int32),
     ]
 
 
@@ -42,6 +44,7 @@ class OrcState(ctypes.Structure):
         ("moved", _u8p), ("grew", _u8p), ("divided", _u8p), ("is_new", _u8p),
         ("grid_lo", ctypes.c_double * 3), ("grid_hi", ctypes.c_double * 3), ("grid_L", ctypes.c_double),
         ("grid_dims", ctypes.c_int64 * 3),
+        ("age", _i32p), ("n_removed", ctypes.c_int64),
     ]
 
 
@@ -80,6 +83,16 @@ def lib():
         L.orc_stats.argtypes = [ctypes.c_int64, _dp, _dp, _dp, ctypes.c_double, _dp, _dp, _dp,
                                 ctypes.POINTER(ctypes.c_float), _i64p]
         L.orc_stats.restype = None
+        L.orc_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                               ctypes.POINTER(ctypes.c_uint32)]
+        L.orc_draw.restype = None
+        L.orc_brownian.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
+                                   _dp]
+        L.orc_brownian.restype = None
+        L.orc_dies.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int32]
+        L.orc_dies.restype = ctypes.c_int
+        L.orc_divides.argtypes = [ctypes.POINTER(OrcParams), ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_divides.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -89,16 +102,18 @@ def _ptr(a, ctype):
 
 
 def make_params(dt=0.01, k=2.0, gamma=1.0, adherence=1.8, mass=0.1, max_disp=3.0, box_len=15.0,
-                div_vol=0.0, shift_frac=0.125, detect_static=False, brute_force=False, seed=0, sim_id=0):
+                div_vol=0.0, shift_frac=0.125, detect_static=False, brute_force=False, seed=0, sim_id=0,
+                brownian_rate=0.0, death_prob=0.0, division_prob=1.0, min_age=0):
     return OrcParams(dt, k, gamma, adherence, mass, max_disp, box_len, div_vol, shift_frac,
-                     int(bool(detect_static)), int(bool(brute_force)), int(seed), int(sim_id), 0)
+                     int(bool(detect_static)), int(bool(brute_force)), int(seed), int(sim_id), 0,
+                     float(brownian_rate), float(death_prob), float(division_prob), int(min_age), 0)
 
 
 class OracleSim:
     """One population advanced by the oracle; arrays are numpy, sized ``cap``."""
 
     def __init__(self, pos, diam, params, vol=None, growth=None, uid=None, cap=None, next_uid=None,
-                 is_static=None, nz=None, iteration=0):
+                 is_static=None, nz=None, iteration=0, age=None):
         pos = np.asarray(pos, dtype=np.float64)
         n = pos.shape[0]
         cap = n if cap is None else int(cap)
@@ -116,6 +131,9 @@ class OracleSim:
         self.box = z(np.int64)
         self.sum_abs_fn, self.sum_dfn, self.sum_fn_d = z(np.float64), z(np.float64), z(np.float64)
         self.moved, self.grew, self.divided, self.is_new = z(np.uint8), z(np.uint8), z(np.uint8), z(np.uint8)
+        self.age = z(np.int32)
+        if age is not None:
+            self.age[:n] = np.asarray(age, dtype=np.int32)
         self.x[:n], self.y[:n], self.z[:n] = pos[:, 0], pos[:, 1], pos[:, 2]
         self.diam[:n] = np.asarray(diam, dtype=np.float64)
         if vol is None:
@@ -141,7 +159,7 @@ class OracleSim:
                          ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double),
                          ("box", ctypes.c_int64), ("sum_abs_fn", ctypes.c_double), ("sum_dfn", ctypes.c_double),
                          ("sum_fn_d", ctypes.c_double), ("moved", ctypes.c_uint8), ("grew", ctypes.c_uint8), ("divided", ctypes.c_uint8),
-                         ("is_new", ctypes.c_uint8)):
+                         ("is_new", ctypes.c_uint8), ("age", ctypes.c_int32)):
             setattr(s, name, _ptr(getattr(self, name), ct))
 
     @property
@@ -151,6 +169,10 @@ class OracleSim:
     @property
     def iteration(self):
         return int(self.state.iter)
+
+    @property
+    def n_removed(self):
+        return int(self.state.n_removed)
 
     def step(self, n_iter=1):
         for _ in range(n_iter):
@@ -231,6 +253,29 @@ def direction(seed, sim_id, uid, iteration):
     u = np.zeros(3)
     lib().orc_direction(seed, sim_id, uid, iteration, _ptr(u, ctypes.c_double))
     return u
+
+
+def draw(seed, tag, sim_id, uid, iteration):
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_draw(seed, tag, sim_id, uid, iteration, o)
+    return [int(v) for v in o]
+
+
+def brownian(seed, sim_id, uid, iteration, rate):
+    d = np.zeros(3)
+    lib().orc_brownian(seed, sim_id, uid, iteration, rate, _ptr(d, ctypes.c_double))
+    return d
+
+
+def dies(params, uid, iteration, age):
+    return bool(lib().orc_dies(ctypes.byref(params), uid, iteration, age))
+
+
+def divides(params, uid, iteration):
+    return bool(lib().orc_divides(ctypes.byref(params), uid, iteration))
+
+
+TAG_BROWNIAN, TAG_DEATH, TAG_DIVISION = 0x42524F57, 0x44454154, 0x44495650
 
 
 def diameter_from_volume(v):

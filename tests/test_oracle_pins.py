@@ -427,3 +427,109 @@ def test_mlp_forward_on_a_network_computed_by_hand():
     y, _ = mlp.forward(theta, x, dims)
     assert np.allclose(y, expect, rtol=1e-14, atol=1e-14)
     assert mlp.n_params(dims) == theta.size == 6 + 3 + 6 + 2 + 4 + 2
+
+
+# --- Algorithm 2 cell behaviour: Brownian step, apoptosis, division probability ------------
+def test_brownian_step_has_the_rate_as_length_and_symmetric_moments():
+    """Lines 1-3 of Algorithm 2: a normalised vector times the displacement
+    rate, so every step is rate long (to rounding); the cube is symmetric
+    under sign flips and axis swaps, so the mean direction is 0 and each
+    squared component averages 1/3 (5 sigma over 1e5 draws)."""
+    rate = 0.005
+    n = 100000
+    d = np.array([sim.brownian(11, 3, uid, 7, rate) for uid in range(n)])
+    assert np.allclose(np.linalg.norm(d, axis=1), rate, rtol=4e-16, atol=0)
+    u = d / rate
+    assert np.all(np.abs(u.mean(axis=0)) < 5 * np.sqrt(1 / 3 / n))
+    # var(u_x^2) <= 1 for a unit vector component
+    assert np.all(np.abs((u ** 2).mean(axis=0) - 1 / 3) < 5 * np.sqrt(1 / n))
+    # a different iteration or simulation gives a different step (counter words)
+    assert not np.array_equal(sim.brownian(11, 3, 5, 7, rate), sim.brownian(11, 3, 5, 8, rate))
+    assert not np.array_equal(sim.brownian(11, 3, 5, 7, rate), sim.brownian(11, 4, 5, 7, rate))
+
+
+def _far_apart(n, seed):
+    """n cells on a lattice of spacing 40 um (no contacts), diameter 10."""
+    rng = np.random.default_rng(seed)
+    side = int(np.ceil(n ** (1 / 3)))
+    g = np.stack(np.meshgrid(*[np.arange(side) * 40.0] * 3, indexing="ij"), -1).reshape(-1, 3)[:n]
+    return g + rng.uniform(-1, 1, size=g.shape), np.full(n, 10.0)
+
+
+def test_apoptosis_removes_the_expected_share_and_only_old_cells():
+    """Line 4: a cell of at least min_age iterations is removed with the death
+    probability.  Of 20,000 eligible cells about N p are removed (5 sigma of
+    the binomial); cells younger than min_age never are; survivors keep
+    their order and uids and age by one; the removed cells are gone."""
+    n = 30000
+    pos, diam = _far_apart(n, 1)
+    age = np.where(np.arange(n) < 20000, 87, 86).astype(np.int32)  # 20,000 eligible, 10,000 one short
+    p = sim.make_params(box_len=15.0, death_prob=0.033, min_age=87, seed=5)
+    o = sim.OracleSim(pos, diam, p, age=age)
+    uid0 = o.uid[:n].copy()
+    o.step(1)
+    removed = np.setdiff1d(uid0, o.uid[: o.n])
+    R = removed.size
+    assert o.n_removed == R and o.n == n - R
+    mean, sd = 20000 * 0.033, np.sqrt(20000 * 0.033 * 0.967)
+    assert abs(R - mean) < 5 * sd
+    assert np.all(removed < 20000), "a cell below the minimum age was removed"
+    assert np.array_equal(o.uid[: o.n], np.setdiff1d(uid0, removed))  # order kept
+    assert np.array_equal(o.age[: o.n], age[np.isin(uid0, o.uid[: o.n])] + 1)
+    # the removal draw is a pure function of (seed, sim, uid, iteration): the same set again
+    o2 = sim.OracleSim(pos, diam, p, age=age)
+    o2.step(1)
+    assert np.array_equal(o2.uid[: o2.n], o.uid[: o.n])
+    assert all(sim.dies(p, int(u), 0, 87) for u in removed[:50])
+
+
+def test_division_probability_divides_the_expected_share():
+    """Line 11: a cell at the division volume divides with the division
+    probability; one whose draw fails neither grows nor divides; a daughter
+    starts at age 0 and the mother keeps her (incremented) age."""
+    n = 8000
+    pos, diam = _far_apart(n, 2)
+    vdiv = np.pi * 10.0 ** 3 / 6
+    p = sim.make_params(box_len=0.0, div_vol=vdiv, division_prob=0.5, seed=8)
+    vol = np.full(n, vdiv)
+    age = np.full(n, 5, dtype=np.int32)
+    o = sim.OracleSim(pos, diam, p, vol=vol, growth=np.ones(n), cap=2 * n, age=age)
+    o.step(1)
+    D = o.n - n
+    assert abs(D - n / 2) < 5 * np.sqrt(n / 4)
+    new = o.is_new[: o.n] == 1
+    assert np.all(o.age[: o.n][new] == 0) and np.all(o.age[: o.n][~new] == 6)
+    mothers = o.divided[: o.n] == 1
+    assert mothers.sum() == D
+    stay = ~new & ~mothers
+    assert np.all(o.vol[: o.n][stay] == vdiv), "a cell at the division volume grew"
+    assert np.allclose(o.vol[: o.n][mothers], vdiv / 2, rtol=0, atol=0)
+
+
+def test_static_skip_is_exact_under_removals():
+    """Condition (iv) of Sec 5.5 lets cells be removed without ending the
+    static state of their neighbours: with removals every iteration, the
+    oracle with static detection on and off gives bitwise equal states."""
+    from paper_2503_10796_amd import inputs
+    pos, diam = inputs.relaxed_lattice(14, seed=2)
+    n = pos.shape[0]
+    age = np.random.default_rng(3).integers(80, 100, size=n).astype(np.int32)
+    kw = dict(box_len=15.0, death_prob=0.05, min_age=87, seed=4)
+    a = sim.OracleSim(pos, diam, sim.make_params(detect_static=True, **kw), age=age)
+    b = sim.OracleSim(pos, diam, sim.make_params(detect_static=False, **kw), age=age)
+    removed = 0
+    for _ in range(12):
+        a.step(1)
+        b.step(1)
+        removed += a.n_removed
+        assert a.n == b.n
+        assert np.array_equal(a.uid[: a.n], b.uid[: b.n])
+        assert np.array_equal(a.pos(), b.pos())
+    assert removed > 50 and a.is_static[: a.n].sum() > 0.8 * a.n
+
+
+def test_static_detection_with_brownian_motion_is_refused():
+    pos, diam = _far_apart(8, 3)
+    o = sim.OracleSim(pos, diam, sim.make_params(detect_static=True, brownian_rate=0.01))
+    with pytest.raises(RuntimeError):
+        o.step(1)
