@@ -66,9 +66,22 @@ extern "C" {
  *          below this volume and divide at or above it; 0 = no growth.
  * shift_frac: on division mother and daughter move shift_frac * r_mother in
  *          opposite directions along a uniformly random unit vector.
- * detect_static: 1 = skip the force of agents meeting the four conditions of Sec 5.5.
- * resort_every: Morton re-sort of agent storage every so many iterations (0 = never).
- * seed, sim_id: key and counter word of the Philox4x32-10 division directions. */
+ * detect_static: 1 = skip the force of agents meeting the four conditions of Sec 5.5
+ *          (not with brownian_rate > 0: every agent then moves every iteration).
+ * resort_every: Morton re-sort of agent storage every so many iterations (0 = never;
+ *          < 0 = let abm_batch_tune pick it, never until then).
+ * seed, sim_id: key and counter words of the Philox4x32-10 draws (division
+ *          directions and the cell behaviour below).
+ * Cell behaviour of Algorithm 2 (Table 4.2), per iteration:
+ * brownian_rate: length of a random step along the normalised vector of three
+ *          uniforms in (-1, 1), added before the mechanical displacement (0 = off).
+ * death_prob, min_age: a cell of at least min_age iterations is removed with
+ *          probability death_prob (0 = off); removals take effect for the next
+ *          iteration and are no change for the static rule (Sec 5.5, condition iv).
+ * division_prob: a cell at or above div_vol divides with this probability and
+ *          otherwise neither grows nor divides; must be in (0, 1] when div_vol > 0
+ *          (1 = the deterministic grow-or-divide rule).
+ * Daughters start at age 0; the mother keeps her age. */
 typedef struct abm_params {
     double dt, k, gamma, adherence, mass, max_disp;
     double box_len;
@@ -79,13 +92,16 @@ typedef struct abm_params {
     uint64_t seed;
     uint32_t sim_id;
     uint32_t flags;
+    double brownian_rate, death_prob, division_prob;
+    int32_t min_age;
+    int32_t reserved; /* 0 */
 } abm_params;
 
 /* Fields for abm_*_query.  Arrays are in the library's current storage order
  * (it changes on a Morton re-sort); match agents across calls by ABM_UID.
  * Element types: POS, FORCE, DISP: 3 doubles per agent (x,y,z interleaved);
  * DIAM, VOL, GROWTH: double; UID: uint64; STATIC: uint8; NZ, NBR_COUNT,
- * CONTACT_COUNT: int32; BOX: int64 linear box id (x fastest) in the grid of
+ * CONTACT_COUNT, AGE (iterations since creation): int32; BOX: int64 linear box id (x fastest) in the grid of
  * the last iteration.  FORCE, DISP, NBR_COUNT, CONTACT_COUNT and BOX are the
  * values of the last iteration run with ABM_DIAG or ABM_RECORD set (NBR_COUNT
  * and CONTACT_COUNT are -1 and FORCE is 0 for agents skipped as static;
@@ -98,7 +114,7 @@ typedef struct abm_params {
 enum abm_field {
     ABM_POS = 0, ABM_DIAM = 1, ABM_VOL = 2, ABM_GROWTH = 3, ABM_UID = 4, ABM_STATIC = 5,
     ABM_NZ = 6, ABM_NBR_COUNT = 7, ABM_CONTACT_COUNT = 8, ABM_FORCE = 9, ABM_DISP = 10,
-    ABM_BOX = 11
+    ABM_BOX = 11, ABM_AGE = 12
 };
 
 typedef struct abm_batch abm_batch;
@@ -129,15 +145,17 @@ int abm_batch_create(int n_sims, const abm_params *per_sim, const int64_t *n0, c
                      int inputs_on_device, const int64_t *capacity, const int64_t *box_capacity,
                      void *workspace, size_t ws_bytes, void *hip_stream, abm_batch **out);
 
-/* Restore per-agent static flags and non-zero-force counts, the next uid and
- * the iteration counter of every simulation (checkpoint resume: query a
- * running batch, create a new one from the queried arrays, restore).
- * is_static (uint8) and nz (int32) are sum(n) arrays in the creation order;
- * next_uid has n_sims entries; any of the three may be NULL.  Only valid
- * right after abm_batch_create, before any step, tune or other restore
- * (ABM_ERR_ARG otherwise: the state is no longer in creation order). */
-int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const int32_t *nz, const uint64_t *next_uid,
-                      int64_t iteration, int on_device);
+/* Restore per-agent static flags, non-zero-force counts and ages, the next
+ * uid and the iteration counter of every simulation (checkpoint resume:
+ * query a running batch, create a new one from the queried arrays, restore;
+ * also the way to give a new population its initial ages).  is_static
+ * (uint8), nz (int32) and age (int32, >= 0) are sum(n) arrays in the
+ * creation order; next_uid has n_sims entries; any of the four may be NULL
+ * (ages then start at 0).  Only valid right after abm_batch_create, before
+ * any step, tune or other restore (ABM_ERR_ARG otherwise: the state is no
+ * longer in creation order). */
+int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const int32_t *nz, const int32_t *age,
+                      const uint64_t *next_uid, int64_t iteration, int on_device);
 
 /* Advance every simulation by n_iter iterations (stream-ordered, graph
  * launched; the call waits for the stream once at the end to read the status).

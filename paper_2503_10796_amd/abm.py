@@ -12,10 +12,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libabm.so")
 
-POS, DIAM, VOL, GROWTH, UID, STATIC, NZ, NBR_COUNT, CONTACT_COUNT, FORCE, DISP, BOX = range(12)
+POS, DIAM, VOL, GROWTH, UID, STATIC, NZ, NBR_COUNT, CONTACT_COUNT, FORCE, DISP, BOX, AGE = range(13)
 _FIELD_TYPES = {POS: (np.float64, 3), DIAM: (np.float64, 1), VOL: (np.float64, 1), GROWTH: (np.float64, 1),
                 UID: (np.uint64, 1), STATIC: (np.uint8, 1), NZ: (np.int32, 1), NBR_COUNT: (np.int32, 1),
-                CONTACT_COUNT: (np.int32, 1), FORCE: (np.float64, 3), DISP: (np.float64, 3), BOX: (np.int64, 1)}
+                CONTACT_COUNT: (np.int32, 1), FORCE: (np.float64, 3), DISP: (np.float64, 3), BOX: (np.int64, 1),
+                AGE: (np.int32, 1)}
 DIAG = 1
 RECORD = 2
 
@@ -35,14 +36,18 @@ class Params(ctypes.Structure):
         ("box_len", ctypes.c_double), ("div_vol", ctypes.c_double), ("shift_frac", ctypes.c_double),
         ("detect_static", ctypes.c_int32), ("resort_every", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("sim_id", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+        ("brownian_rate", ctypes.c_double), ("death_prob", ctypes.c_double), ("division_prob", ctypes.c_double),
+        ("min_age", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
 def params(dt=0.01, k=2.0, gamma=1.0, adherence=1.8, mass=0.1, max_disp=3.0, box_len=15.0, div_vol=0.0,
-           shift_frac=0.125, detect_static=False, resort_every=0, seed=0, sim_id=0, diag=False, record=False):
+           shift_frac=0.125, detect_static=False, resort_every=0, seed=0, sim_id=0, diag=False, record=False,
+           brownian_rate=0.0, death_prob=0.0, division_prob=1.0, min_age=0):
     flags = (DIAG if diag else 0) | (RECORD if record else 0)
     return Params(dt, k, gamma, adherence, mass, max_disp, box_len, div_vol, shift_frac, int(bool(detect_static)),
-                  int(resort_every), int(seed), int(sim_id), flags)
+                  int(resort_every), int(seed), int(sim_id), flags, float(brownian_rate), float(death_prob),
+                  float(division_prob), int(min_age), 0)
 
 
 _lib = None
@@ -62,7 +67,7 @@ def lib():
         L.abm_batch_workspace_bytes.argtypes = [ctypes.c_int, _i64p, _i64p]
         L.abm_batch_create.argtypes = [ctypes.c_int, ctypes.POINTER(Params), _i64p, _vp, _vp, _vp, _vp, _vp,
                                        ctypes.c_int, _i64p, _i64p, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)]
-        L.abm_batch_restore.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int]
+        L.abm_batch_restore.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int]
         L.abm_batch_schedule.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int)] * 4
         L.abm_batch_step.argtypes = [_vp, ctypes.c_int]
         L.abm_batch_num_agents.argtypes = [_vp, _i64p]
@@ -228,10 +233,11 @@ class Batch:
     def hist_device(self, out, hist_rmax=400.0):
         check(lib().abm_batch_hist(self.h, float(hist_rmax), ctypes.c_void_p(out.data_ptr()), 1))
 
-    def restore(self, is_static=None, nz=None, next_uid=None, iteration=0):
+    def restore(self, is_static=None, nz=None, next_uid=None, iteration=0, age=None):
         keep = []
         check(lib().abm_batch_restore(self.h, _arg(is_static, np.uint8, False, keep), _arg(nz, np.int32, False, keep),
-                                      _arg(next_uid, np.uint64, False, keep), int(iteration), 0))
+                                      _arg(age, np.int32, False, keep), _arg(next_uid, np.uint64, False, keep),
+                                      int(iteration), 0))
 
     def tune(self, n_trial_iters=3):
         b = ctypes.c_int(0)

@@ -60,8 +60,8 @@ struct Carver {
 };
 
 struct Layout {
-    size_t sims, ctl, tile_begin, btile_begin, utile_begin, a_begin, wblk_begin, bnd, blist;
-    size_t pos[2], diam[2], vol[2], growth[2], uid[2], flags[2], nz[2];
+    size_t sims, ctl, tile_begin, btile_begin, utile_begin, a_begin, wblk_begin, mv_begin, bnd, blist;
+    size_t pos[2], diam[2], vol[2], growth[2], uid[2], flags[2], nz[2], birth[2];
     size_t stage8, key, rank, payload, sorted_idx, nbr, contacts, force, disp, boxid;
     size_t count, box_start, brank, dirty, arrive, dirty_blk, arrive_blk, active_blk, near_blk, tile_sum, tile_off, fix_list, dense_list, divflag, divrank;
     size_t stat_part, hist_cnt, stat_out;
@@ -97,6 +97,7 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
     L.utile_begin = c.take<int64_t>(n_sims + 1);
     L.a_begin = c.take<int64_t>(n_sims + 1);
     L.wblk_begin = c.take<int64_t>(n_sims + 1);
+    L.mv_begin = c.take<int64_t>(n_sims + 1);
     L.bnd = c.take<unsigned long long>((size_t)n_sims * kBndSlots * 7);
     for (int b = 0; b < 2; ++b) {
         L.pos[b] = c.take<double>(3 * A);
@@ -106,6 +107,7 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
         L.uid[b] = c.take<uint64_t>(A);
         L.flags[b] = c.take<uint8_t>(A);
         L.nz[b] = c.take<uint8_t>(A);
+        L.birth[b] = c.take<int32_t>(A);
     }
     L.stage8 = c.take<uint8_t>(A);
     L.key = c.take<uint32_t>(A);
@@ -185,6 +187,18 @@ __global__ void k_nz_from_i32(uint8_t *dst, const int32_t *src, int64_t a_off, i
     }
 }
 
+// birth = iteration - age (age = 0 where src is null)
+__global__ void k_birth_from_age(int32_t *dst, const int32_t *src, int64_t a_off, int64_t n, int64_t iteration) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        dst[a_off + q] = (int32_t)(iteration - (src ? (int64_t)src[q] : 0));
+}
+
+// age = iteration - birth
+__global__ void k_age(int32_t *dst, const int32_t *birth, int64_t n, int64_t iteration) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+        dst[q] = (int32_t)(iteration - (int64_t)birth[q]);
+}
+
 __global__ void k_widen_u8(int32_t *dst, const uint8_t *src, int64_t n, int mask) {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
         dst[q] = mask ? ((src[q] & mask) ? 1 : 0) : (int32_t)src[q];
@@ -216,6 +230,7 @@ struct abm_batch {
     Sched sched;            // launch schedule of the force sweep (autotuned)
     int grid_agents = 2048, grid_boxes = 2048;
     bool any_growth = false, any_static = false;
+    bool any_death = false, any_record = false;  // Algorithm 2 removals; recorded fields
     int resort_every = 0;
     hipGraphExec_t exec[3][2] = {};  // [part][diag], see capture()
     bool grid_valid = false;         // grid of the current state is built
@@ -246,12 +261,12 @@ static int capture(abm_batch *b, int part, int diag) {
     bool resort = b->resort_every > 0;
     if (part == 0)
         launch_iteration(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, b->sched, diag != 0, b->any_growth,
-                         b->any_static, resort);
+                         b->any_static, resort, b->any_death, b->any_record);
     else if (part == 1)
         launch_sweep(b->d, b->cap_stream, b->sched, diag != 0, b->any_static);
     else
         launch_after_sweep(b->d, b->cap_stream, b->grid_agents, b->grid_boxes, diag != 0, b->any_growth, b->any_static,
-                           resort);
+                           resort, b->any_death, b->any_record);
     hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (e != hipSuccess) return fail(ABM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&b->exec[part][diag], g, nullptr, nullptr, 0);
@@ -264,6 +279,11 @@ static bool params_ok(const abm_params &p) {
     if (!(p.dt > 0.0) || !(p.mass > 0.0) || !(p.max_disp > 0.0) || !(p.adherence >= 0.0)) return false;
     if (!isfinite(p.k) || !isfinite(p.gamma) || !(p.box_len >= 0.0) || !(p.div_vol >= 0.0)) return false;
     if (!(p.shift_frac >= 0.0) || !isfinite(p.shift_frac)) return false;
+    // Algorithm 2 cell behaviour
+    if (!(p.brownian_rate >= 0.0) || !isfinite(p.brownian_rate)) return false;
+    if (!(p.death_prob >= 0.0 && p.death_prob <= 1.0) || p.min_age < 0) return false;
+    if (p.div_vol > 0.0 && !(p.division_prob > 0.0 && p.division_prob <= 1.0)) return false;
+    if (p.detect_static && p.brownian_rate > 0.0) return false;  // every agent moves: none can be static
     return true;
 }
 
@@ -320,6 +340,7 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     d.utile_begin = (int64_t *)(w + L.utile_begin);
     d.a_begin = (int64_t *)(w + L.a_begin);
     d.wblk_begin = (int64_t *)(w + L.wblk_begin);
+    d.mv_begin = (int64_t *)(w + L.mv_begin);
     d.bnd = (unsigned long long *)(w + L.bnd);
     for (int k = 0; k < 2; ++k) {
         d.pos[k] = (double *)(w + L.pos[k]);
@@ -329,6 +350,7 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
         d.uid[k] = (uint64_t *)(w + L.uid[k]);
         d.flags[k] = (uint8_t *)(w + L.flags[k]);
         d.nz[k] = (uint8_t *)(w + L.nz[k]);
+        d.birth[k] = (int32_t *)(w + L.birth[k]);
     }
     d.stage8 = (uint8_t *)(w + L.stage8);
     d.key = (uint32_t *)(w + L.key);
@@ -375,6 +397,8 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     HIPCHK_C(hipMemsetAsync(d.divflag, 0, sizeof(uint32_t) * A, st));
     HIPCHK_C(hipMemsetAsync(d.flags[0], 0, A, st));
     HIPCHK_C(hipMemsetAsync(d.flags[1], 0, A, st));
+    HIPCHK_C(hipMemsetAsync(d.birth[0], 0, sizeof(int32_t) * A, st));  // age 0 at iteration 0
+    HIPCHK_C(hipMemsetAsync(d.birth[1], 0, sizeof(int32_t) * A, st));
     HIPCHK_C(hipMemsetAsync(d.nz[0], 0, A, st));
     HIPCHK_C(hipMemsetAsync(d.arrive, 0, B, st));
     HIPCHK_C(hipMemsetAsync(d.dirty_blk, 0, B, st));
@@ -389,6 +413,8 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     int64_t aoff = 0, boff = 0, sboff = 0, in_off = 0;
     b->any_growth = false;
     b->any_static = false;
+    b->any_death = false;
+    b->any_record = false;
     for (int s = 0; s < n_sims; ++s) {
         SimDesc &S = b->host_sims[s];
         memset(&S, 0, sizeof S);
@@ -405,11 +431,17 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
         S.seed = p.seed;
         S.sim_id = p.sim_id;
         S.flags = p.flags;
+        S.brownian_rate = p.brownian_rate;
+        S.death_prob = p.death_prob;
+        S.division_prob = p.division_prob;
+        S.min_age = p.min_age;
         S.n = n0[s];
         S.n_start = n0[s];
         S.next_uid = n0[s];
         a_begin[s] = aoff;
         b->any_growth |= p.div_vol > 0.0;
+        b->any_death |= p.death_prob > 0.0;
+        b->any_record |= (p.flags & ABM_RECORD) != 0;
         b->any_static |= p.detect_static != 0;
         // inputs
         if (n0[s] > 0) {
@@ -481,18 +513,25 @@ static int read_sims(abm_batch *b, std::vector<SimDesc> &v) {
     return ABM_OK;
 }
 
-extern "C" int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const int32_t *nz, const uint64_t *next_uid,
-                                 int64_t iteration, int on_device) {
+extern "C" int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const int32_t *nz, const int32_t *age,
+                                 const uint64_t *next_uid, int64_t iteration, int on_device) {
     g_err.clear();
     if (!b) return fail(ABM_ERR_ARG, "null handle");
     // the arrays are in creation order: only the untouched state of a new
     // handle is in that order (a step, the tuner or a restore re-sorts or
     // changes it)
     if (!b->fresh) return fail(ABM_ERR_ARG, "restore must directly follow abm_batch_create");
+    if (iteration < 0 || iteration > INT32_MAX) return fail(ABM_ERR_ARG, "iteration outside 0..2^31-1");
     std::vector<SimDesc> sims;
     int rc = read_sims(b, sims);
     if (rc) return rc;
     hipStream_t st = b->stream;
+    if (age && !on_device) {
+        int64_t tot = 0;
+        for (int s = 0; s < b->n_sims; ++s) tot += sims[s].n;
+        for (int64_t q = 0; q < tot; ++q)
+            if (age[q] < 0 || age[q] > iteration + (int64_t)INT32_MAX) return fail(ABM_ERR_ARG, "negative age");
+    }
     int64_t in_off = 0;
     for (int s = 0; s < b->n_sims; ++s) {
         int64_t n = sims[s].n;
@@ -512,6 +551,15 @@ extern "C" int abm_batch_restore(abm_batch *b, const uint8_t *is_static, const i
                     src = b->d.nbr;
                 }
                 hipLaunchKernelGGL(k_nz_from_i32, dim3(grid_for(n)), dim3(256), 0, st, b->d.nz[0], src, sims[s].a_off, n);
+            }
+            {  // birth iteration = iteration - age (age 0 without ages)
+                const int32_t *src = age ? age + in_off : nullptr;
+                if (src && !on_device) {
+                    HIPCHK(hipMemcpyAsync(b->d.contacts, src, sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+                    src = b->d.contacts;
+                }
+                hipLaunchKernelGGL(k_birth_from_age, dim3(grid_for(n)), dim3(256), 0, st, b->d.birth[0], src,
+                                   sims[s].a_off, n, iteration);
             }
             HIPCHK(hipStreamSynchronize(st));
         }
@@ -738,6 +786,11 @@ extern "C" int abm_batch_query(abm_batch *b, int sim, int field, void *dst, int 
     case ABM_NZ: {
         int32_t *tmp = (int32_t *)b->d.fix_list;  // free between steps
         hipLaunchKernelGGL(k_widen_u8, dim3(grid_for(n)), dim3(256), 0, st, tmp, b->d.nz[lp] + a, n, 0);
+        return copy(tmp, sizeof(int32_t) * n);
+    }
+    case ABM_AGE: {
+        int32_t *tmp = (int32_t *)b->d.fix_list;  // free between steps
+        hipLaunchKernelGGL(k_age, dim3(grid_for(n)), dim3(256), 0, st, tmp, b->d.birth[lp] + a, n, c.iter);
         return copy(tmp, sizeof(int32_t) * n);
     }
     case ABM_NBR_COUNT: return copy(b->d.nbr + a, sizeof(int32_t) * n);

@@ -147,6 +147,36 @@ __device__ inline void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
     }
 }
 
+// Per-agent random words of the cell behaviour (Algorithm 2): Philox4x32-10
+// with counter (uid low, uid high, iteration, simulation) and key (seed low
+// XOR a per-purpose tag, seed high), so that every draw is a pure function
+// of the agent and the iteration.  A word w gives the uniform (w + 1/2) 2^-32
+// in the open interval (0, 1), exact in FP64.
+constexpr uint32_t kTagBrownian = 0x42524f57u, kTagDeath = 0x44454154u, kTagDivision = 0x44495650u;
+__device__ inline void agent_draw(uint64_t seed, uint32_t tag, uint32_t sim, uint64_t uid, uint64_t iter,
+                                  uint32_t c[4]) {
+    c[0] = (uint32_t)uid;
+    c[1] = (uint32_t)(uid >> 32);
+    c[2] = (uint32_t)iter;
+    c[3] = sim;
+    philox(c, (uint32_t)seed ^ tag, (uint32_t)(seed >> 32));
+}
+__device__ inline double uniform_open(uint32_t w) { return ((double)w + 0.5) * 0x1.0p-32; }
+
+// Brownian step of Algorithm 2 (lines 1-3): three uniforms in (-1, 1), divided
+// by their Euclidean norm, times the displacement rate (correctly rounded FP64
+// division and square root, no contraction).
+__device__ inline void brownian_step(uint64_t seed, uint32_t sim, uint64_t uid, uint64_t iter, double rate,
+                                     double b[3]) {
+#pragma clang fp contract(off)
+    uint32_t c[4];
+    agent_draw(seed, kTagBrownian, sim, uid, iter, c);
+    double v[3];
+    for (int a = 0; a < 3; ++a) v[a] = 2.0 * uniform_open(c[a]) - 1.0;
+    const double norm = sqrt(fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0])));
+    for (int a = 0; a < 3; ++a) b[a] = (v[a] / norm) * rate;
+}
+
 // Squared distance below L^2 with the neighbour predicate's exact expression.
 __device__ inline bool near_point(double x, double y, double z, double px, double py, double pz, double L2) {
 #pragma clang fp contract(off)

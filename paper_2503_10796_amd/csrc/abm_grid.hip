@@ -24,6 +24,7 @@ __global__ void k_begin(Dev d) {
         SimDesc &S = d.sims[s];
         S.n_start = S.n;
         S.n_div = 0;
+        S.n_dead = 0;
         S.nonfinite = 0;
         S.L_prev = S.L;
     }
@@ -539,7 +540,7 @@ __global__ void k_end(Dev d) {
     if (ABM_ABORTED(d)) return;
     for (int s = threadIdx.x; s < d.n_sims; s += blockDim.x) {
         SimDesc &S = d.sims[s];
-        S.n = S.n_start + S.n_div;
+        S.n = S.n_start + S.n_div - S.n_dead;
         S.next_uid += S.n_div;
         S.n_start = S.n;
     }
@@ -627,6 +628,7 @@ __global__ void __launch_bounds__(256) k_rs_move(Dev d) {
         d.uid[nl][j] = d.uid[lp][i];
         d.flags[nl][j] = d.flags[lp][i] | kBufDiff;
         d.nz[nl][j] = d.nz[lp][i];
+        d.birth[nl][j] = d.birth[lp][i];
     }
 }
 

@@ -25,6 +25,7 @@ constexpr uint8_t kStatic = 1;
 constexpr uint8_t kBufDiff = 2;
 constexpr uint8_t kMoved = 4, kGrew = 8, kDivided = 16, kNew = 32;
 constexpr uint8_t kChgMask = kMoved | kGrew | kDivided | kNew;
+constexpr uint8_t kDead = 64;  // removed at the end of this iteration (Algorithm 2)
 
 // Sweep payload of one agent: its centre relative to the origin of its grid
 // box in fixed point, units of U = L 2^-kFixBits (exact integer offsets
@@ -47,8 +48,11 @@ struct alignas(256) SimDesc {
     int32_t detect_static, resort_every;
     uint64_t seed;
     uint32_t sim_id, flags;
+    double brownian_rate, death_prob, division_prob;  // Algorithm 2 cell behaviour
+    int32_t min_age;
     // dynamic
     int64_t n, n_start, next_uid, n_div;
+    int64_t n_dead;  // cells removed at the end of this iteration
     double lo[3], hi[3], L;
     double L_prev;  // box length of the previous grid (static rule radius)
     int32_t dims[3];
@@ -90,12 +94,14 @@ struct Dev {
     int64_t *utile_begin;  // n_sims + 1: prefix of uid tiles
     int64_t *a_begin;      // n_sims + 1: agent range starts (for agent -> sim)
     int64_t *wblk_begin;   // n_sims + 1: prefix of sweep work units (box blocks)
+    int64_t *mv_begin;     // n_sims + 1: prefix of the removals (movers of the compaction)
     unsigned long long *bnd;  // n_sims x kBndSlots x 7 bounds accumulators
     uint32_t *blist;       // per simulation: packed block coords in Morton order
     double *pos[2];        // each 3*A: x block, y block, z block
     double *diam[2], *vol[2], *growth[2];
     uint64_t *uid[2];
     uint8_t *flags[2], *nz[2];
+    int32_t *birth[2];  // iteration at whose start the agent was first present (age = iteration - birth)
     uint8_t *stage8;  // byte staging for host transfers (free between steps)
     uint32_t *key, *rank;
     Pay *payload;
@@ -193,11 +199,11 @@ struct Sched {
 
 // Host-side launch helpers implemented in the .hip files.
 void launch_iteration(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, const Sched &sc, bool diag,
-                      bool any_growth, bool any_static, bool resort);
+                      bool any_growth, bool any_static, bool resort, bool any_death, bool any_record);
 void launch_grid_build(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool any_static);
 void launch_sweep(const Dev &d, hipStream_t s, const Sched &sc, bool diag, bool any_static);
 void launch_after_sweep(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool diag, bool any_growth,
-                        bool any_static, bool resort);
+                        bool any_static, bool resort, bool any_death, bool any_record);
 void launch_resort(const Dev &d, hipStream_t s, int grid_agents, int grid_boxes, bool force, bool any_static);
 void launch_end(const Dev &d, hipStream_t s, int grid_boxes, bool any_static);
 void launch_near_marks(const Dev &d, hipStream_t s, int grid_boxes, bool arrivals);

@@ -84,15 +84,22 @@ template <bool DIAG>
 __device__ inline void commit_agent(const Dev &d, const SimDesc &S, int64_t i, int P, int lp, uint8_t fl, double x,
                                     double y, double z, double fx, double fy, double fz, int nz, int nbr,
                                     int contacts, uint32_t m, int64_t lin) {
+#pragma clang fp contract(off)
     const int64_t A = d.A;
     double dx, dy, dz;
-    bool moved = displacement64(fx, fy, fz, S, dx, dy, dz);
+    displacement64(fx, fy, fz, S, dx, dy, dz);
+    // Algorithm 2: the Brownian step comes first, then the mechanical
+    // displacement: x' = (x + b) + d
+    double b[3] = {0.0, 0.0, 0.0};
+    if (S.brownian_rate > 0.0) brownian_step(S.seed, S.sim_id, d.uid[lp][i], (uint64_t)d.ctl->iter, S.brownian_rate, b);
+    const double nx = (x + b[0]) + dx, ny = (y + b[1]) + dy, nzz = (z + b[2]) + dz;
+    const bool moved = nx != x || ny != y || nzz != z;
     d.nz[lp][i] = (uint8_t)(nz > 255 ? 255 : nz);
     fl &= (uint8_t)~kChgMask;
     if (moved) {
-        d.pos[1 - P][i] = x + dx;
-        d.pos[1 - P][A + i] = y + dy;
-        d.pos[1 - P][2 * A + i] = z + dz;
+        d.pos[1 - P][i] = nx;
+        d.pos[1 - P][A + i] = ny;
+        d.pos[1 - P][2 * A + i] = nzz;
         d.flags[lp][i] = fl | kBufDiff | kMoved;
         if (S.detect_static) mark_box(d.dirty, d.dirty_blk, S, m);  // start box of a changed agent
     } else {
@@ -1448,25 +1455,47 @@ __device__ inline void division_direction(uint64_t seed, uint32_t sim, uint64_t 
     u[2] = zc;
 }
 
-__global__ void __launch_bounds__(256) k_div_mark(Dev d) {
+// Fate of every cell from the start-of-iteration state (Algorithm 2): removal
+// (line 4: at least min_age iterations old and the death draw below the
+// death probability), then, for the cells that stay, division (lines 9-12:
+// at or above the division volume and the division draw below the division
+// probability).  A removed cell is no change for the static rule (Sec 5.5,
+// condition iv): its change bits are cleared.
+__global__ void __launch_bounds__(256) k_fate(Dev d) {
     if (ABM_ABORTED(d)) return;
     const int lp = d.ctl->lay_par;
     const int64_t total = d.ctl->total_tiles;
+    const int64_t iter = d.ctl->iter;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         int s = find_sim(d.tile_begin, d.n_sims, t);
         SimDesc &S = d.sims[s];
-        if (!(S.div_vol > 0.0)) continue;
+        const bool growth = S.div_vol > 0.0, death = S.death_prob > 0.0;
+        if (!growth && !death) continue;
         int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        bool div = false;
+        bool div = false, dead = false;
         if (loc < S.n_start) {
-            int64_t i = S.a_off + loc;
-            if (d.vol[lp][i] >= S.div_vol) {
-                div = true;
-                d.divflag[S.a_off + d.uid[lp][i]] = 1u;
+            const int64_t i = S.a_off + loc;
+            const uint64_t u_id = d.uid[lp][i];
+            uint32_t c[4];
+            if (death && iter - (int64_t)d.birth[lp][i] >= (int64_t)S.min_age) {
+                agent_draw(S.seed, kTagDeath, S.sim_id, u_id, (uint64_t)iter, c);
+                dead = uniform_open(c[0]) < S.death_prob;
+            }
+            if (dead) {
+                d.flags[lp][i] = (uint8_t)((d.flags[lp][i] & ~kChgMask) | kDead);
+            } else if (growth && d.vol[lp][i] >= S.div_vol) {
+                div = S.division_prob >= 1.0;
+                if (!div) {
+                    agent_draw(S.seed, kTagDivision, S.sim_id, u_id, (uint64_t)iter, c);
+                    div = uniform_open(c[0]) < S.division_prob;
+                }
+                if (div) d.divflag[S.a_off + u_id] = 1u;
             }
         }
         unsigned long long b = __ballot(div);
         if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long *)&S.n_div, (unsigned long long)__popcll(b));
+        b = __ballot(dead);
+        if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long *)&S.n_dead, (unsigned long long)__popcll(b));
     }
 }
 
@@ -1581,8 +1610,9 @@ __global__ void __launch_bounds__(256) k_div_apply(Dev d) {
         int64_t i = S.a_off + loc;
         double v = d.vol[lp][i];
         const int Q = 1 - P;  // buffer of committed positions
-        if (v >= S.div_vol) {
-            uint64_t u_id = d.uid[lp][i];
+        if (d.flags[lp][i] & kDead) continue;  // removed: neither grows nor divides
+        const uint64_t u_id = d.uid[lp][i];
+        if (v >= S.div_vol && d.divflag[S.a_off + u_id]) {
             uint32_t rank = d.divrank[S.a_off + u_id];
             d.divflag[S.a_off + u_id] = 0u;
             int64_t j = S.a_off + S.n_start + rank;
@@ -1607,13 +1637,16 @@ __global__ void __launch_bounds__(256) k_div_apply(Dev d) {
             d.growth[lp][j] = d.growth[lp][i];
             d.uid[lp][j] = (uint64_t)S.next_uid + rank;
             d.nz[lp][j] = 0;
+            d.birth[lp][j] = (int32_t)(iter + 1);  // present from the next iteration, at age 0
             d.flags[lp][j] = kBufDiff | kNew;
             d.flags[lp][i] = (d.flags[lp][i] & ~kStatic) | kBufDiff | kMoved | kDivided;
-        } else {
+        } else if (v < S.div_vol) {
             double nv = v + d.growth[lp][i];
             d.vol[lp][i] = nv;
             d.diam[lp][i] = diameter_from_volume(nv);
             d.flags[lp][i] |= kGrew;
+        } else {
+            continue;  // at the division volume with a failed division draw: no change
         }
         if (S.detect_static) mark_box(d.dirty, d.dirty_blk, S, key_rank(d, S, d.key[i]));  // start box of a changed agent
     }
@@ -1705,6 +1738,125 @@ __global__ void __launch_bounds__(256) k_static(Dev d, const SimDesc *__restrict
     }
 }
 
+// ------------------------------------------------------------------ removals
+// Removed cells leave the state at the end of the iteration without gaps
+// (Sec 5.3.2, Fig 5.1): with R removals out of m agents (daughters included,
+// never removed in the iteration that creates them) the state shrinks to
+// m - R.  Removed cells left of m - R are holes; living cells right of it
+// are movers; there are as many of each, and the k-th mover (ascending index)
+// fills the k-th hole.  Both ranks come from one index-ordered exclusive scan
+// of the removal flags (dp = removals before an index): a hole's rank is dp,
+// a mover's is its offset past m - R minus the removals in between.  Only
+// the R movers are copied, and the result does not depend on any timing.
+
+// Scan tiles (1,024 agents of [0, n_start)) of the simulations with
+// removals, and the prefix of their mover counts (the removals R).
+__global__ void k_rm_plan(Dev d) {
+    if (ABM_ABORTED(d)) return;
+    if (threadIdx.x == 0) {
+        int64_t t = 0, mv = 0;
+        for (int s = 0; s < d.n_sims; ++s) {
+            const SimDesc &S = d.sims[s];
+            d.utile_begin[s] = t;
+            d.mv_begin[s] = mv;
+            if (S.n_dead > 0) {
+                t += ceil_div(S.n_start, kBoxTile);
+                mv += S.n_dead;
+            }
+        }
+        d.utile_begin[d.n_sims] = t;
+        d.mv_begin[d.n_sims] = mv;
+        d.ctl->total_utiles = t;
+    }
+}
+
+__device__ inline uint32_t dead_flag(const Dev &d, const SimDesc &S, int lp, int64_t k) {
+    return (k < S.n_start && (d.flags[lp][S.a_off + k] & kDead)) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(256) k_rm_tiles(Dev d) {
+    if (ABM_ABORTED(d)) return;
+    __shared__ uint32_t sh[4];
+    const int lp = d.ctl->lay_par;
+    const int64_t total = d.ctl->total_utiles;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const int s = find_sim(d.utile_begin, d.n_sims, t);
+        const SimDesc &S = d.sims[s];
+        const int64_t k0 = (t - d.utile_begin[s]) * kBoxTile + threadIdx.x * 4;
+        uint32_t v[4];
+        for (int q = 0; q < 4; ++q) v[q] = dead_flag(d, S, lp, k0 + q);
+        uint32_t tot;
+        block_excl_scan_4(v, sh, tot);
+        if (threadIdx.x == 0) d.tile_sum[t] = tot;
+    }
+}
+
+// Per agent of [0, n_start): the removals before it (into divrank, free after
+// the divisions); per hole: its index at its rank (into fix_list, free after
+// the FP64 path).
+__global__ void __launch_bounds__(256) k_rm_apply(Dev d) {
+    if (ABM_ABORTED(d)) return;
+    __shared__ uint32_t sh[4];
+    const int lp = d.ctl->lay_par;
+    const int64_t total = d.ctl->total_utiles;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const int s = find_sim(d.utile_begin, d.n_sims, t);
+        const SimDesc &S = d.sims[s];
+        const int64_t k0 = (t - d.utile_begin[s]) * kBoxTile + threadIdx.x * 4;
+        const int64_t keep = S.n_start + S.n_div - S.n_dead;
+        uint32_t v[4];
+        for (int q = 0; q < 4; ++q) v[q] = dead_flag(d, S, lp, k0 + q);
+        uint32_t tot;
+        uint32_t dp = d.tile_off[t] + block_excl_scan_4(v, sh, tot);
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = k0 + q;
+            if (k < S.n_start) {
+                d.divrank[S.a_off + k] = dp;
+                if (v[q] && k < keep) d.fix_list[S.a_off + dp] = (uint32_t)k;
+            }
+            dp += v[q];
+        }
+    }
+}
+
+// The movers fill the holes: every per-agent field of the state (both
+// position buffers) and, when recorded, the iteration's recorded fields.
+__global__ void __launch_bounds__(256) k_rm_move(Dev d, int record) {
+    if (ABM_ABORTED(d)) return;
+    const int lp = d.ctl->lay_par;
+    const int64_t A = d.A;
+    const int64_t total = d.mv_begin[d.n_sims];
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < total; g += (int64_t)gridDim.x * blockDim.x) {
+        const int s = find_sim(d.mv_begin, d.n_sims, g);
+        const SimDesc &S = d.sims[s];
+        const int64_t R = S.n_dead, keep = S.n_start + S.n_div - R;
+        const int64_t k = keep + (g - d.mv_begin[s]);  // in [keep, m)
+        if (dead_flag(d, S, lp, k)) continue;           // a removed cell past the new end
+        const int64_t dpk = k < S.n_start ? (int64_t)d.divrank[S.a_off + k] : R;
+        const int64_t dpe = keep < S.n_start ? (int64_t)d.divrank[S.a_off + keep] : R;
+        const int64_t rank = (k - keep) - (dpk - dpe);
+        const int64_t i = S.a_off + k, j = S.a_off + (int64_t)d.fix_list[S.a_off + rank];
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 3; ++a) d.pos[b][a * A + j] = d.pos[b][a * A + i];
+        d.diam[lp][j] = d.diam[lp][i];
+        d.vol[lp][j] = d.vol[lp][i];
+        d.growth[lp][j] = d.growth[lp][i];
+        d.uid[lp][j] = d.uid[lp][i];
+        d.flags[lp][j] = d.flags[lp][i];
+        d.nz[lp][j] = d.nz[lp][i];
+        d.birth[lp][j] = d.birth[lp][i];
+        if (record) {
+            for (int a = 0; a < 3; ++a) {
+                d.force[3 * j + a] = d.force[3 * i + a];
+                d.disp[3 * j + a] = d.disp[3 * i + a];
+            }
+            d.nbr[j] = d.nbr[i];
+            d.contacts[j] = d.contacts[i];
+            d.boxid[j] = d.boxid[i];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 void launch_sweep(const Dev &d, hipStream_t st, const Sched &sc, bool diag, bool any_static) {
     const SimDesc *sims = d.sims;
@@ -1728,14 +1880,14 @@ void launch_sweep(const Dev &d, hipStream_t st, const Sched &sc, bool diag, bool
 // Everything of one iteration after the sweep; ends by building the grid of
 // the committed state.
 void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, bool diag, bool any_growth,
-                        bool any_static, bool resort) {
+                        bool any_static, bool resort, bool any_death, bool any_record) {
     // two agents per wave on the FP64 path (32768 at a time, grid-stride beyond)
     const SimDesc *sims = d.sims;
     const int64_t *a_begin = d.a_begin;
     if (diag) hipLaunchKernelGGL(k_fixup<true>, dim3(4096), dim3(256), 0, st, d, sims, a_begin);
     else hipLaunchKernelGGL(k_fixup<false>, dim3(4096), dim3(256), 0, st, d, sims, a_begin);
+    if (any_growth || any_death) hipLaunchKernelGGL(k_fate, dim3(grid_agents), dim3(256), 0, st, d);
     if (any_growth) {
-        hipLaunchKernelGGL(k_div_mark, dim3(grid_agents), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_div_check, dim3(1), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_uscan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_uscan_top, dim3(1), dim3(1024), 0, st, d);
@@ -1747,6 +1899,13 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
         hipLaunchKernelGGL(k_static, dim3(grid_boxes), dim3(256), 0, st, d, (const SimDesc *)d.sims,
                            (const int64_t *)d.btile_begin);
     }
+    if (any_death) {
+        hipLaunchKernelGGL(k_rm_plan, dim3(1), dim3(64), 0, st, d);
+        hipLaunchKernelGGL(k_rm_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
+        hipLaunchKernelGGL(k_uscan_top, dim3(1), dim3(1024), 0, st, d);
+        hipLaunchKernelGGL(k_rm_apply, dim3(grid_boxes), dim3(256), 0, st, d);
+        hipLaunchKernelGGL(k_rm_move, dim3(grid_agents), dim3(256), 0, st, d, (diag || any_record) ? 1 : 0);
+    }
     launch_end(d, st, grid_boxes, any_static);
     if (resort) launch_resort(d, st, grid_agents, grid_boxes, false, any_static);
     launch_grid_build(d, st, grid_agents, grid_boxes, any_static);
@@ -1754,9 +1913,9 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
 
 // One iteration on the grid built at the end of the previous one.
 void launch_iteration(const Dev &d, hipStream_t st, int grid_agents, int grid_boxes, const Sched &sc, bool diag,
-                      bool any_growth, bool any_static, bool resort) {
+                      bool any_growth, bool any_static, bool resort, bool any_death, bool any_record) {
     launch_sweep(d, st, sc, diag, any_static);
-    launch_after_sweep(d, st, grid_agents, grid_boxes, diag, any_growth, any_static, resort);
+    launch_after_sweep(d, st, grid_agents, grid_boxes, diag, any_growth, any_static, resort, any_death, any_record);
 }
 
 }  // namespace abm

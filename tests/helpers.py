@@ -21,14 +21,14 @@ def gpu_state(abm, b, sim=0):
     """Full state of one simulation in the library's storage order."""
     return dict(pos=b.query(abm.POS, sim), diam=b.query(abm.DIAM, sim), vol=b.query(abm.VOL, sim),
                 growth=b.query(abm.GROWTH, sim), uid=b.query(abm.UID, sim), static=b.query(abm.STATIC, sim),
-                nz=b.query(abm.NZ, sim))
+                nz=b.query(abm.NZ, sim), age=b.query(abm.AGE, sim))
 
 
 def oracle_from_state(st, params, cap=None, next_uid=None, iteration=0):
     n = st["pos"].shape[0]
     return osim.OracleSim(st["pos"], st["diam"], params, vol=st["vol"], growth=st["growth"], uid=st["uid"],
                           cap=cap or max(n, 1), next_uid=next_uid, is_static=st["static"], nz=st["nz"],
-                          iteration=iteration)
+                          iteration=iteration, age=st.get("age"))
 
 
 def force_tolerance(o):
@@ -130,10 +130,11 @@ def compare_single_step(abm, b, o, sim=0, check_static=True, check_nbr=True):
     return out
 
 
-def compare_positions_single_step(abm, b, o, start_pos, sim=0):
-    """Production (non-diagnostic) step against the oracle stepped once from
-    the same state: the same agents move, and every new position is within
-    dt/m times the force tolerance of the oracle's."""
+def compare_positions_single_step(abm, b, o, st, sim=0):
+    """Production step against the oracle stepped once from the same state
+    (st: the start state from gpu_state): the same agents move, and every new
+    position is within dt/m times the force tolerance of the oracle's.
+    Agents are matched by uid (removals reorder the oracle's rows)."""
     n = o.n
     g_uid = b.query(abm.UID, sim)
     order_g = np.argsort(g_uid, kind="stable")
@@ -141,10 +142,15 @@ def compare_positions_single_step(abm, b, o, start_pos, sim=0):
     assert np.array_equal(g_uid[order_g], o.uid[:n][order_o]), "agent sets differ"
     pg = b.query(abm.POS, sim)[order_g]
     po = o.pos()[order_o]
-    p0 = np.full((n, 3), np.nan)  # daughters of this step have no start position
-    p0[: start_pos.shape[0]] = start_pos
-    p0 = p0[order_o]
-    old = o.is_new[:n][order_o] == 0
+    su = np.asarray(st["uid"])
+    so = np.argsort(su, kind="stable")
+    ou = o.uid[:n][order_o]
+    k = np.searchsorted(su[so], ou)
+    k = np.minimum(k, su.size - 1)
+    present = su[so][k] == ou  # daughters of this step have no start position
+    p0 = np.full((n, 3), np.nan)
+    p0[present] = np.asarray(st["pos"])[so][k[present]]
+    old = (o.is_new[:n][order_o] == 0) & present
     moved_g = np.any(pg[old] != p0[old], axis=1)
     moved_o = np.any(po[old] != p0[old], axis=1)
     assert np.array_equal(moved_g, moved_o), "move decisions differ"

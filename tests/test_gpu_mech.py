@@ -216,7 +216,7 @@ def test_spheroid_scale_run_first_100_iterations(abm):
                 res = H.compare_single_step(abm, b, o, check_static=False, check_nbr=False)
                 print(f"iteration {it}: {res}", flush=True)
             else:
-                H.compare_positions_single_step(abm, b, o, st["pos"])
+                H.compare_positions_single_step(abm, b, o, st)
             err = np.abs(b.query(abm.POS)[og] - o.pos()[oo]).max()
             assert err <= 1e-4, err
             print(f"iteration {it}: {o.n} agents, max position error {err:.2e} um", flush=True)
@@ -380,7 +380,8 @@ def test_checkpoint_resume_is_bitwise(abm, workload):
     nu = int(st["uid"].max()) + 1
     b = abm.Population(gp, st["pos"], st["diam"], vol=st["vol"], growth=st["growth"], uid=st["uid"], capacity=cap,
                        box_capacity=1 << 16)
-    b.restore(is_static=st["static"], nz=st["nz"], next_uid=np.array([nu], dtype=np.uint64), iteration=5)
+    b.restore(is_static=st["static"], nz=st["nz"], next_uid=np.array([nu], dtype=np.uint64), iteration=5,
+              age=st["age"])
     with pytest.raises(abm.AbmError) as e:  # only right after create
         b.restore(is_static=st["static"], iteration=5)
     assert e.value.code == abm.ERR_ARG
@@ -390,7 +391,7 @@ def test_checkpoint_resume_is_bitwise(abm, workload):
     ua, ub = a.query(abm.UID), b.query(abm.UID)
     oa, ob = np.argsort(ua), np.argsort(ub)
     assert np.array_equal(ua[oa], ub[ob])
-    for f in (abm.POS, abm.DIAM, abm.VOL, abm.GROWTH, abm.STATIC, abm.NZ):
+    for f in (abm.POS, abm.DIAM, abm.VOL, abm.GROWTH, abm.STATIC, abm.NZ, abm.AGE):
         assert np.array_equal(a.query(f)[oa], b.query(f)[ob]), f
     if workload == "spheroid":
         assert int(a.num_agents()[0]) > 800
