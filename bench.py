@@ -237,6 +237,52 @@ def bench_spheroid(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_apoptosis(args):
+    """Algorithm 2 cell behaviour at scale: the uniform mechanics population
+    (1 agent per 1000 um^3, diameters U[10,15) um, box 15 um) with the
+    Table 4.2 Brownian step (0.005 um) and apoptosis (minimum age 87, death
+    probability 0.033), initial ages uniform in [0, 100): every iteration
+    removes cells, which the removal kernels compact out of the state."""
+    import numpy as np
+    import torch
+    from paper_2503_10796_amd import abm, inputs
+    abm.lib()
+    n = args.agents
+    pos, diam = inputs.at_density(n, seed=1)
+    age = np.random.default_rng(7).integers(0, 100, size=n).astype(np.int32)
+    side = inputs.cube_side(n)
+    box_cap = int(1.1 * (side / 15.0 + 4.0) ** 3) + 4096
+    p = abm.params(box_len=15.0, resort_every=args.resort_every, seed=9, brownian_rate=0.005, death_prob=0.033,
+                   min_age=87)
+    pop = abm.Population(p, pos, diam, capacity=n, box_capacity=box_cap)
+    del pos, diam
+    pop.restore(age=age)
+    pop.set_sweep_grid(SWEEP_GRID["uniform"])
+    torch.cuda.synchronize()
+    pop.step(args.warmup)
+    torch.cuda.synchronize()
+    n0 = int(pop.num_agents()[0])
+    t0 = time.perf_counter()
+    pop.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    n1 = int(pop.num_agents()[0])
+    updates = float(n0 + n1) / 2.0 * args.steps
+    log(f"[bench] apoptosis: {n0} -> {n1} agents over {args.steps} timed iterations in {elapsed:.3f} s")
+    out = {
+        "metric": "Algorithm 2 cell behaviour with removals: agent updates/s",
+        "value": updates / elapsed, "unit": "agent updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"{n} agents uniform in a {side:.1f} um cube (1 per 1000 um^3), diameters U[10,15) "
+                               f"um, box 15 um, Brownian step 0.005 um, apoptosis from age 87 with probability "
+                               f"0.033, initial ages U[0,100), Morton re-sort every {args.resort_every}",
+                   "agents_start_timed": n0, "agents_end": n1,
+                   "removed_per_iteration": (n0 - n1) / args.steps},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_surrogate(args):
     """Surrogate screening: train on windows of a batched sweep, judge on the
     simulated histograms of held-out parameter sets, time the screening."""
@@ -359,11 +405,12 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--agents", type=int, default=100_000_000)
-    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate", "spheroid"],
+    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate", "spheroid", "apoptosis"],
                     default="uniform",
                     help="uniform / relaxed: mechanics at scale (the headline line); sweep: batched parameter "
                          "sweep vs the per-simulation path; surrogate: screening speedup and error; spheroid: "
-                         "one tumour spheroid grown to about 5e6 agents")
+                         "one tumour spheroid grown to about 5e6 agents; apoptosis: the uniform population with "
+                         "the Brownian step and apoptosis of Algorithm 2")
     ap.add_argument("--spheroid-scale", type=float, default=8.0,
                     help="spheroid: factor on the growth rates (8.0 reaches about 5e6 agents at 600 iterations)")
     ap.add_argument("--spheroid-iters", type=int, default=600, help="spheroid: iterations")
@@ -405,6 +452,9 @@ def main():
         return
     if args.workload == "spheroid":
         bench_spheroid(args)
+        return
+    if args.workload == "apoptosis":
+        bench_apoptosis(args)
         return
     from paper_2503_10796_amd import abm
 

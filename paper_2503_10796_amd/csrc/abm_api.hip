@@ -63,7 +63,7 @@ struct Layout {
     size_t sims, ctl, tile_begin, btile_begin, utile_begin, a_begin, wblk_begin, mv_begin, bnd, blist;
     size_t pos[2], diam[2], vol[2], growth[2], uid[2], flags[2], nz[2], birth[2];
     size_t stage8, key, rank, payload, sorted_idx, nbr, contacts, force, disp, boxid;
-    size_t count, box_start, brank, dirty, arrive, dirty_blk, arrive_blk, active_blk, near_blk, tile_sum, tile_off, fix_list, dense_list, divflag, divrank;
+    size_t count, box_start, brank, dirty, arrive, dirty_blk, arrive_blk, active_blk, near_blk, tile_sum, tile_off, rm_sum, rm_off, fix_list, dense_list, divflag, divrank;
     size_t stat_part, hist_cnt, stat_out;
     size_t total;
 };
@@ -131,6 +131,8 @@ bool make_layout(int n_sims, const int64_t *cap, const int64_t *bcap, Layout &L,
     L.near_blk = c.take<uint8_t>(B);
     L.tile_sum = c.take<uint32_t>(ST);
     L.tile_off = c.take<uint32_t>(ST);
+    L.rm_sum = c.take<uint32_t>(T);
+    L.rm_off = c.take<uint32_t>(T);
     L.fix_list = c.take<uint32_t>(A);
     L.dense_list = c.take<uint64_t>(dense_capacity(A, B));
     L.divflag = c.take<uint32_t>(A);
@@ -374,6 +376,8 @@ extern "C" int abm_batch_create(int n_sims, const abm_params *per_sim, const int
     d.near_blk = (uint8_t *)(w + L.near_blk);
     d.tile_sum = (uint32_t *)(w + L.tile_sum);
     d.tile_off = (uint32_t *)(w + L.tile_off);
+    d.rm_sum = (uint32_t *)(w + L.rm_sum);
+    d.rm_off = (uint32_t *)(w + L.rm_off);
     d.fix_list = (uint32_t *)(w + L.fix_list);
     d.dense_list = (uint64_t *)(w + L.dense_list);
     d.dense_cap = dense_capacity(A, B);

@@ -117,6 +117,7 @@ struct Dev {
     uint8_t *active_blk;  // blocks of the current grid holding an agent the next sweep must visit
     uint8_t *near_blk;    // a dirty (or arrival) mark in the block or one of its 26 neighbours
     uint32_t *tile_sum, *tile_off;
+    uint32_t *rm_sum, *rm_off;  // per agent tile: removals, and their exclusive prefix per simulation
     uint32_t *fix_list;
     uint64_t *dense_list;  // box-wise sweep items: unit << 9 | core box << 3 | pass group
     int64_t dense_cap;     // entries of dense_list

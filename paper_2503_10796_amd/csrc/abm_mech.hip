@@ -1460,20 +1460,22 @@ __device__ inline void division_direction(uint64_t seed, uint32_t sim, uint64_t 
 // death probability), then, for the cells that stay, division (lines 9-12:
 // at or above the division volume and the division draw below the division
 // probability).  A removed cell is no change for the static rule (Sec 5.5,
-// condition iv): its change bits are cleared.
+// condition iv): its change bits are cleared.  Each agent tile also writes
+// its number of removals (rm_sum) for the compaction's scan; the totals come
+// from the scans, not from atomics.
 __global__ void __launch_bounds__(256) k_fate(Dev d) {
     if (ABM_ABORTED(d)) return;
+    __shared__ uint32_t wsum[4];
     const int lp = d.ctl->lay_par;
     const int64_t total = d.ctl->total_tiles;
     const int64_t iter = d.ctl->iter;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
         int s = find_sim(d.tile_begin, d.n_sims, t);
-        SimDesc &S = d.sims[s];
+        const SimDesc &S = d.sims[s];
         const bool growth = S.div_vol > 0.0, death = S.death_prob > 0.0;
-        if (!growth && !death) continue;
         int64_t loc = (t - d.tile_begin[s]) * kTile + threadIdx.x;
-        bool div = false, dead = false;
-        if (loc < S.n_start) {
+        bool dead = false;
+        if ((growth || death) && loc < S.n_start) {
             const int64_t i = S.a_off + loc;
             const uint64_t u_id = d.uid[lp][i];
             uint32_t c[4];
@@ -1484,7 +1486,7 @@ __global__ void __launch_bounds__(256) k_fate(Dev d) {
             if (dead) {
                 d.flags[lp][i] = (uint8_t)((d.flags[lp][i] & ~kChgMask) | kDead);
             } else if (growth && d.vol[lp][i] >= S.div_vol) {
-                div = S.division_prob >= 1.0;
+                bool div = S.division_prob >= 1.0;
                 if (!div) {
                     agent_draw(S.seed, kTagDivision, S.sim_id, u_id, (uint64_t)iter, c);
                     div = uniform_open(c[0]) < S.division_prob;
@@ -1492,13 +1494,29 @@ __global__ void __launch_bounds__(256) k_fate(Dev d) {
                 if (div) d.divflag[S.a_off + u_id] = 1u;
             }
         }
-        unsigned long long b = __ballot(div);
-        if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long *)&S.n_div, (unsigned long long)__popcll(b));
-        b = __ballot(dead);
-        if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long *)&S.n_dead, (unsigned long long)__popcll(b));
+        const uint64_t bd = __ballot(dead);
+        if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(bd);
+        __syncthreads();
+        if (threadIdx.x == 0) d.rm_sum[t] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
     }
 }
 
+// Layout of the divider scan: tiles of kBoxTile uids per simulation with growth.
+__global__ void k_div_plan(Dev d) {
+    if (ABM_ABORTED(d)) return;
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int s = 0; s < d.n_sims; ++s) {
+            d.utile_begin[s] = t;
+            t += d.sims[s].div_vol > 0.0 ? ceil_div(d.sims[s].next_uid, kBoxTile) : 0;
+        }
+        d.utile_begin[d.n_sims] = t;
+        d.ctl->total_utiles = t;
+    }
+}
+
+// Capacity check once the divider scan has counted the divisions (n_div).
 __global__ void k_div_check(Dev d) {
     if (ABM_ABORTED(d)) return;
     __shared__ int bad;
@@ -1513,16 +1531,7 @@ __global__ void k_div_check(Dev d) {
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int s = 0; s < d.n_sims; ++s) {
-            d.utile_begin[s] = t;
-            t += d.sims[s].div_vol > 0.0 ? ceil_div(d.sims[s].next_uid, kBoxTile) : 0;
-        }
-        d.utile_begin[d.n_sims] = t;
-        d.ctl->total_utiles = t;
-        if (bad) d.ctl->abort = 1;
-    }
+    if (threadIdx.x == 0 && bad) d.ctl->abort = 1;
 }
 
 // Segmented exclusive scan of the divider flags (indexed by uid) -> rank.
@@ -1542,20 +1551,24 @@ __global__ void __launch_bounds__(256) k_uscan_tiles(Dev d) {
     }
 }
 
-__global__ void __launch_bounds__(1024) k_uscan_top(Dev d) {
+// Exclusive scan of per-tile counts within each simulation's tile range
+// (begin: n_sims + 1 tile prefix): offsets into off; each simulation's total
+// goes to its n_div (what = 0) or n_dead (what = 1).
+__global__ void __launch_bounds__(1024) k_tile_scan(Dev d, const int64_t *begin, const uint32_t *sum, uint32_t *off,
+                                                    int what) {
     if (ABM_ABORTED(d)) return;
     __shared__ uint32_t sh[16];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int s = 0; s < d.n_sims; ++s) {
-        int64_t b0 = d.utile_begin[s], b1 = d.utile_begin[s + 1];
+        int64_t b0 = begin[s], b1 = begin[s + 1];
         uint32_t carry = 0;
         for (int64_t c = b0; c < b1; c += blockDim.x) {
             int64_t t = c + threadIdx.x;
-            uint32_t v = t < b1 ? d.tile_sum[t] : 0u;
+            uint32_t v = t < b1 ? sum[t] : 0u;
             uint32_t x = v;
-            for (int off = 1; off < 64; off <<= 1) {
-                uint32_t y = __shfl_up(x, off);
-                if (lane >= off) x += y;
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t y = __shfl_up(x, o);
+                if (lane >= o) x += y;
             }
             if (lane == 63) sh[wid] = x;
             __syncthreads();
@@ -1564,9 +1577,13 @@ __global__ void __launch_bounds__(1024) k_uscan_top(Dev d) {
                 if (w < wid) wpre += sh[w];
                 tot += sh[w];
             }
-            if (t < b1) d.tile_off[t] = carry + wpre + x - v;
+            if (t < b1) off[t] = carry + wpre + x - v;
             carry += tot;
             __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (what == 0) d.sims[s].n_div = carry;
+            else d.sims[s].n_dead = carry;
         }
     }
 }
@@ -1749,74 +1766,51 @@ __global__ void __launch_bounds__(256) k_static(Dev d, const SimDesc *__restrict
 // a mover's is its offset past m - R minus the removals in between.  Only
 // the R movers are copied, and the result does not depend on any timing.
 
-// Scan tiles (1,024 agents of [0, n_start)) of the simulations with
-// removals, and the prefix of their mover counts (the removals R).
+// Prefix of the mover counts (the removals R) over the simulations, once
+// the scan of k_fate's per-tile counts has given each simulation's R.
 __global__ void k_rm_plan(Dev d) {
     if (ABM_ABORTED(d)) return;
     if (threadIdx.x == 0) {
-        int64_t t = 0, mv = 0;
+        int64_t mv = 0;
         for (int s = 0; s < d.n_sims; ++s) {
-            const SimDesc &S = d.sims[s];
-            d.utile_begin[s] = t;
             d.mv_begin[s] = mv;
-            if (S.n_dead > 0) {
-                t += ceil_div(S.n_start, kBoxTile);
-                mv += S.n_dead;
-            }
+            mv += d.sims[s].n_dead;
         }
-        d.utile_begin[d.n_sims] = t;
         d.mv_begin[d.n_sims] = mv;
-        d.ctl->total_utiles = t;
     }
 }
 
-__device__ inline uint32_t dead_flag(const Dev &d, const SimDesc &S, int lp, int64_t k) {
-    return (k < S.n_start && (d.flags[lp][S.a_off + k] & kDead)) ? 1u : 0u;
-}
-
-__global__ void __launch_bounds__(256) k_rm_tiles(Dev d) {
-    if (ABM_ABORTED(d)) return;
-    __shared__ uint32_t sh[4];
-    const int lp = d.ctl->lay_par;
-    const int64_t total = d.ctl->total_utiles;
-    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const int s = find_sim(d.utile_begin, d.n_sims, t);
-        const SimDesc &S = d.sims[s];
-        const int64_t k0 = (t - d.utile_begin[s]) * kBoxTile + threadIdx.x * 4;
-        uint32_t v[4];
-        for (int q = 0; q < 4; ++q) v[q] = dead_flag(d, S, lp, k0 + q);
-        uint32_t tot;
-        block_excl_scan_4(v, sh, tot);
-        if (threadIdx.x == 0) d.tile_sum[t] = tot;
-    }
-}
-
-// Per agent of [0, n_start): the removals before it (into divrank, free after
-// the divisions); per hole: its index at its rank (into fix_list, free after
-// the FP64 path).
+// Per agent tile (kTile agents of [0, n_start)): the removals before each
+// agent (dp, from the tile's offset and a block scan); each hole writes its
+// index at its rank (into fix_list, free after the FP64 path), and agents of
+// the tail [keep, n_start) keep dp for the movers (into divrank, free after
+// the divisions).
 __global__ void __launch_bounds__(256) k_rm_apply(Dev d) {
     if (ABM_ABORTED(d)) return;
-    __shared__ uint32_t sh[4];
+    __shared__ uint32_t wsum[4];
     const int lp = d.ctl->lay_par;
-    const int64_t total = d.ctl->total_utiles;
+    const int64_t total = d.ctl->total_tiles;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-        const int s = find_sim(d.utile_begin, d.n_sims, t);
+        const int s = find_sim(d.tile_begin, d.n_sims, t);
         const SimDesc &S = d.sims[s];
-        const int64_t k0 = (t - d.utile_begin[s]) * kBoxTile + threadIdx.x * 4;
+        if (S.n_dead == 0) continue;  // (block-uniform)
+        const int64_t k = (t - d.tile_begin[s]) * kTile + threadIdx.x;
+        const bool dead = k < S.n_start && (d.flags[lp][S.a_off + k] & kDead);
+        const uint64_t bd = __ballot(dead);
+        if (lane == 0) wsum[w] = (uint32_t)__popcll(bd);
+        __syncthreads();
+        uint32_t dp = d.rm_off[t] + (uint32_t)__popcll(bd & ((1ull << lane) - 1ull));
+        for (int v = 0; v < w; ++v) dp += wsum[v];
         const int64_t keep = S.n_start + S.n_div - S.n_dead;
-        uint32_t v[4];
-        for (int q = 0; q < 4; ++q) v[q] = dead_flag(d, S, lp, k0 + q);
-        uint32_t tot;
-        uint32_t dp = d.tile_off[t] + block_excl_scan_4(v, sh, tot);
-        for (int q = 0; q < 4; ++q) {
-            const int64_t k = k0 + q;
-            if (k < S.n_start) {
-                d.divrank[S.a_off + k] = dp;
-                if (v[q] && k < keep) d.fix_list[S.a_off + dp] = (uint32_t)k;
-            }
-            dp += v[q];
-        }
+        if (dead && k < keep) d.fix_list[S.a_off + dp] = (uint32_t)k;
+        if (k >= keep && k < S.n_start) d.divrank[S.a_off + k] = dp;
+        __syncthreads();
     }
+}
+
+__device__ inline bool dead_flag(const Dev &d, const SimDesc &S, int lp, int64_t k) {
+    return k < S.n_start && (d.flags[lp][S.a_off + k] & kDead);
 }
 
 // The movers fill the holes: every per-agent field of the state (both
@@ -1833,7 +1827,7 @@ __global__ void __launch_bounds__(256) k_rm_move(Dev d, int record) {
         const int64_t k = keep + (g - d.mv_begin[s]);  // in [keep, m)
         if (dead_flag(d, S, lp, k)) continue;           // a removed cell past the new end
         const int64_t dpk = k < S.n_start ? (int64_t)d.divrank[S.a_off + k] : R;
-        const int64_t dpe = keep < S.n_start ? (int64_t)d.divrank[S.a_off + keep] : R;
+        const int64_t dpe = keep < S.n_start ? (int64_t)d.divrank[S.a_off + keep] : R;  // (k >= keep: written)
         const int64_t rank = (k - keep) - (dpk - dpe);
         const int64_t i = S.a_off + k, j = S.a_off + (int64_t)d.fix_list[S.a_off + rank];
         for (int b = 0; b < 2; ++b)
@@ -1888,9 +1882,11 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
     else hipLaunchKernelGGL(k_fixup<false>, dim3(4096), dim3(256), 0, st, d, sims, a_begin);
     if (any_growth || any_death) hipLaunchKernelGGL(k_fate, dim3(grid_agents), dim3(256), 0, st, d);
     if (any_growth) {
-        hipLaunchKernelGGL(k_div_check, dim3(1), dim3(256), 0, st, d);
+        hipLaunchKernelGGL(k_div_plan, dim3(1), dim3(64), 0, st, d);
         hipLaunchKernelGGL(k_uscan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_uscan_top, dim3(1), dim3(1024), 0, st, d);
+        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, d, (const int64_t *)d.utile_begin,
+                           (const uint32_t *)d.tile_sum, d.tile_off, 0);
+        hipLaunchKernelGGL(k_div_check, dim3(1), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_uscan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_div_apply, dim3(grid_agents), dim3(256), 0, st, d);
     }
@@ -1900,10 +1896,10 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
                            (const int64_t *)d.btile_begin);
     }
     if (any_death) {
+        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, d, (const int64_t *)d.tile_begin,
+                           (const uint32_t *)d.rm_sum, d.rm_off, 1);
         hipLaunchKernelGGL(k_rm_plan, dim3(1), dim3(64), 0, st, d);
-        hipLaunchKernelGGL(k_rm_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_uscan_top, dim3(1), dim3(1024), 0, st, d);
-        hipLaunchKernelGGL(k_rm_apply, dim3(grid_boxes), dim3(256), 0, st, d);
+        hipLaunchKernelGGL(k_rm_apply, dim3(grid_agents), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_rm_move, dim3(grid_agents), dim3(256), 0, st, d, (diag || any_record) ? 1 : 0);
     }
     launch_end(d, st, grid_boxes, any_static);
