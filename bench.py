@@ -291,7 +291,7 @@ def bench_surrogate(args):
     from paper_2503_10796_amd import sweep, surrogate
     cfg = sweep.SweepConfig(args.sims, seed=4, iters=args.sweep_iters)
     hist, t_train_sim, _, _ = sweep.run_batched(cfg, record=True, tune=False, log=log)
-    x, y = surrogate.windows(cfg, hist, 20000, seed=6, t_max=cfg.iters - surrogate.HORIZON)
+    x, y = surrogate.windows(cfg, hist, 20000, seed=6, t_max=cfg.iters - surrogate.HORIZON, early=args.early_windows)
     model, t_train = surrogate.train(x, y, steps=args.train_steps, log=log)
     log(f"[bench] trained {args.train_steps} steps in {t_train:.2f} s")
     held = sweep.SweepConfig(2 * args.sims, seed=5, iters=cfg.iters)
@@ -304,8 +304,8 @@ def bench_surrogate(args):
     times = list(range(0, cfg.iters - surrogate.HORIZON + 1, 50))
     xe, ye, h0 = surrogate.eval_windows(held, hh, times)
     pred = model.predict(xe)
-    W = surrogate.linear_fit(x, y)
-    pred_lin = surrogate.to_hist(xe, surrogate.linear_predict(W, xe))
+    lin = surrogate.Linear(x, y)
+    pred_lin = lin.predict(xe)
     j_mlp, j_pers, j_lin = (surrogate.judge(p, ye, h0) for p in (pred, h0, pred_lin))
     log(f"[bench] held-out relative L2 error: surrogate {j_mlp}, persistence {j_pers}, linear {j_lin}")
     rg_true = surrogate.r_gyr_from_hist(ye)
@@ -339,6 +339,7 @@ def bench_surrogate(args):
     torch.cuda.synchronize()
     t_inf_big = (time.perf_counter() - t0) / reps
     flops = 2.0 * sum(surrogate.DIMS[i] * surrogate.DIMS[i + 1] for i in range(len(surrogate.DIMS) - 1)) * 4096
+    screen = screening(args, held, hh, model, t_b, t_ps)
     out = {
         "metric": "surrogate screening speedup over the batched simulation at the stated error",
         "value": t_b / t_inf, "unit": "x", "n_gpus": 1, "steps": args.train_steps, "warmup": 0,
@@ -358,8 +359,82 @@ def bench_surrogate(args):
         "speedup_vs_per_simulation": t_ps / t_inf,
         "inference_4096": {"ms": t_inf_big * 1e3, "tflops": flops / t_inf_big / 1e12},
         "training_s": t_train,
+        "screen_with_fallback": screen,
     }
     print(json.dumps(out), flush=True)
+
+
+SCREEN_TARGET = 0.02  # mean relative L2 error of the screened histograms
+
+
+def screening(args, held, hh, model, t_all, t_ps_all):
+    """Screening the held-out sweep 50 iterations ahead from its initial
+    state, with the plain simulation as fallback: the surrogate predicts every
+    set, the sets whose predicted change exceeds a threshold are simulated
+    instead (batched), the rest keep the prediction.  The threshold is the
+    largest that keeps the mean error within SCREEN_TARGET on the first half
+    of the sets; it is applied to the second half, where the end-to-end time
+    (inputs to screened histograms) and the error against the full simulation
+    of every set are reported.  t_all, t_ps_all: batched and per-simulation
+    simulation of all sets."""
+    import numpy as np
+    import torch
+    from paper_2503_10796_amd import sweep, surrogate
+    H = surrogate.HORIZON
+    n = held.n_sims
+    xe = np.concatenate([held.params_unit, np.log1p(hh[0])], axis=1).astype(np.float32)
+    truth = hh[H].astype(np.float64)
+    pred = model.predict(xe)
+    change = surrogate.predicted_change(xe, pred)
+    err = surrogate.rel_err(pred, truth)
+    pick, judge_sets = np.arange(n // 2), np.arange(n // 2, n)
+    tau, frac_pick = surrogate.pick_threshold(change[pick], err[pick], SCREEN_TARGET)
+    # end to end on the second half: inference from host inputs, flags, fallback simulation
+    xs = xe[judge_sets]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p2 = model.predict(xs)
+    flag = surrogate.predicted_change(xs, p2) > tau
+    t_pred = time.perf_counter() - t0
+    flagged = [int(judge_sets[k]) for k in np.nonzero(flag)[0]]
+    t_fb = 0.0
+    final = p2.copy()
+    if flagged:
+        hf, t_fb, _, _ = sweep.run_batched(held, record=True, tune=False, sims=flagged, iters=H)
+        assert np.array_equal(hf[H], hh[H][flagged]), "fallback histograms differ from the full simulation"
+        final[np.nonzero(flag)[0]] = hf[H]
+    e_final = surrogate.rel_err(final, truth[judge_sets])
+    e_pred = surrogate.rel_err(p2, truth[judge_sets])
+    t_screen = t_pred + t_fb
+    t_all_half = t_all * len(judge_sets) / n
+    t_ps_half = t_ps_all * len(judge_sets) / n
+    # other error targets: threshold from the first half, fallback simulated on the second
+    tradeoff = []
+    for target in (0.05, 0.10):
+        tau2, _ = surrogate.pick_threshold(change[pick], err[pick], target)
+        fl2 = [int(judge_sets[k]) for k in np.nonzero(surrogate.predicted_change(xs, p2) > tau2)[0]]
+        fin2 = p2.copy()
+        t2 = 0.0
+        if fl2:
+            hf2, t2, _, _ = sweep.run_batched(held, record=True, tune=False, sims=fl2, iters=H)
+            fin2[[judge_sets.tolist().index(f) for f in fl2]] = hf2[H]
+        e2 = surrogate.rel_err(fin2, truth[judge_sets])
+        tradeoff.append({"target_mean_rel_l2": target, "simulated": len(fl2), "mean_error": float(e2.mean()),
+                         "seconds": t_pred + t2, "speedup_vs_simulating_all": t_all_half / (t_pred + t2)})
+    log(f"[bench] screen: threshold {tau:.4f}, {len(flagged)} of {len(judge_sets)} sets simulated, "
+        f"mean error {e_final.mean():.4f} (surrogate alone {e_pred.mean():.4f}), {t_screen:.3f} s vs "
+        f"{t_all_half:.3f} s simulating all")
+    return {"target_mean_rel_l2": SCREEN_TARGET, "threshold_predicted_change": tau,
+            "fallback_fraction_pick_half": frac_pick, "sets": len(judge_sets), "simulated": len(flagged),
+            "final_error_rel_l2": {"mean": float(e_final.mean()), "median": float(np.median(e_final)),
+                                   "max": float(e_final.max())},
+            "surrogate_alone_error_rel_l2": {"mean": float(e_pred.mean()), "median": float(np.median(e_pred)),
+                                             "max": float(e_pred.max())},
+            "seconds": {"screen": t_screen, "predict_and_flag": t_pred, "fallback_simulation": t_fb,
+                        "simulate_all_batched": t_all_half},
+            "speedup_vs_simulating_all": t_all_half / t_screen if t_screen > 0 else None,
+            "speedup_vs_per_simulation": t_ps_half / t_screen if t_screen > 0 else None,
+            "other_targets": tradeoff}
 
 
 # Sweep work groups per workload, from a scan of 1,024 to 4,096 on one MI355X
@@ -419,6 +494,8 @@ def main():
     ap.add_argument("--batched-only", action="store_true",
                     help="sweep: time the batched path only (for kernel traces), no per-simulation comparison")
     ap.add_argument("--train-steps", type=int, default=3000, help="surrogate: Adam steps")
+    ap.add_argument("--early-windows", type=float, default=0.0,
+                    help="surrogate: share of training windows drawn with density 1/sqrt(t) (near the start)")
     ap.add_argument("--resort-every", type=int, default=10)
     ap.add_argument("--sweep-grid", type=int, default=None,
                     help="sweep work groups (default: 1024 for uniform, 2048 for relaxed)")

@@ -18,11 +18,17 @@ HORIZON = 50
 DIMS = (35, 256, 256, 256, 32)
 
 
-def windows(cfg, hist, n, seed, t_max=250):
-    """n training windows (x, y) from histories hist [iters+1, n_sims, 32]."""
+def windows(cfg, hist, n, seed, t_max=250, early=0.0):
+    """n training windows (x, y) from histories hist [iters+1, n_sims, 32]:
+    t uniform in [0, t_max], or with `early` > 0 that share of the windows
+    drawn with density falling as 1/sqrt(t) (more windows near the start,
+    where screening begins)."""
     rng = np.random.default_rng(seed)
     s = rng.integers(0, cfg.n_sims, size=n)
     t = rng.integers(0, t_max + 1, size=n)
+    k = int(early * n)
+    if k:
+        t[:k] = np.floor((t_max + 1) * rng.random(k) ** 2).astype(t.dtype)
     x = np.concatenate([cfg.params_unit[s], np.log1p(hist[t, s])], axis=1).astype(np.float32)
     y = (np.log1p(hist[t + HORIZON, s]) - np.log1p(hist[t, s])).astype(np.float32)
     return x, y
@@ -134,11 +140,43 @@ def train(x, y, steps=3000, batch=512, lr=1e-3, seed=0, log=None):
     return Surrogate(m, xm, xs, ym, ys), time.perf_counter() - t0
 
 
-def linear_fit(x, y):
-    X = np.concatenate([x.astype(np.float64), np.ones((x.shape[0], 1))], axis=1)
-    W, *_ = np.linalg.lstsq(X, y.astype(np.float64), rcond=None)
-    return W
+class Linear:
+    """Least-squares affine map of the same inputs to the same target (the
+    change of log(1 + histogram)); its predictions are clipped per bin to
+    the range of changes seen in training, so that it cannot extrapolate
+    outside the data it was fitted on."""
+
+    def __init__(self, x, y):
+        X = np.concatenate([x.astype(np.float64), np.ones((x.shape[0], 1))], axis=1)
+        self.W, *_ = np.linalg.lstsq(X, y.astype(np.float64), rcond=None)
+        self.lo, self.hi = y.min(axis=0).astype(np.float64), y.max(axis=0).astype(np.float64)
+
+    def predict_change(self, x):
+        X = np.concatenate([x.astype(np.float64), np.ones((x.shape[0], 1))], axis=1)
+        return np.clip(X @ self.W, self.lo, self.hi)
+
+    def predict(self, x):
+        return to_hist(x, self.predict_change(x))
 
 
-def linear_predict(W, x):
-    return np.concatenate([x.astype(np.float64), np.ones((x.shape[0], 1))], axis=1) @ W
+def predicted_change(x, pred):
+    """Relative L2 change of the histogram from the input to the prediction:
+    the screen's flag for a fallback (the surrogate is least accurate where
+    the spheroid changes most)."""
+    h0 = np.expm1(x[:, 3:].astype(np.float64))
+    return rel_err(pred, h0)
+
+
+def pick_threshold(change, err, target):
+    """The largest threshold on the predicted change at which the mean error
+    over all sets stays within target, when every set above the threshold is
+    simulated instead (error 0).  Returns (threshold, fallback fraction)."""
+    order = np.argsort(change)
+    n = change.size
+    kept_err = np.cumsum(err[order])  # error sum if the first k sets keep their prediction
+    best_k = 0
+    for k in range(1, n + 1):
+        if kept_err[k - 1] / n <= target:
+            best_k = k
+    tau = change[order[best_k - 1]] if best_k > 0 else -1.0
+    return float(tau), 1.0 - best_k / n

@@ -32,3 +32,33 @@ def test_surrogate_beats_persistence_on_held_out_sets(mods):
     print(f"surrogate {j}\npersistence {jp}", flush=True)
     assert j["mean"] < jp["mean"]
     assert j["median_changing"] < 0.7 * jp["median_changing"]
+
+
+def test_screen_with_simulation_fallback(mods):
+    """The screen: sets whose predicted change exceeds a threshold (picked on
+    the first half to keep the mean error within 2 %) are simulated instead;
+    on the second half the fallback histograms equal the full simulation bit
+    for bit and the screened mean error meets the target within a margin."""
+    sweep, surrogate = mods
+    iters = 100
+    cfg = sweep.SweepConfig(128, seed=4, iters=iters)
+    hist, _, _, _ = sweep.run_batched(cfg, record=True, tune=False)
+    x, y = surrogate.windows(cfg, hist, 8000, seed=6, t_max=iters - surrogate.HORIZON)
+    model, _ = surrogate.train(x, y, steps=2000)
+    held = sweep.SweepConfig(128, seed=5, iters=surrogate.HORIZON)
+    hh, _, _, _ = sweep.run_batched(held, record=True, tune=False)
+    xe = np.concatenate([held.params_unit, np.log1p(hh[0])], axis=1).astype(np.float32)
+    pred = model.predict(xe)
+    change = surrogate.predicted_change(xe, pred)
+    err = surrogate.rel_err(pred, hh[surrogate.HORIZON])
+    tau, frac = surrogate.pick_threshold(change[:64], err[:64], 0.02)
+    flag = np.nonzero(change[64:] > tau)[0] + 64
+    final = pred[64:].copy()
+    if flag.size:
+        hf, _, _, _ = sweep.run_batched(held, record=True, tune=False, sims=list(flag), iters=surrogate.HORIZON)
+        assert np.array_equal(hf[surrogate.HORIZON], hh[surrogate.HORIZON][flag])
+        final[flag - 64] = hf[surrogate.HORIZON]
+    e = surrogate.rel_err(final, hh[surrogate.HORIZON][64:])
+    print(f"threshold {tau:.4f}, fallback {flag.size} of 64 (pick half {frac:.2f}), mean error {e.mean():.4f} "
+          f"(surrogate alone {err[64:].mean():.4f})", flush=True)
+    assert e.mean() < 0.04 and flag.size < 64
