@@ -20,6 +20,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -59,30 +60,60 @@ def measured_traffic(n_agents, workload):
     return pmc.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(args):
-    """The FP64 oracle as it stands on a bounded sample of the same workload."""
+def oracle_sample(workload, n, iters):
+    """Time the FP64 oracle for `iters` iterations (after one untimed one) on
+    `n` agents of the mechanics workload; returns (agents, seconds)."""
     sys.path.insert(0, ROOT)
     from oracle import sim as osim
     from paper_2503_10796_amd import inputs
-    n = args.cpu_sample_agents
-    if args.workload == "uniform":
+    if workload == "uniform":
         pos, diam = inputs.at_density(n, seed=1)
         detect = False
     else:
         side = round(n ** (1.0 / 3.0))
         pos, diam = inputs.relaxed_lattice(side, seed=2)
         detect = True
-    n = pos.shape[0]
     o = osim.OracleSim(pos, diam, osim.make_params(box_len=15.0, detect_static=detect))
     o.step(1)  # first iteration untimed (initialisation excluded)
     t0 = time.perf_counter()
-    o.step(args.cpu_sample_iters)
-    dt = time.perf_counter() - t0
+    o.step(iters)
+    return pos.shape[0], time.perf_counter() - t0
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(args):
+    """The FP64 oracle as it stands on a bounded sample of the same workload:
+    with the host's OpenMP threads, and single-threaded (a child process with
+    one OpenMP thread) on a smaller sample."""
+    n, dt = oracle_sample(args.workload, args.cpu_sample_agents, args.cpu_sample_iters)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": n * args.cpu_sample_iters / dt, "unit": "agent updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{n} agents of the same workload (same density and diameters), {args.cpu_sample_iters} "
-                      f"iterations after one untimed iteration, FP64, OpenMP over agents, {dt:.1f} s"}
+    out = {"value": n * args.cpu_sample_iters / dt, "unit": "agent updates/s", "cores": threads,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{n} agents of the same workload (same density and diameters), {args.cpu_sample_iters} "
+                     f"iterations after one untimed iteration, FP64, OpenMP over agents, {dt:.1f} s"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample", args.workload,
+                        str(args.cpu_single_agents), str(args.cpu_single_iters)],
+                       env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode == 0:
+        n1, dt1 = json.loads(r.stdout.strip().splitlines()[-1])
+        out["single_thread"] = {"value": n1 * args.cpu_single_iters / dt1, "unit": "agent updates/s", "cores": 1,
+                                "sample": f"{n1} agents, {args.cpu_single_iters} iterations after one untimed "
+                                          f"iteration, one OpenMP thread, {dt1:.1f} s"}
+    else:
+        out["single_thread"] = None
+        log(f"[bench] single-thread oracle sample failed: {r.stderr[-500:]}")
+    return out
 
 
 def _counter_per_dispatch(path, kernel_substr, counter):
@@ -500,14 +531,24 @@ def main():
     ap.add_argument("--sweep-grid", type=int, default=None,
                     help="sweep work groups (default: 1024 for uniform, 2048 for relaxed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--static-trace", type=int, default=20,
+                    help="relaxed: iterations after the timed region whose static share is reported one by one")
     ap.add_argument("--cpu-sample-agents", type=int, default=4_000_000)
     ap.add_argument("--cpu-sample-iters", type=int, default=8)
+    ap.add_argument("--cpu-single-agents", type=int, default=1_000_000)
+    ap.add_argument("--cpu-single-iters", type=int, default=4)
+    ap.add_argument("--oracle-sample", nargs=3, metavar=("WORKLOAD", "AGENTS", "ITERS"),
+                    help="only time the oracle on the host (used for the single-thread cpu_baseline sample)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 2 GiB (reference kernel for the HBM byte counters)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
                     help="write the HBM bytes per force-sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counter "
                          "files (this workload, then the copy calibration) into " + os.path.relpath(PMC_FILE, ROOT))
     args = ap.parse_args()
+    if args.oracle_sample:
+        w, na, it = args.oracle_sample
+        print(json.dumps(oracle_sample(w, int(na), int(it))), flush=True)
+        return
     if args.pmc_summary:
         pmc_summary(args)
         return
@@ -558,6 +599,14 @@ def main():
     lo, L, gdims = pop.grid()
     nboxes = int(np.prod(gdims))
     static_frac = float(pop.query(abm.STATIC).mean()) if args.workload == "relaxed" else 0.0
+    static_trace = None
+    if args.workload == "relaxed":
+        # static share per iteration over the next iterations (untimed, one at a time)
+        static_trace = []
+        for _ in range(args.static_trace):
+            pop.step(1)
+            static_trace.append(round(float(pop.query(abm.STATIC).mean()), 6))
+        log(f"[bench] static fraction over {args.static_trace} further iterations: {static_trace}")
     sweep_avg_s = sweep_ms / max(n_sweeps, 1) / 1e3
     alg_bytes = n * SWEEP_BYTES_PER_AGENT + nboxes * SWEEP_BYTES_PER_BOX
     achieved = alg_bytes / sweep_avg_s / 1e9
@@ -578,6 +627,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "agents": n, "box_len_um": 15.0, "grid_boxes": nboxes,
                    "static_fraction_end": static_frac, "sweep_workgroups": sweep_grid},
+        "static_fraction_per_iteration": static_trace,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sweep", "kernel_ms": sweep_avg_s * 1e3,

@@ -179,7 +179,11 @@ def test_growth_division_matches_oracle(abm):
     pg = b.query(abm.POS)[np.argsort(b.query(abm.UID))]
     po = o.pos()[np.argsort(o.uid[:o.n])]
     err = np.linalg.norm(pg - po, axis=1)
-    print(f"C2 (reading A) 700 iterations: N={counts_g[-1]}, max position error {err.max():.3e} um", flush=True)
+    print(f"C2 (reading A) 700 iterations: N={counts_g[-1]}, max position error {err.max():.3e} um, "
+          f"rms {np.sqrt((err ** 2).mean()):.3e} um", flush=True)
+    # every move decision is certified, so the trajectories only differ by the
+    # forces' rounding (measured 4.5e-6 um after 700 iterations)
+    assert err.max() <= 1e-4
 
 
 def test_spheroid_scale_run_first_100_iterations(abm):

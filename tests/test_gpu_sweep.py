@@ -71,7 +71,7 @@ def test_tuned_batch_extremes_match_the_oracle(mods):
     move decisions, positions and static flags (Algorithm 2, Eq 4.1-4.2)."""
     abm, sweep = mods
     from tests import helpers as H
-    cfg = sweep.SweepConfig(256, seed=4, iters=31)
+    cfg = sweep.SweepConfig(256, seed=4, iters=41)  # capacities for 31 + 10 iterations
     sims = [73, 24, 218, 201, 148, 143]  # d_div 6.04 / 6.08, adherence 0.904 / 2.689 / 2.695, growth scale 1.5
     b, states, caps = sweep.build_batch(cfg, sims, record=True)
     b.tune(2)
@@ -96,6 +96,23 @@ def test_tuned_batch_extremes_match_the_oracle(mods):
             assert np.array_equal(b.query(abm.DIAM, k)[og], o.diam[:o.n][oo]), (s, it)
             res = H.compare_single_step(abm, b, o, sim=k, check_static=True, check_nbr=False)
             print(f"sim {s} iteration {it}: {o.n} agents, {res}", flush=True)
+    # 10-iteration trajectories from iteration 31 (divisions, static skip and a re-sort in between)
+    snaps = [H.gpu_state(abm, b, k) for k in range(len(sims))]
+    b.step(10)
+    for k, s in enumerate(sims):
+        st = snaps[k]
+        op = H.oracle_params(box_len=0.0, div_vol=sweep.inputs.division_volume(float(cfg.d_div[s])),
+                             adherence=float(cfg.adherence[s]), detect_static=True, seed=cfg.seed, sim_id=s)
+        o = H.oracle_from_state(st, op, cap=caps[k], next_uid=int(st["uid"].max()) + 1, iteration=31)
+        o.step(10)
+        ug = b.query(abm.UID, k)
+        og, oo = np.argsort(ug), np.argsort(o.uid[: o.n])
+        assert np.array_equal(ug[og], o.uid[: o.n][oo]), s
+        assert np.array_equal(b.query(abm.VOL, k)[og], o.vol[: o.n][oo]), s
+        err = np.linalg.norm(b.query(abm.POS, k)[og] - o.pos()[oo], axis=1)
+        print(f"sim {s}: 10-iteration trajectory, {o.n} agents, max {err.max():.3e} um, "
+              f"rms {np.sqrt((err ** 2).mean()):.3e} um", flush=True)
+        assert err.max() <= 1e-4
 
 
 def test_tuner_picks_every_schedule_parameter(mods):
