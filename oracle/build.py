@@ -1,6 +1,7 @@
 """Build the FP64 CPU oracle shared library (test infrastructure only).
 
-``python oracle/build.py`` compiles ``abm_oracle.c`` with gcc into
+``python oracle/build.py`` compiles ``abm_oracle.c`` (mechanics, cell
+behaviour, statistics) and ``sir_oracle.c`` (SIR epidemiology) with gcc into
 ``oracle/liboracle.so``.  The flags keep IEEE semantics: no fast-math and no
 floating-point contraction, so every product and sum rounds as written.
 """
@@ -9,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "abm_oracle.c")
+SRCS = [os.path.join(HERE, "abm_oracle.c"), os.path.join(HERE, "sir_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
@@ -17,7 +18,7 @@ def build(verbose: bool = False) -> str:
     cmd = [
         "gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp",
         "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter",
-        SRC, "-o", LIB + ".tmp", "-lquadmath", "-lm",
+        *SRCS, "-o", LIB + ".tmp", "-lquadmath", "-lm",
     ]
     if verbose:
         print(" ".join(cmd), flush=True)

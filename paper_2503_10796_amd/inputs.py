@@ -18,6 +18,11 @@ Recipes (sizes and distributions of the thesis's tissue benchmarks):
   sweep_params(n, seed)     Latin hypercube over growth scale [0.5, 1.5],
                             division diameter [6, 18] um, adherence [0.9, 2.7],
                             and log-uniform initial counts in [1e3, 5e4]
+  sir_population(...)       persons uniform in a cube of side S (metres), the
+                            first n_infected infected, the rest susceptible;
+                            SIR_MEASLES / SIR_INFLUENZA hold the Table 4.3
+                            sizes and parameters, scaled_sir() the same density
+                            at k times the persons
 """
 import math
 
@@ -102,3 +107,32 @@ def sweep_params(n_sims, seed=4, n_lo=1.0e3, n_hi=5.0e4):
     d_div = lhs(6.0, 18.0)
     adherence = lhs(0.9, 2.7)
     return n0, gscale, d_div, adherence
+
+
+# Table 4.3: cubic space length (m), persons (susceptible, infected), infection
+# radius (m), infection and recovery probabilities, maximum movement per step
+# (m), time steps; beta and gamma of the SIR equations it is compared with.
+SIR_MEASLES = dict(space=100.0, n_susceptible=2000, n_infected=20, radius=3.24179, infection_prob=0.28510,
+                   recovery_prob=0.00521, speed=5.78594, steps=1000, beta=0.06719, gamma=0.00521)
+SIR_INFLUENZA = dict(space=215.0, n_susceptible=20000, n_infected=200, radius=3.2123, infection_prob=0.04980,
+                     recovery_prob=0.01016, speed=4.2942, steps=2500, beta=0.01321, gamma=0.01016)
+
+
+def scaled_sir(cfg, k):
+    """The same model at k times the persons and the same density."""
+    out = dict(cfg)
+    out["n_susceptible"] = int(cfg["n_susceptible"] * k)
+    out["n_infected"] = int(cfg["n_infected"] * k)
+    out["space"] = cfg["space"] * float(k) ** (1.0 / 3.0)
+    return out
+
+
+def sir_population(n_susceptible, n_infected, space, seed=0):
+    """Positions uniform in [0, space)^3 (float64, n x 3) and states (uint8:
+    0 susceptible, 1 infected); persons 0..n_infected-1 start infected."""
+    n = int(n_susceptible) + int(n_infected)
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, space, size=(n, 3))
+    state = np.zeros(n, dtype=np.uint8)
+    state[: int(n_infected)] = 1
+    return pos, state
