@@ -286,6 +286,89 @@ int abm_mlp_set_params(abm_mlp *m, const float *src, size_t n);
 size_t abm_mlp_num_params(abm_mlp *m);
 int abm_mlp_destroy(abm_mlp *m);
 
+/* ------------------------------------------------------------------------- */
+/* SIR epidemiology (Sec 4.6.3): persons in a cubic space [0, S]^3 with a      */
+/* state each (susceptible, infected, recovered).  Per iteration, from the    */
+/* start-of-iteration state (copy semantics, Sec 5.2.1), every person runs    */
+/* its behaviours in the order:                                               */
+/*   infection  a susceptible person that draws U < infection_prob becomes    */
+/*              infected if an infected person is strictly within the         */
+/*              infection radius (Algorithm 3)                                */
+/*   recovery   an infected person (also one infected just now) recovers if   */
+/*              it draws U < recovery_prob (Algorithm 4)                      */
+/*   movement   a step of length `speed` along three uniforms in (-1, 1)      */
+/*              normalised to unit length, then the boundary (Algorithm 5,    */
+/*              Sec 4.4.11): toroidal wraps every coordinate into [0, S) with */
+/*              fmod, closed clamps it to [0, S].                             */
+/* On the torus, distances are minimum-image.  Draws: Philox4x32-10 with      */
+/* counter (uid, iteration, sim_id) and key (seed low XOR tag, seed high),    */
+/* tags 'INFE', 'RECO', 'MOVE'; a word w gives (w + 1/2) 2^-32.  Positions    */
+/* are FP64 and every operation is IEEE-rounded as written, so results are    */
+/* deterministic and independent of the storage order.                       */
+/* ------------------------------------------------------------------------- */
+#define ABM_SIR_SUSCEPTIBLE 0
+#define ABM_SIR_INFECTED 1
+#define ABM_SIR_RECOVERED 2
+#define ABM_BOUNDARY_TOROIDAL 0
+#define ABM_BOUNDARY_CLOSED 1
+
+/* Fields of abm_sir_query: positions (double, n x 3 interleaved), states
+ * (uint8), uids (uint32).  Rows are in the handle's storage order (persons
+ * sorted by grid box), the same order for every field of one query state. */
+#define ABM_SIR_POS 0
+#define ABM_SIR_STATE 1
+#define ABM_SIR_UID 2
+
+typedef struct abm_sir_params {
+    double space;          /* side S of the cubic space (> 0) */
+    double radius;         /* infection radius (> 0) */
+    double infection_prob; /* in [0, 1] */
+    double recovery_prob;  /* in [0, 1] */
+    double speed;          /* step length per iteration (>= 0) */
+    int32_t boundary;      /* ABM_BOUNDARY_TOROIDAL or ABM_BOUNDARY_CLOSED */
+    uint32_t sim_id;       /* counter word of the draws */
+    uint64_t seed;
+} abm_sir_params;
+
+typedef struct abm_sir abm_sir;
+
+/* Workspace bytes for n persons (n < 2^31) and a history of hist_cap
+ * iterations of counts; 0 for invalid arguments. */
+size_t abm_sir_workspace_bytes(const abm_sir_params *p, int64_t n, int hist_cap);
+
+/* Create from host arrays: pos (n x 3 interleaved, every coordinate in
+ * [0, S]), state (n bytes, 0..2); person k gets uid k.  The workspace
+ * (device memory of at least abm_sir_workspace_bytes) is owned by the caller
+ * and must outlive the handle; every kernel runs on hip_stream (NULL: the
+ * default stream).  Errors: ABM_ERR_ARG (bad parameters or inputs, workspace
+ * too small), ABM_ERR_NONFINITE (a non-finite coordinate), ABM_ERR_HIP. */
+int abm_sir_create(const abm_sir_params *p, int64_t n, const double *pos, const uint8_t *state, int hist_cap,
+                   void *workspace, size_t ws_bytes, void *hip_stream, abm_sir **out);
+
+/* Advance n_iter iterations.  counts (host, n_iter x 3 int64, or NULL)
+ * receives the numbers of susceptible, infected and recovered persons after
+ * each iteration.  Synchronises the stream when counts is not NULL. */
+int abm_sir_step(abm_sir *s, int n_iter, int64_t *counts);
+
+/* Copy one field (ABM_SIR_*) to dst (host, or device when dst_on_device);
+ * cap: rows dst holds (ABM_ERR_ARG if fewer than the persons). */
+int abm_sir_query(abm_sir *s, int field, void *dst, int dst_on_device, int64_t cap);
+
+/* Iterations done and persons per state now (host). */
+int abm_sir_counts(abm_sir *s, int64_t *iteration, int64_t counts[3]);
+
+/* Grid of the neighbour search: boxes per axis and box length (>= 2 radius). */
+int abm_sir_grid(abm_sir *s, int64_t *dims, double *box_len);
+
+/* Timing of the person kernel (infection, recovery, movement, binning):
+ * with timing on, every iteration brackets it with HIP events on the
+ * handle's stream; abm_sir_kernel_time returns the total and the count of the
+ * iterations timed since the last call, and resets them. */
+int abm_sir_set_timing(abm_sir *s, int on);
+int abm_sir_kernel_time(abm_sir *s, double *ms_total, int64_t *n_launches);
+
+int abm_sir_destroy(abm_sir *s);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *abm_last_error(void);
 

@@ -105,6 +105,17 @@ def lib():
         L.abm_mlp_num_params.restype = ctypes.c_size_t
         L.abm_mlp_num_params.argtypes = [_vp]
         L.abm_mlp_destroy.argtypes = [_vp]
+        L.abm_sir_workspace_bytes.restype = ctypes.c_size_t
+        L.abm_sir_workspace_bytes.argtypes = [ctypes.POINTER(SirParams), ctypes.c_int64, ctypes.c_int]
+        L.abm_sir_create.argtypes = [ctypes.POINTER(SirParams), ctypes.c_int64, _vp, _vp, ctypes.c_int, _vp,
+                                     ctypes.c_size_t, _vp, _vp]
+        L.abm_sir_step.argtypes = [_vp, ctypes.c_int, _vp]
+        L.abm_sir_query.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64]
+        L.abm_sir_counts.argtypes = [_vp, _i64p, _i64p]
+        L.abm_sir_grid.argtypes = [_vp, _i64p, ctypes.POINTER(ctypes.c_double)]
+        L.abm_sir_set_timing.argtypes = [_vp, ctypes.c_int]
+        L.abm_sir_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
+        L.abm_sir_destroy.argtypes = [_vp]
         _lib = L
     return _lib
 
@@ -135,6 +146,92 @@ def _arg(a, dtype, on_device, keep):
     arr = np.ascontiguousarray(a, dtype=dtype)
     keep.append(arr)
     return arr.ctypes.data_as(ctypes.c_void_p)
+
+
+# SIR epidemiology (abm_sir_*): states, boundaries, query fields
+SUSCEPTIBLE, INFECTED, RECOVERED = 0, 1, 2
+TOROIDAL, CLOSED = 0, 1
+SIR_POS, SIR_STATE, SIR_UID = 0, 1, 2
+
+
+class SirParams(ctypes.Structure):
+    _fields_ = [
+        ("space", ctypes.c_double), ("radius", ctypes.c_double), ("infection_prob", ctypes.c_double),
+        ("recovery_prob", ctypes.c_double), ("speed", ctypes.c_double), ("boundary", ctypes.c_int32),
+        ("sim_id", ctypes.c_uint32), ("seed", ctypes.c_uint64),
+    ]
+
+
+def sir_params(space, radius, infection_prob, recovery_prob, speed, boundary=TOROIDAL, seed=0, sim_id=0):
+    return SirParams(float(space), float(radius), float(infection_prob), float(recovery_prob), float(speed),
+                     int(boundary), int(sim_id), int(seed))
+
+
+class Sir:
+    """One SIR population (the abm_sir_* entry points); pos: host n x 3
+    float64 in [0, space], state: host uint8 (0, 1, 2)."""
+
+    def __init__(self, p, pos, state, hist_cap=1024, stream=None):
+        torch = _torch()
+        L = lib()
+        self._params = p
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        state = np.ascontiguousarray(state, dtype=np.uint8)
+        self.n = int(pos.shape[0])
+        nbytes = L.abm_sir_workspace_bytes(ctypes.byref(p), self.n, int(hist_cap))
+        if nbytes == 0:
+            raise AbmError(ERR_ARG, "invalid SIR parameters or sizes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self._stream = _stream_handle(stream)
+        h = ctypes.c_void_p()
+        check(L.abm_sir_create(ctypes.byref(p), self.n, pos.ctypes.data_as(ctypes.c_void_p),
+                               state.ctypes.data_as(ctypes.c_void_p), int(hist_cap),
+                               ctypes.c_void_p(self.workspace.data_ptr()), nbytes + 256, self._stream,
+                               ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n_iter=1, counts=False):
+        """Advance n_iter iterations; with counts=True returns the (n_iter, 3)
+        numbers of susceptible, infected and recovered persons after each."""
+        out = np.zeros((max(int(n_iter), 1), 3), dtype=np.int64) if counts else None
+        check(lib().abm_sir_step(self.h, int(n_iter), out.ctypes.data_as(ctypes.c_void_p) if counts else None))
+        return out[: int(n_iter)] if counts else None
+
+    def query(self, field):
+        dt, width = {SIR_POS: (np.float64, 3), SIR_STATE: (np.uint8, 1), SIR_UID: (np.uint32, 1)}[field]
+        out = np.zeros((max(self.n, 1), width) if width > 1 else max(self.n, 1), dtype=dt)
+        check(lib().abm_sir_query(self.h, int(field), out.ctypes.data_as(ctypes.c_void_p), 0, max(self.n, 1)))
+        return out[: self.n]
+
+    def counts(self):
+        it = ctypes.c_int64(0)
+        c = np.zeros(3, dtype=np.int64)
+        check(lib().abm_sir_counts(self.h, ctypes.byref(it), c.ctypes.data_as(_i64p)))
+        return it.value, c
+
+    def grid(self):
+        dims = ctypes.c_int64(0)
+        lb = ctypes.c_double(0.0)
+        check(lib().abm_sir_grid(self.h, ctypes.byref(dims), ctypes.byref(lb)))
+        return dims.value, lb.value
+
+    def set_timing(self, on):
+        check(lib().abm_sir_set_timing(self.h, int(bool(on))))
+
+    def kernel_time(self):
+        ms = ctypes.c_double(0.0)
+        k = ctypes.c_int64(0)
+        check(lib().abm_sir_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.abm_sir_destroy(h)
+            self.h = None
+
+    def close(self):
+        self.__del__()
 
 
 class Batch:

@@ -1,0 +1,680 @@
+// abm_sir.hip -- SIR epidemiology on the GPU (Sec 4.6.3, Algorithms 3-5,
+// Table 4.3) with toroidal or closed space boundaries (Sec 4.4.11).
+//
+// Persons live in a cubic space [0, S]^3.  Their state is kept sorted by the
+// box of a uniform grid whose box length Lb is at least twice the infection
+// radius, so that every person within the radius of a point lies in the
+// point's own box or in the one neighbour box per axis on the side of the
+// box's half the point is in: eight boxes, not 27.  One iteration:
+//   k_sir_behave   per person, in storage order: infection (Algorithm 3) from
+//                  the start-of-iteration states of the eight boxes, recovery
+//                  (Algorithm 4), random step and boundary (Algorithm 5);
+//                  writes the new person in the same order to the temporary
+//                  arrays with the box of its new position and its rank in
+//                  that box (one atomic on the box count); counts per state
+//   k_sir_tiles / k_sir_top / k_sir_apply
+//                  exclusive scan of the box counts into box starts (and the
+//                  counts cleared for the next iteration)
+//   k_sir_scatter  every person to its slot: box start + rank
+//   k_sir_end      iteration counter and the next history slot
+// All of it is captured once into a HIP graph and replayed.  The order of
+// persons inside a box depends on the order of the atomics, but nothing
+// computed depends on it (the infection test is an OR over neighbours, every
+// draw is keyed by the person's uid), so results are deterministic.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "abm_device.h"
+
+namespace abm {
+namespace sir {
+
+constexpr uint32_t kTagInfection = 0x494e4645u;  // 'INFE'
+constexpr uint32_t kTagRecovery = 0x5245434fu;   // 'RECO'
+constexpr uint32_t kTagMove = 0x4d4f5645u;       // 'MOVE'
+constexpr uint8_t kSusceptible = ABM_SIR_SUSCEPTIBLE, kInfected = ABM_SIR_INFECTED, kRecovered = ABM_SIR_RECOVERED;
+constexpr int kThreads = 256;
+constexpr int kScanTile = 4096;     // boxes per scan tile: 256 threads x 16
+constexpr int kTopThreads = 1024;   // the single work group of the tile-offset scan
+constexpr int64_t kMaxDims = 1600;  // boxes per axis: D^3 < 2^32
+constexpr int kBehaveGrid = 4096;   // persistent work groups of the person kernel (16 per CU)
+
+struct alignas(64) Ctl {
+    int64_t iter;
+};
+
+// Device view of one population (passed by value to every kernel).
+struct Dev {
+    int64_t n, nbox, ntiles;
+    int32_t D, boundary, hist_cap, pad;
+    double S, halfS, Lb, halfLb, r2, p_inf, p_rec, speed;
+    uint64_t seed;
+    uint32_t sim_id;
+    Ctl *ctl;
+    double *pos;                 // storage order (sorted by box): x block, y block, z block
+    double *tmp;                 // after the behaviours, in the same order as pos
+    uint8_t *state, *state_t;
+    uint32_t *uid, *uid_t;
+    uint32_t *key, *rank;        // box of the new position, rank within it
+    uint32_t *count;             // nbox
+    uint32_t *start;             // nbox + 1
+    uint32_t *tile;              // ntiles: tile sums, then their exclusive prefix
+    unsigned long long *hist;    // hist_cap x 3
+};
+
+// Box coordinate along one axis of a coordinate in [0, S] (FP64 division).
+__device__ inline int box_axis(const Dev &d, double v) {
+    double q = floor(v / d.Lb);
+    int b = (int)q;
+    return b < 0 ? 0 : (b >= d.D ? d.D - 1 : b);
+}
+
+// Offset from a to b along one axis, minimum image on the torus.
+__device__ inline double axis_offset(const Dev &d, double a, double b) {
+#pragma clang fp contract(off)
+    double o = b - a;
+    if (d.boundary == ABM_BOUNDARY_TOROIDAL) {
+        if (o > d.halfS) o -= d.S;
+        else if (o < -d.halfS) o += d.S;
+    }
+    return o;
+}
+
+// A coordinate after the step (Sec 4.4.11).  Toroidal: the fmod wrap of
+// Algorithm 5; for |v| < 2S (the step is shorter than S) it reduces exactly
+// to one subtraction or addition of S (Sterbenz: S <= v < 2S makes v - S
+// exact, and fmod returns v itself for -S < v < S).  Closed: clamped.
+__device__ inline double bound(const Dev &d, double v) {
+#pragma clang fp contract(off)
+    if (d.boundary == ABM_BOUNDARY_CLOSED) return v < 0.0 ? 0.0 : (v > d.S ? d.S : v);
+    if (v >= d.S) return v - d.S;
+    if (v < 0.0) return d.S + v;
+    return v;
+}
+
+// Algorithm 3's neighbourhood test: an infected person strictly within the
+// radius of (x, y, z) in the start-of-iteration state.  Per axis the own box
+// and the neighbour box on the side of the point's half of it: Lb >= 2 r (1 +
+// 2^-20), so the far side is out of reach with a margin far above the
+// rounding of the box coordinate.
+__device__ bool infected_near(const Dev &d, double x, double y, double z) {
+#pragma clang fp contract(off)
+    const double c[3] = {x, y, z};
+    int nb[3][2], cnt[3];
+    for (int a = 0; a < 3; ++a) {
+        const int b = box_axis(d, c[a]);
+        const double o = c[a] - (double)b * d.Lb;
+        int other = b + (o < d.halfLb ? -1 : 1);
+        bool ok;
+        if (d.boundary == ABM_BOUNDARY_TOROIDAL) {
+            other = other < 0 ? other + d.D : (other >= d.D ? other - d.D : other);
+            ok = other != b;
+        } else {
+            ok = other >= 0 && other < d.D;
+        }
+        nb[a][0] = b;
+        nb[a][1] = other;
+        cnt[a] = ok ? 2 : 1;
+    }
+    const int64_t n = d.n;
+    for (int iz = 0; iz < cnt[2]; ++iz)
+        for (int iy = 0; iy < cnt[1]; ++iy)
+            for (int ix = 0; ix < cnt[0]; ++ix) {
+                const uint32_t box =
+                    (uint32_t)nb[0][ix] + (uint32_t)d.D * ((uint32_t)nb[1][iy] + (uint32_t)d.D * (uint32_t)nb[2][iz]);
+                const uint32_t j0 = d.start[box], j1 = d.start[box + 1];
+                for (uint32_t j = j0; j < j1; ++j) {
+                    if (d.state[j] != kInfected) continue;
+                    const double dx = axis_offset(d, x, d.pos[j]);
+                    const double dy = axis_offset(d, y, d.pos[n + j]);
+                    const double dz = axis_offset(d, z, d.pos[2 * n + j]);
+                    if (fma(dz, dz, fma(dy, dy, dx * dx)) < d.r2) return true;
+                }
+            }
+    return false;
+}
+
+__device__ inline uint32_t box_key(const Dev &d, double x, double y, double z) {
+    return (uint32_t)box_axis(d, x) + (uint32_t)d.D * ((uint32_t)box_axis(d, y) + (uint32_t)d.D * (uint32_t)box_axis(d, z));
+}
+
+// Adds this wave's persons per state to the work group's counters.
+__device__ inline void count_states(bool active, uint8_t st, uint32_t *cnt) {
+    const uint64_t m0 = __ballot(active && st == kSusceptible);
+    const uint64_t m1 = __ballot(active && st == kInfected);
+    const uint64_t m2 = __ballot(active && st == kRecovered);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&cnt[0], (uint32_t)__popcll(m0));
+        atomicAdd(&cnt[1], (uint32_t)__popcll(m1));
+        atomicAdd(&cnt[2], (uint32_t)__popcll(m2));
+    }
+}
+
+// One iteration of the behaviours of every person (Algorithms 3, 4, 5).
+__global__ __launch_bounds__(kThreads) void k_sir_behave(Dev d) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t cnt[3];
+    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t iter = d.ctl->iter;
+    const int64_t n = d.n;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < n; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool active = i < n;
+        uint8_t st = 0;
+        if (active) {
+            const double x = d.pos[i], y = d.pos[n + i], z = d.pos[2 * n + i];
+            st = d.state[i];
+            const uint32_t u = d.uid[i];
+            uint32_t c[4];
+            if (st == kSusceptible) {
+                agent_draw(d.seed, kTagInfection, d.sim_id, u, (uint64_t)iter, c);
+                if (uniform_open(c[0]) < d.p_inf && infected_near(d, x, y, z)) st = kInfected;
+            }
+            if (st == kInfected) {
+                agent_draw(d.seed, kTagRecovery, d.sim_id, u, (uint64_t)iter, c);
+                if (uniform_open(c[0]) < d.p_rec) st = kRecovered;
+            }
+            agent_draw(d.seed, kTagMove, d.sim_id, u, (uint64_t)iter, c);
+            double v[3];
+            for (int a = 0; a < 3; ++a) v[a] = 2.0 * uniform_open(c[a]) - 1.0;
+            const double norm = sqrt(fma(v[2], v[2], fma(v[1], v[1], v[0] * v[0])));
+            const double nx = bound(d, x + (v[0] / norm) * d.speed);
+            const double ny = bound(d, y + (v[1] / norm) * d.speed);
+            const double nz = bound(d, z + (v[2] / norm) * d.speed);
+            const uint32_t k = box_key(d, nx, ny, nz);
+            d.rank[i] = atomicAdd(&d.count[k], 1u);
+            d.key[i] = k;
+            d.tmp[i] = nx;
+            d.tmp[n + i] = ny;
+            d.tmp[2 * n + i] = nz;
+            d.state_t[i] = st;
+            d.uid_t[i] = u;
+        }
+        count_states(active, st, cnt);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3 && cnt[threadIdx.x])
+        atomicAdd(&d.hist[(iter % d.hist_cap) * 3 + threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+}
+
+// Box and rank of every person of the temporary arrays (initial sort).
+__global__ __launch_bounds__(kThreads) void k_sir_bin(Dev d) {
+    const int64_t n = d.n;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const uint32_t k = box_key(d, d.tmp[i], d.tmp[n + i], d.tmp[2 * n + i]);
+        d.rank[i] = atomicAdd(&d.count[k], 1u);
+        d.key[i] = k;
+    }
+}
+
+// Sum of the box counts of one scan tile.
+__global__ __launch_bounds__(kThreads) void k_sir_tiles(Dev d) {
+    __shared__ uint32_t sh[kThreads / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
+    uint32_t s = 0;
+    for (int k = 0; k < 16; ++k)
+        if (b0 + k < d.nbox) s += d.count[b0 + k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) d.tile[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Exclusive prefix of the tile sums, in place (one work group).
+__global__ __launch_bounds__(kTopThreads) void k_sir_top(Dev d) {
+    __shared__ uint32_t sh[kTopThreads / 64];
+    __shared__ uint32_t carry_sh;
+    if (threadIdx.x == 0) carry_sh = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int64_t base = 0; base < d.ntiles; base += kTopThreads) {
+        const int64_t t = base + threadIdx.x;
+        const uint32_t v = t < d.ntiles ? d.tile[t] : 0u;
+        uint32_t x = v;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) sh[wid] = x;
+        __syncthreads();
+        uint32_t wpre = 0, total = 0;
+        for (int w = 0; w < kTopThreads / 64; ++w) {
+            if (w < wid) wpre += sh[w];
+            total += sh[w];
+        }
+        const uint32_t carry = carry_sh;
+        if (t < d.ntiles) d.tile[t] = carry + wpre + x - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_sh = carry + total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.start[d.nbox] = (uint32_t)d.n;
+}
+
+// Box starts of one tile (its offset plus the exclusive prefix of its
+// counts); the counts are cleared for the next binning.
+__global__ __launch_bounds__(kThreads) void k_sir_apply(Dev d) {
+    __shared__ uint32_t sh[kThreads / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
+    uint32_t c[16];
+    uint32_t s = 0;
+    for (int k = 0; k < 16; ++k) {
+        c[k] = b0 + k < d.nbox ? d.count[b0 + k] : 0u;
+        s += c[k];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = s;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    uint32_t wpre = 0;
+    for (int w = 0; w < wid; ++w) wpre += sh[w];
+    uint32_t run = d.tile[blockIdx.x] + wpre + x - s;
+    for (int k = 0; k < 16; ++k) {
+        if (b0 + k < d.nbox) {
+            d.start[b0 + k] = run;
+            d.count[b0 + k] = 0u;
+        }
+        run += c[k];
+    }
+}
+
+// Every person to its slot in box order.
+__global__ __launch_bounds__(kThreads) void k_sir_scatter(Dev d) {
+    const int64_t n = d.n;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const int64_t j = (int64_t)d.start[d.key[i]] + d.rank[i];
+        d.pos[j] = d.tmp[i];
+        d.pos[n + j] = d.tmp[n + i];
+        d.pos[2 * n + j] = d.tmp[2 * n + i];
+        d.state[j] = d.state_t[i];
+        d.uid[j] = d.uid_t[i];
+    }
+}
+
+__global__ void k_sir_end(Dev d) {
+    const int64_t next = d.ctl->iter + 1;
+    unsigned long long *h = d.hist + (next % d.hist_cap) * 3;
+    h[0] = h[1] = h[2] = 0ull;
+    d.ctl->iter = next;
+}
+
+// Interleaved n x 3 positions from the coordinate blocks (src) into dst.
+__global__ void k_sir_interleave(const double *src, double *dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        dst[3 * i] = src[i];
+        dst[3 * i + 1] = src[n + i];
+        dst[3 * i + 2] = src[2 * n + i];
+    }
+}
+__global__ void k_sir_deinterleave(const double *src, double *dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        dst[i] = src[3 * i];
+        dst[n + i] = src[3 * i + 1];
+        dst[2 * n + i] = src[3 * i + 2];
+    }
+}
+__global__ void k_sir_iota(uint32_t *u, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        u[i] = (uint32_t)i;
+}
+// Fill with a kernel (not a memset node: the graph replays it).
+__global__ void k_sir_zero(uint32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+inline int grid_for(int64_t n, int cap) {
+    int64_t g = (n + kThreads - 1) / kThreads;
+    return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+// The grid scan and the scatter (shared by creation and every iteration).
+void launch_sort(const Dev &d, hipStream_t s) {
+    hipLaunchKernelGGL(k_sir_tiles, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sir_top, dim3(1), dim3(kTopThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sir_apply, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d);
+    if (d.n > 0) hipLaunchKernelGGL(k_sir_scatter, dim3(grid_for(d.n, 65536)), dim3(kThreads), 0, s, d);
+}
+
+void launch_behave(const Dev &d, hipStream_t s) {
+    if (d.n > 0) hipLaunchKernelGGL(k_sir_behave, dim3(grid_for(d.n, kBehaveGrid)), dim3(kThreads), 0, s, d);
+}
+
+void launch_rest(const Dev &d, hipStream_t s) {
+    launch_sort(d, s);
+    hipLaunchKernelGGL(k_sir_end, dim3(1), dim3(1), 0, s, d);
+}
+
+// ---------------------------------------------------------------- layout
+struct Carver {
+    size_t off = 0;
+    template <class T>
+    size_t take(size_t count) {
+        size_t o = (off + 255) & ~size_t(255);
+        off = o + count * sizeof(T);
+        return o;
+    }
+};
+
+struct Layout {
+    size_t ctl, pos, tmp, state, state_t, uid, uid_t, key, rank, count, start, tile, hist, total;
+};
+
+bool geometry(const abm_sir_params &p, int64_t &D, double &Lb) {
+    if (!(p.space > 0.0) || !isfinite(p.space) || !(p.radius > 0.0) || !isfinite(p.radius)) return false;
+    // boxes of at least twice the radius, with a relative margin of 2^-20
+    double q = floor(p.space / (2.0 * p.radius * (1.0 + 0x1.0p-20)));
+    D = q < 1.0 ? 1 : (q > (double)kMaxDims ? kMaxDims : (int64_t)q);
+    Lb = p.space / (double)D;
+    return Lb >= 2.0 * p.radius;
+}
+
+bool params_ok(const abm_sir_params &p) {
+    int64_t D;
+    double Lb;
+    if (!geometry(p, D, Lb)) return false;
+    if (!(p.infection_prob >= 0.0 && p.infection_prob <= 1.0)) return false;
+    if (!(p.recovery_prob >= 0.0 && p.recovery_prob <= 1.0)) return false;
+    if (!(p.speed >= 0.0) || !isfinite(p.speed)) return false;
+    if (p.boundary != ABM_BOUNDARY_TOROIDAL && p.boundary != ABM_BOUNDARY_CLOSED) return false;
+    // the toroidal wrap reduces to one subtraction or addition of S only for steps shorter than S
+    if (p.boundary == ABM_BOUNDARY_TOROIDAL && !(p.speed < p.space)) return false;
+    return true;
+}
+
+bool make_layout(const abm_sir_params &p, int64_t n, int hist_cap, Layout &L, int64_t &nbox, int64_t &ntiles) {
+    if (n < 0 || n >= ((int64_t)1 << 31) || hist_cap < 2 || hist_cap > (1 << 24) || !params_ok(p)) return false;
+    int64_t D;
+    double Lb;
+    geometry(p, D, Lb);
+    nbox = D * D * D;
+    ntiles = (nbox + kScanTile - 1) / kScanTile;
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    Carver c;
+    L.ctl = c.take<Ctl>(1);
+    L.pos = c.take<double>(3 * N);
+    L.tmp = c.take<double>(3 * N);
+    L.state = c.take<uint8_t>(N);
+    L.state_t = c.take<uint8_t>(N);
+    L.uid = c.take<uint32_t>(N);
+    L.uid_t = c.take<uint32_t>(N);
+    L.key = c.take<uint32_t>(N);
+    L.rank = c.take<uint32_t>(N);
+    L.count = c.take<uint32_t>((size_t)nbox + 16);
+    L.start = c.take<uint32_t>((size_t)nbox + 16);
+    L.tile = c.take<uint32_t>((size_t)ntiles);
+    L.hist = c.take<unsigned long long>((size_t)hist_cap * 3);
+    L.total = c.off + 256;
+    return true;
+}
+
+}  // namespace sir
+}  // namespace abm
+
+using abm::set_error;
+using abm::clear_error;
+namespace sirk = abm::sir;
+
+struct abm_sir {
+    sirk::Dev d;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t exec[3] = {};  // 0: a whole iteration; 1: the person kernel; 2: the rest
+    int64_t iter = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    double ms_total = 0.0;
+    int64_t n_timed = 0;
+};
+
+#define SIRCHK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t _e = (expr);                                                       \
+        if (_e != hipSuccess) return set_error(ABM_ERR_HIP, hipGetErrorString(_e));   \
+    } while (0)
+
+static int capture(abm_sir *s, int part) {
+    if (s->exec[part]) return ABM_OK;
+    if (!s->cap_stream) SIRCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    SIRCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    if (part == 0 || part == 1) sirk::launch_behave(s->d, s->cap_stream);
+    if (part == 0 || part == 2) sirk::launch_rest(s->d, s->cap_stream);
+    hipGraph_t g;
+    hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+    if (e != hipSuccess) return set_error(ABM_ERR_HIP, hipGetErrorString(e));
+    e = hipGraphInstantiate(&s->exec[part], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);  // the instantiated graph no longer needs its template
+    if (e != hipSuccess) return set_error(ABM_ERR_HIP, hipGetErrorString(e));
+    return ABM_OK;
+}
+
+extern "C" size_t abm_sir_workspace_bytes(const abm_sir_params *p, int64_t n, int hist_cap) {
+    if (!p) return 0;
+    sirk::Layout L;
+    int64_t nbox, ntiles;
+    if (!sirk::make_layout(*p, n, hist_cap, L, nbox, ntiles)) return 0;
+    return L.total;
+}
+
+extern "C" int abm_sir_create(const abm_sir_params *p, int64_t n, const double *pos, const uint8_t *state,
+                              int hist_cap, void *workspace, size_t ws_bytes, void *hip_stream, abm_sir **out) {
+    clear_error();
+    if (!p || !out || !workspace || (n > 0 && (!pos || !state))) return set_error(ABM_ERR_ARG, "null argument");
+    *out = nullptr;
+    sirk::Layout L;
+    int64_t nbox, ntiles;
+    if (!sirk::make_layout(*p, n, hist_cap, L, nbox, ntiles))
+        return set_error(ABM_ERR_ARG, "bad SIR parameters, person count or history length");
+    if (ws_bytes < L.total) return set_error(ABM_ERR_ARG, "workspace too small");
+    for (int64_t i = 0; i < 3 * n; ++i) {
+        if (!isfinite(pos[i])) return set_error(ABM_ERR_NONFINITE, "non-finite position");
+        if (pos[i] < 0.0 || pos[i] > p->space) return set_error(ABM_ERR_ARG, "position outside [0, space]");
+    }
+    int64_t counts[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; ++i) {
+        if (state[i] > ABM_SIR_RECOVERED) return set_error(ABM_ERR_ARG, "state outside 0..2");
+        counts[state[i]] += 1;
+    }
+    abm_sir *s = new (std::nothrow) abm_sir();
+    if (!s) return set_error(ABM_ERR_ARG, "out of host memory");
+    int64_t D;
+    double Lb;
+    sirk::geometry(*p, D, Lb);
+    char *base = (char *)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    sirk::Dev &d = s->d;
+    d.n = n;
+    d.nbox = nbox;
+    d.ntiles = ntiles;
+    d.D = (int32_t)D;
+    d.boundary = p->boundary;
+    d.hist_cap = hist_cap;
+    d.S = p->space;
+    d.halfS = 0.5 * p->space;
+    d.Lb = Lb;
+    d.halfLb = 0.5 * Lb;
+    d.r2 = p->radius * p->radius;
+    d.p_inf = p->infection_prob;
+    d.p_rec = p->recovery_prob;
+    d.speed = p->speed;
+    d.seed = p->seed;
+    d.sim_id = p->sim_id;
+    d.ctl = (sirk::Ctl *)(base + L.ctl);
+    d.pos = (double *)(base + L.pos);
+    d.tmp = (double *)(base + L.tmp);
+    d.state = (uint8_t *)(base + L.state);
+    d.state_t = (uint8_t *)(base + L.state_t);
+    d.uid = (uint32_t *)(base + L.uid);
+    d.uid_t = (uint32_t *)(base + L.uid_t);
+    d.key = (uint32_t *)(base + L.key);
+    d.rank = (uint32_t *)(base + L.rank);
+    d.count = (uint32_t *)(base + L.count);
+    d.start = (uint32_t *)(base + L.start);
+    d.tile = (uint32_t *)(base + L.tile);
+    d.hist = (unsigned long long *)(base + L.hist);
+    s->stream = (hipStream_t)hip_stream;
+    hipStream_t st = s->stream;
+    auto undo = [&](int rc) {
+        delete s;
+        return rc;
+    };
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        // positions: interleaved upload into pos, de-interleaved into tmp
+        e = hipMemcpyAsync(d.pos, pos, sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d.state_t, state, (size_t)n, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return undo(set_error(ABM_ERR_HIP, hipGetErrorString(e)));
+        hipLaunchKernelGGL(sirk::k_sir_deinterleave, dim3(sirk::grid_for(n, 65536)), dim3(sirk::kThreads), 0, st, d.pos, d.tmp, n);
+        hipLaunchKernelGGL(sirk::k_sir_iota, dim3(sirk::grid_for(n, 65536)), dim3(sirk::kThreads), 0, st, d.uid_t, n);
+    }
+    hipLaunchKernelGGL(sirk::k_sir_zero, dim3(sirk::grid_for(nbox, 65536)), dim3(sirk::kThreads), 0, st, d.count, nbox);
+    hipLaunchKernelGGL(sirk::k_sir_zero, dim3(sirk::grid_for(2 * (int64_t)hist_cap * 3, 65536)), dim3(sirk::kThreads), 0, st,
+                       (uint32_t *)d.hist, 2 * (int64_t)hist_cap * 3);
+    hipLaunchKernelGGL(sirk::k_sir_zero, dim3(1), dim3(64), 0, st, (uint32_t *)d.ctl, (int64_t)(sizeof(sirk::Ctl) / 4));
+    if (n > 0) hipLaunchKernelGGL(sirk::k_sir_bin, dim3(sirk::grid_for(n, 65536)), dim3(sirk::kThreads), 0, st, d);
+    sirk::launch_sort(d, st);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return undo(set_error(ABM_ERR_HIP, hipGetErrorString(e)));
+    *out = s;
+    return ABM_OK;
+}
+
+extern "C" int abm_sir_step(abm_sir *s, int n_iter, int64_t *counts) {
+    clear_error();
+    if (!s || n_iter < 0) return set_error(ABM_ERR_ARG, "bad handle or iteration count");
+    if (n_iter == 0) return ABM_OK;
+    int rc = s->timing ? capture(s, 1) : capture(s, 0);
+    if (!rc && s->timing) rc = capture(s, 2);
+    if (rc) return rc;
+    const int cap = s->d.hist_cap;
+    std::vector<unsigned long long> h;
+    for (int done = 0; done < n_iter;) {
+        // fewer iterations than history slots between reads of the counts (the
+        // end of an iteration clears the slot of the next one)
+        const int chunk = counts ? std::min(cap - 1, n_iter - done) : n_iter - done;
+        if (s->timing) {
+            while ((int)s->ev.size() < 2 * chunk) {
+                hipEvent_t e;
+                SIRCHK(hipEventCreate(&e));
+                s->ev.push_back(e);
+            }
+            for (int it = 0; it < chunk; ++it) {
+                SIRCHK(hipEventRecord(s->ev[2 * it], s->stream));
+                SIRCHK(hipGraphLaunch(s->exec[1], s->stream));
+                SIRCHK(hipEventRecord(s->ev[2 * it + 1], s->stream));
+                SIRCHK(hipGraphLaunch(s->exec[2], s->stream));
+            }
+            SIRCHK(hipStreamSynchronize(s->stream));
+            for (int it = 0; it < chunk; ++it) {
+                float ms = 0.0f;
+                SIRCHK(hipEventElapsedTime(&ms, s->ev[2 * it], s->ev[2 * it + 1]));
+                s->ms_total += ms;
+            }
+            s->n_timed += chunk;
+        } else {
+            for (int it = 0; it < chunk; ++it) SIRCHK(hipGraphLaunch(s->exec[0], s->stream));
+        }
+        if (counts) {
+            h.resize((size_t)cap * 3);
+            SIRCHK(hipMemcpyAsync(h.data(), s->d.hist, sizeof(unsigned long long) * 3 * (size_t)cap,
+                                  hipMemcpyDeviceToHost, s->stream));
+            SIRCHK(hipStreamSynchronize(s->stream));
+            for (int it = 0; it < chunk; ++it) {
+                const int64_t slot = (s->iter + it) % cap;
+                for (int k = 0; k < 3; ++k) counts[3 * (int64_t)(done + it) + k] = (int64_t)h[3 * slot + k];
+            }
+        }
+        s->iter += chunk;
+        done += chunk;
+    }
+    SIRCHK(hipGetLastError());
+    return ABM_OK;
+}
+
+extern "C" int abm_sir_query(abm_sir *s, int field, void *dst, int dst_on_device, int64_t cap) {
+    clear_error();
+    if (!s || !dst) return set_error(ABM_ERR_ARG, "null argument");
+    const int64_t n = s->d.n;
+    if (cap < n) return set_error(ABM_ERR_ARG, "destination holds fewer rows than persons");
+    if (n == 0) return ABM_OK;
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    hipStream_t st = s->stream;
+    if (field == ABM_SIR_POS) {
+        // the temporary arrays are free between iterations
+        double *src = s->d.tmp;
+        hipLaunchKernelGGL(sirk::k_sir_interleave, dim3(sirk::grid_for(n, 65536)), dim3(sirk::kThreads), 0, st, s->d.pos, src, n);
+        SIRCHK(hipMemcpyAsync(dst, src, sizeof(double) * 3 * (size_t)n, kind, st));
+    } else if (field == ABM_SIR_STATE) {
+        SIRCHK(hipMemcpyAsync(dst, s->d.state, (size_t)n, kind, st));
+    } else if (field == ABM_SIR_UID) {
+        SIRCHK(hipMemcpyAsync(dst, s->d.uid, sizeof(uint32_t) * (size_t)n, kind, st));
+    } else {
+        return set_error(ABM_ERR_ARG, "unknown field");
+    }
+    SIRCHK(hipGetLastError());
+    SIRCHK(hipStreamSynchronize(st));
+    return ABM_OK;
+}
+
+extern "C" int abm_sir_counts(abm_sir *s, int64_t *iteration, int64_t counts[3]) {
+    clear_error();
+    if (!s || !iteration || !counts) return set_error(ABM_ERR_ARG, "null argument");
+    *iteration = s->iter;
+    counts[0] = counts[1] = counts[2] = 0;
+    const int64_t n = s->d.n;
+    if (n == 0) return ABM_OK;
+    std::vector<uint8_t> st((size_t)n);
+    SIRCHK(hipMemcpyAsync(st.data(), s->d.state, (size_t)n, hipMemcpyDeviceToHost, s->stream));
+    SIRCHK(hipStreamSynchronize(s->stream));
+    for (uint8_t v : st) counts[v < 3 ? v : 2] += 1;
+    return ABM_OK;
+}
+
+extern "C" int abm_sir_grid(abm_sir *s, int64_t *dims, double *box_len) {
+    clear_error();
+    if (!s || !dims || !box_len) return set_error(ABM_ERR_ARG, "null argument");
+    *dims = s->d.D;
+    *box_len = s->d.Lb;
+    return ABM_OK;
+}
+
+extern "C" int abm_sir_set_timing(abm_sir *s, int on) {
+    clear_error();
+    if (!s) return set_error(ABM_ERR_ARG, "null handle");
+    s->timing = on != 0;
+    return ABM_OK;
+}
+
+extern "C" int abm_sir_kernel_time(abm_sir *s, double *ms_total, int64_t *n_launches) {
+    clear_error();
+    if (!s || !ms_total || !n_launches) return set_error(ABM_ERR_ARG, "null argument");
+    *ms_total = s->ms_total;
+    *n_launches = s->n_timed;
+    s->ms_total = 0.0;
+    s->n_timed = 0;
+    return ABM_OK;
+}
+
+extern "C" int abm_sir_destroy(abm_sir *s) {
+    clear_error();
+    if (!s) return ABM_OK;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);  // teardown: nothing to recover
+    for (hipGraphExec_t &g : s->exec)
+        if (g) (void)hipGraphExecDestroy(g);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    delete s;
+    return ABM_OK;
+}
