@@ -7,7 +7,10 @@ gamma = 1, adherence 1.8, mass 0.1, cap 3 um, Morton re-sort every 10
 iterations; FP32 forces, FP64 positions.  ``--workload relaxed`` runs the
 pre-relaxed lattice (most agents static, static skip on); ``spheroid`` grows
 one tumour spheroid from 1,000 cells to about 5e6; ``sweep`` and
-``surrogate`` time the batched parameter sweep and the surrogate screening.
+``surrogate`` time the batched parameter sweep and the surrogate screening;
+``apoptosis`` adds the Brownian step and apoptosis of Algorithm 2; ``sir``
+runs Table 4.5's large-scale measles epidemic (1.01e7 persons, 1,000
+iterations).
 
 A step is one iteration of the whole hot path (grid build, force sweep,
 displacement, static flags, re-sort when due).  Prints one JSON line with the
@@ -314,6 +317,93 @@ def bench_apoptosis(args):
     print(json.dumps(out), flush=True)
 
 
+# Algorithmic bytes of the SIR person kernel per person: position 24, state 1
+# and uid 4 read; new position 24, state 1, uid 4, box key 4 and rank 4
+# written; the box count's atomic read and write 8.
+SIR_BEHAVE_BYTES = 29 + 37 + 8
+
+
+def bench_sir(args):
+    """Table 4.5's large-scale measles run: Table 4.3's measles model at
+    `sir_scale` times the persons and the same density (default 5,000:
+    1e7 susceptible + 1e5 infected in a 1,710 m torus), `steps` iterations
+    (the thesis runs 1,000)."""
+    import torch
+    from paper_2503_10796_amd import abm, inputs
+    abm.lib()
+    cfg = inputs.scaled_sir(inputs.SIR_MEASLES, args.sir_scale)
+    boundary = abm.CLOSED if args.sir_boundary == "closed" else abm.TOROIDAL
+    t_gen = time.perf_counter()
+    pos, st = inputs.sir_population(cfg["n_susceptible"], cfg["n_infected"], cfg["space"], seed=12)
+    n = pos.shape[0]
+    p = abm.sir_params(cfg["space"], cfg["radius"], cfg["infection_prob"], cfg["recovery_prob"], cfg["speed"],
+                       boundary=boundary, seed=12)
+    g = abm.Sir(p, pos, st, hist_cap=1024)
+    del pos, st
+    dims, box_len = g.grid()
+    log(f"[bench] sir: {n} persons in a {cfg['space']:.1f} m cube, grid {dims}^3 boxes of {box_len:.3f} m, "
+        f"set up in {time.perf_counter() - t_gen:.1f} s")
+    g.set_timing(True)
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+    g.kernel_time()
+    t0 = time.perf_counter()
+    g.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_ms, k_n = g.kernel_time()
+    it, counts = g.counts()
+    log(f"[bench] sir: {args.steps} iterations in {elapsed:.3f} s; counts after iteration {it}: {counts.tolist()}")
+    nbox = dims ** 3
+    k_avg_s = k_ms / max(k_n, 1) / 1e3
+    achieved = n * SIR_BEHAVE_BYTES / k_avg_s / 1e9
+    out = {
+        "metric": "SIR epidemiology (Algorithms 3-5): person updates/s",
+        "value": n * args.steps / elapsed, "unit": "person updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"measles SIR (Table 4.3) at {args.sir_scale} times the persons: "
+                               f"{cfg['n_susceptible']} susceptible + {cfg['n_infected']} infected uniform in a "
+                               f"{cfg['space']:.1f} m {args.sir_boundary} cube, radius {cfg['radius']} m, "
+                               f"infection probability {cfg['infection_prob']}, recovery probability "
+                               f"{cfg['recovery_prob']}, step {cfg['speed']} m; iterations "
+                               f"{args.warmup}..{args.warmup + args.steps}",
+                   "persons": n, "grid_boxes": nbox, "box_len_m": box_len,
+                   "counts_end": counts.tolist()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sir_behave",
+                     "kernel_ms": k_avg_s * 1e3, "algorithmic_bytes_per_launch": n * SIR_BEHAVE_BYTES},
+        "paper_context": "Table 4.5: 10,050,000 persons, 1,000 iterations in 59.19 s on 72 CPU cores "
+                         "(1.70e8 person updates/s)",
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host")
+        out["cpu_baseline"] = sir_cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+def sir_cpu_baseline(args):
+    """The SIR oracle (brute-force neighbourhoods, O(N^2) per iteration) on
+    the measles model at 10 times Table 4.3 (20,200 persons)."""
+    sys.path.insert(0, ROOT)
+    from oracle import sir as osir
+    from paper_2503_10796_amd import inputs
+    cfg = inputs.scaled_sir(inputs.SIR_MEASLES, args.sir_cpu_scale)
+    pos, st = inputs.sir_population(cfg["n_susceptible"], cfg["n_infected"], cfg["space"], seed=12)
+    op = osir.make_params(cfg["space"], cfg["radius"], cfg["infection_prob"], cfg["recovery_prob"], cfg["speed"],
+                          boundary=osir.CLOSED if args.sir_boundary == "closed" else osir.TOROIDAL, seed=12)
+    o = osir.OracleSIR(pos, st, op)
+    t0 = time.perf_counter()
+    o.step(args.sir_cpu_iters)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pos.shape[0] * args.sir_cpu_iters / dt, "unit": "person updates/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"the same model at {args.sir_cpu_scale} times Table 4.3 ({pos.shape[0]} persons), the first "
+                      f"{args.sir_cpu_iters} iterations, FP64, brute-force neighbourhoods (O(N^2): the rate falls "
+                      f"with N), OpenMP over persons, {dt:.1f} s"}
+
+
 def bench_surrogate(args):
     """Surrogate screening: train on windows of a batched sweep, judge on the
     simulated histograms of held-out parameter sets, time the screening."""
@@ -511,12 +601,18 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--agents", type=int, default=100_000_000)
-    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate", "spheroid", "apoptosis"],
+    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate", "spheroid", "apoptosis", "sir"],
                     default="uniform",
                     help="uniform / relaxed: mechanics at scale (the headline line); sweep: batched parameter "
                          "sweep vs the per-simulation path; surrogate: screening speedup and error; spheroid: "
                          "one tumour spheroid grown to about 5e6 agents; apoptosis: the uniform population with "
-                         "the Brownian step and apoptosis of Algorithm 2")
+                         "the Brownian step and apoptosis of Algorithm 2; sir: Table 4.5's large-scale measles "
+                         "epidemic (use --steps 1000)")
+    ap.add_argument("--sir-scale", type=int, default=5000,
+                    help="sir: persons as a multiple of Table 4.3's measles model (5000: 1.01e7 persons)")
+    ap.add_argument("--sir-boundary", choices=["toroidal", "closed"], default="toroidal")
+    ap.add_argument("--sir-cpu-scale", type=int, default=10)
+    ap.add_argument("--sir-cpu-iters", type=int, default=1000)
     ap.add_argument("--spheroid-scale", type=float, default=8.0,
                     help="spheroid: factor on the growth rates (8.0 reaches about 5e6 agents at 600 iterations)")
     ap.add_argument("--spheroid-iters", type=int, default=600, help="spheroid: iterations")
@@ -573,6 +669,9 @@ def main():
         return
     if args.workload == "apoptosis":
         bench_apoptosis(args)
+        return
+    if args.workload == "sir":
+        bench_sir(args)
         return
     from paper_2503_10796_amd import abm
 

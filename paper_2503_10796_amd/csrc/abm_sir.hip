@@ -40,7 +40,7 @@ constexpr uint32_t kTagRecovery = 0x5245434fu;   // 'RECO'
 constexpr uint32_t kTagMove = 0x4d4f5645u;       // 'MOVE'
 constexpr uint8_t kSusceptible = ABM_SIR_SUSCEPTIBLE, kInfected = ABM_SIR_INFECTED, kRecovered = ABM_SIR_RECOVERED;
 constexpr int kThreads = 256;
-constexpr int kScanTile = 4096;     // boxes per scan tile: 256 threads x 16
+constexpr int kScanTile = 4096;     // boxes per scan tile: 4 rounds of 256 threads x 4
 constexpr int kTopThreads = 1024;   // the single work group of the tile-offset scan
 constexpr int64_t kMaxDims = 1600;  // boxes per axis: D^3 < 2^32
 constexpr int kBehaveGrid = 4096;   // persistent work groups of the person kernel (16 per CU)
@@ -215,13 +215,22 @@ __global__ __launch_bounds__(kThreads) void k_sir_bin(Dev d) {
     }
 }
 
-// Sum of the box counts of one scan tile.
+// Sum of the box counts of one scan tile: four rounds of 1,024 boxes, each
+// thread loading four consecutive counts per round (16-byte loads).
 __global__ __launch_bounds__(kThreads) void k_sir_tiles(Dev d) {
     __shared__ uint32_t sh[kThreads / 64];
-    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
     uint32_t s = 0;
-    for (int k = 0; k < 16; ++k)
-        if (b0 + k < d.nbox) s += d.count[b0 + k];
+    for (int r = 0; r < kScanTile / (4 * kThreads); ++r) {
+        const int64_t b = t0 + (int64_t)r * 4 * kThreads + 4 * (int64_t)threadIdx.x;
+        if (b + 4 <= d.nbox) {
+            const uint4 c = *reinterpret_cast<const uint4 *>(d.count + b);
+            s += c.x + c.y + c.z + c.w;
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (b + k < d.nbox) s += d.count[b + k];
+        }
+    }
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -260,33 +269,38 @@ __global__ __launch_bounds__(kTopThreads) void k_sir_top(Dev d) {
 }
 
 // Box starts of one tile (its offset plus the exclusive prefix of its
-// counts); the counts are cleared for the next binning.
+// counts), in four rounds of 1,024 boxes with 16-byte loads and stores; the
+// counts are cleared for the next binning.
 __global__ __launch_bounds__(kThreads) void k_sir_apply(Dev d) {
     __shared__ uint32_t sh[kThreads / 64];
-    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * 16;
-    uint32_t c[16];
-    uint32_t s = 0;
-    for (int k = 0; k < 16; ++k) {
-        c[k] = b0 + k < d.nbox ? d.count[b0 + k] : 0u;
-        s += c[k];
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    uint32_t x = s;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) sh[wid] = x;
-    __syncthreads();
-    uint32_t wpre = 0;
-    for (int w = 0; w < wid; ++w) wpre += sh[w];
-    uint32_t run = d.tile[blockIdx.x] + wpre + x - s;
-    for (int k = 0; k < 16; ++k) {
-        if (b0 + k < d.nbox) {
-            d.start[b0 + k] = run;
-            d.count[b0 + k] = 0u;
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+    uint32_t carry = d.tile[blockIdx.x];
+    for (int r = 0; r < kScanTile / (4 * kThreads); ++r) {
+        const int64_t b = t0 + (int64_t)r * 4 * kThreads + 4 * (int64_t)threadIdx.x;
+        if (t0 + (int64_t)r * 4 * kThreads >= d.nbox) break;  // the whole round is past the end (uniform)
+        const bool full = b + 4 <= d.nbox;
+        uint32_t v[4];
+        if (full) {
+            const uint4 c = *reinterpret_cast<const uint4 *>(d.count + b);
+            v[0] = c.x; v[1] = c.y; v[2] = c.z; v[3] = c.w;
+        } else {
+            for (int k = 0; k < 4; ++k) v[k] = b + k < d.nbox ? d.count[b + k] : 0u;
         }
-        run += c[k];
+        uint32_t total;
+        const uint32_t pre = carry + block_excl_scan_4(v, sh, total);
+        const uint32_t s0 = pre, s1 = s0 + v[0], s2 = s1 + v[1], s3 = s2 + v[2];
+        if (full) {
+            *reinterpret_cast<uint4 *>(d.start + b) = make_uint4(s0, s1, s2, s3);
+            *reinterpret_cast<uint4 *>(d.count + b) = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            const uint32_t sv[4] = {s0, s1, s2, s3};
+            for (int k = 0; k < 4; ++k)
+                if (b + k < d.nbox) {
+                    d.start[b + k] = sv[k];
+                    d.count[b + k] = 0u;
+                }
+        }
+        carry += total;
     }
 }
 
