@@ -1,7 +1,8 @@
 """Build the FP64 CPU oracle shared library (test infrastructure only).
 
 ``python oracle/build.py`` compiles ``abm_oracle.c`` (mechanics, cell
-behaviour, statistics) and ``sir_oracle.c`` (SIR epidemiology) with gcc into
+behaviour, statistics), ``sir_oracle.c`` (SIR epidemiology) and
+``soma_oracle.c`` (diffusion, secretion, chemotaxis) with gcc into
 ``oracle/liboracle.so``.  The flags keep IEEE semantics: no fast-math and no
 floating-point contraction, so every product and sum rounds as written.
 """
@@ -10,7 +11,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "abm_oracle.c"), os.path.join(HERE, "sir_oracle.c")]
+SRCS = [os.path.join(HERE, f) for f in ("abm_oracle.c", "sir_oracle.c", "soma_oracle.c")]
 LIB = os.path.join(HERE, "liboracle.so")
 
 
