@@ -369,6 +369,75 @@ int abm_sir_kernel_time(abm_sir *s, double *ms_total, int64_t *n_launches);
 
 int abm_sir_destroy(abm_sir *s);
 
+/* ------------------------------------------------------------------------- */
+/* Extracellular diffusion with secreting, chemotactic cells (Sec 4.5.2,      */
+/* Eq 4.3; soma clustering, Sec 4.7.1, Algorithms 6-7).  n_substances         */
+/* concentration grids of R^3 points at the voxel centres of the cubic space  */
+/* [lo, lo + S]^3 (dx = S / R); a position belongs to voxel                   */
+/* floor((x - lo) / dx), clamped to [0, R - 1].  Per iteration, from the      */
+/* start-of-iteration state:                                                  */
+/*   chemotaxis  every cell moves by gradient_weight along the normalised     */
+/*               central-difference gradient (u[+1] - u[-1]) / (2 dx) of its  */
+/*               substance at its voxel (no move where it vanishes); the      */
+/*               new coordinates are clamped to the space (Algorithm 7)       */
+/*   secretion   every voxel gains secretion times the number of cells of     */
+/*               that substance's type in it at the start (Algorithm 6)       */
+/*   diffusion   Eq 4.3, evaluated left to right as                           */
+/*               u (1 - mu dt) + c ((u[x+1] - 2u) + u[x-1]) + c (... y) +     */
+/*               c (... z), c = (nu dt) / (dx dx), zero beyond the grid (the  */
+/*               substances diffuse out of the space).                        */
+/* All arithmetic is FP64 and IEEE-rounded as written (no contraction), so    */
+/* results do not depend on the order in which cells or voxels are visited.   */
+/* ------------------------------------------------------------------------- */
+#define ABM_SOMA_POS 0  /* double, n_cells x 3 interleaved */
+#define ABM_SOMA_TYPE 1 /* int32, n_cells */
+#define ABM_SOMA_CONC 2 /* double, n_substances x R^3 (x fastest, then y, z) */
+
+typedef struct abm_soma_params {
+    double lo;              /* lower corner of the space on every axis */
+    double space;           /* side S (> 0) */
+    int32_t resolution;     /* grid points per axis R (1 .. 2048) */
+    int32_t n_substances;   /* 1 .. 16; cells of type t follow substance t */
+    double diffusion;       /* nu (>= 0) */
+    double decay;           /* mu (>= 0) */
+    double dt;              /* time step (> 0) */
+    double secretion;       /* quantity per cell and iteration */
+    double gradient_weight; /* length of a chemotaxis step */
+} abm_soma_params;
+
+typedef struct abm_soma abm_soma;
+
+/* Workspace bytes for n_cells cells (0 allowed: diffusion alone); 0 for
+ * invalid arguments. */
+size_t abm_soma_workspace_bytes(const abm_soma_params *p, int64_t n_cells);
+
+/* Create from host arrays: pos (n_cells x 3 interleaved, inside the space),
+ * type (n_cells int32 in [0, n_substances)), conc (n_substances x R^3
+ * initial concentrations, or NULL for zero).  The workspace (device memory of
+ * at least abm_soma_workspace_bytes) is owned by the caller and must outlive
+ * the handle; kernels run on hip_stream.  Errors: ABM_ERR_ARG (bad
+ * parameters or inputs, workspace too small), ABM_ERR_NONFINITE (a
+ * non-finite position or concentration), ABM_ERR_HIP. */
+int abm_soma_create(const abm_soma_params *p, int64_t n_cells, const double *pos, const int32_t *type,
+                    const double *conc, void *workspace, size_t ws_bytes, void *hip_stream, abm_soma **out);
+
+/* Advance n_iter iterations (asynchronous on the handle's stream). */
+int abm_soma_step(abm_soma *s, int n_iter);
+
+/* Copy one field (ABM_SOMA_*) to dst (host, or device when dst_on_device);
+ * cap: elements dst holds (rows for POS and TYPE, values for CONC);
+ * ABM_ERR_ARG if it is too small.  Cells keep their creation order. */
+int abm_soma_query(abm_soma *s, int field, void *dst, int dst_on_device, int64_t cap);
+
+/* Timing of the diffusion kernel (Eq 4.3 over every substance): with timing
+ * on, every iteration brackets it with HIP events on the handle's stream;
+ * abm_soma_kernel_time returns the total and the count of the iterations
+ * timed since the last call, and resets them. */
+int abm_soma_set_timing(abm_soma *s, int on);
+int abm_soma_kernel_time(abm_soma *s, double *ms_total, int64_t *n_launches);
+
+int abm_soma_destroy(abm_soma *s);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *abm_last_error(void);
 

@@ -116,6 +116,15 @@ def lib():
         L.abm_sir_set_timing.argtypes = [_vp, ctypes.c_int]
         L.abm_sir_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
         L.abm_sir_destroy.argtypes = [_vp]
+        L.abm_soma_workspace_bytes.restype = ctypes.c_size_t
+        L.abm_soma_workspace_bytes.argtypes = [ctypes.POINTER(SomaParams), ctypes.c_int64]
+        L.abm_soma_create.argtypes = [ctypes.POINTER(SomaParams), ctypes.c_int64, _vp, _vp, _vp, _vp,
+                                      ctypes.c_size_t, _vp, _vp]
+        L.abm_soma_step.argtypes = [_vp, ctypes.c_int]
+        L.abm_soma_query.argtypes = [_vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int64]
+        L.abm_soma_set_timing.argtypes = [_vp, ctypes.c_int]
+        L.abm_soma_kernel_time.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), _i64p]
+        L.abm_soma_destroy.argtypes = [_vp]
         _lib = L
     return _lib
 
@@ -228,6 +237,86 @@ class Sir:
         h = getattr(self, "h", None)
         if h is not None and _lib is not None:
             _lib.abm_sir_destroy(h)
+            self.h = None
+
+    def close(self):
+        self.__del__()
+
+
+# Diffusion with secreting, chemotactic cells (abm_soma_*): query fields
+SOMA_POS, SOMA_TYPE, SOMA_CONC = 0, 1, 2
+
+
+class SomaParams(ctypes.Structure):
+    _fields_ = [
+        ("lo", ctypes.c_double), ("space", ctypes.c_double), ("resolution", ctypes.c_int32),
+        ("n_substances", ctypes.c_int32), ("diffusion", ctypes.c_double), ("decay", ctypes.c_double),
+        ("dt", ctypes.c_double), ("secretion", ctypes.c_double), ("gradient_weight", ctypes.c_double),
+    ]
+
+
+def soma_params(lo=0.0, space=100.0, resolution=20, n_substances=2, diffusion=1.0, decay=0.01, dt=1.0,
+                secretion=1.0, gradient_weight=0.75):
+    return SomaParams(float(lo), float(space), int(resolution), int(n_substances), float(diffusion), float(decay),
+                      float(dt), float(secretion), float(gradient_weight))
+
+
+class Soma:
+    """Concentration grids and chemotactic cells (the abm_soma_* entry
+    points); pos: host n x 3 float64 inside the space, cell_type: host int32,
+    conc: host n_substances x R x R x R float64 ([s, z, y, x]) or None."""
+
+    def __init__(self, p, pos, cell_type, conc=None, stream=None):
+        torch = _torch()
+        L = lib()
+        self._params = p
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        cell_type = np.ascontiguousarray(cell_type, dtype=np.int32)
+        self.n = int(pos.shape[0])
+        self.R, self.nsub = int(p.resolution), int(p.n_substances)
+        nbytes = L.abm_soma_workspace_bytes(ctypes.byref(p), self.n)
+        if nbytes == 0:
+            raise AbmError(ERR_ARG, "invalid diffusion parameters or sizes")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        self._stream = _stream_handle(stream)
+        c = None if conc is None else np.ascontiguousarray(conc, dtype=np.float64)
+        h = ctypes.c_void_p()
+        check(L.abm_soma_create(ctypes.byref(p), self.n, pos.ctypes.data_as(ctypes.c_void_p),
+                                cell_type.ctypes.data_as(ctypes.c_void_p),
+                                None if c is None else c.ctypes.data_as(ctypes.c_void_p),
+                                ctypes.c_void_p(self.workspace.data_ptr()), nbytes + 256, self._stream,
+                                ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n_iter=1):
+        check(lib().abm_soma_step(self.h, int(n_iter)))
+
+    def query(self, field):
+        if field == SOMA_CONC:
+            out = np.zeros((self.nsub, self.R, self.R, self.R), dtype=np.float64)
+            cap = out.size
+        elif field == SOMA_POS:
+            out = np.zeros((max(self.n, 1), 3), dtype=np.float64)
+            cap = max(self.n, 1)
+        else:
+            out = np.zeros(max(self.n, 1), dtype=np.int32)
+            cap = max(self.n, 1)
+        check(lib().abm_soma_query(self.h, int(field), out.ctypes.data_as(ctypes.c_void_p), 0, cap))
+        return out if field == SOMA_CONC else out[: self.n]
+
+    def set_timing(self, on):
+        check(lib().abm_soma_set_timing(self.h, int(bool(on))))
+
+    def kernel_time(self):
+        ms = ctypes.c_double(0.0)
+        k = ctypes.c_int64(0)
+        check(lib().abm_soma_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.abm_soma_destroy(h)
             self.h = None
 
     def close(self):

@@ -23,6 +23,10 @@ Recipes (sizes and distributions of the thesis's tissue benchmarks):
                             SIR_MEASLES / SIR_INFLUENZA hold the Table 4.3
                             sizes and parameters, scaled_sir() the same density
                             at k times the persons
+  soma_population(cfg)      cells uniform in the cubic space, types alternating
+                            0, 1; SOMA_CELL_CLUSTERING holds Table 5.1's cell
+                            clustering sizes (2e6 cells, two substances on
+                            300^3 points)
 """
 import math
 
@@ -136,3 +140,23 @@ def sir_population(n_susceptible, n_infected, space, seed=0):
     state = np.zeros(n, dtype=np.uint8)
     state[: int(n_infected)] = 1
     return pos, state
+
+
+# Table 5.1, cell clustering: 2e6 cells and 54 million diffusion volumes (two
+# substances on 300^3 points), 1,000 iterations.  The thesis gives the
+# secretion quantity (1) and the gradient weight (0.75) of the model
+# (Sec 4.7.1); the space (1,200 um: 4 um voxels, 1.16 cells per 1000 um^3),
+# diffusion coefficient, decay and time step are this build's choice
+# (stable: 6 nu dt / dx^2 = 0.375).
+SOMA_CELL_CLUSTERING = dict(lo=0.0, space=1200.0, resolution=300, n_substances=2, diffusion=1.0, decay=0.01,
+                            dt=1.0, secretion=1.0, gradient_weight=0.75, n_cells=2_000_000, steps=1000)
+
+
+def soma_population(cfg, seed=0):
+    """Cell positions uniform in the cubic space (float64, n x 3) and types
+    (int32) alternating over the substances."""
+    rng = np.random.default_rng(seed)
+    n = int(cfg["n_cells"])
+    pos = cfg["lo"] + rng.uniform(0.0, cfg["space"], size=(n, 3))
+    t = (np.arange(n) % int(cfg["n_substances"])).astype(np.int32)
+    return pos, t

@@ -1,0 +1,154 @@
+"""Extracellular diffusion (Eq 4.3) and soma clustering (Algorithms 6-7) on
+the GPU against the oracle.  Both sides evaluate the same FP64 expressions
+in the same order, and the secretions of a voxel are one sum of an integer
+count, so the comparison is exact: every concentration and every cell
+coordinate bit for bit."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import soma as osoma
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def abm():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_10796_amd import abm as _abm
+    _abm.lib()
+    return _abm
+
+
+def _pair(abm, kw, pos, t, conc=None):
+    gp = abm.soma_params(**kw)
+    op = osoma.make_params(**kw)
+    return abm.Soma(gp, pos, t, conc=conc), osoma.OracleSoma(pos, t, op, conc=conc)
+
+
+def _same(abm, g, o, what):
+    u = g.query(abm.SOMA_CONC)
+    assert np.array_equal(u, o.u), f"{what}: concentrations differ (max {np.abs(u - o.u).max():.3e})"
+    if o.n:
+        p = g.query(abm.SOMA_POS)
+        assert np.array_equal(p, o.pos()), f"{what}: positions differ (max {np.abs(p - o.pos()).max():.3e})"
+
+
+@pytest.mark.parametrize("R,nsub,steps", [(37, 2, 20), (130, 1, 5), (1, 1, 3), (64, 1, 4)])
+def test_diffusion_matches_oracle(abm, R, nsub, steps):
+    """Eq 4.3 alone from random concentrations, on grids that are not
+    multiples of the 64 x 16 x 32 work-group tile (and on one point)."""
+    rng = np.random.default_rng(R)
+    kw = dict(space=2.0 * R, resolution=R, n_substances=nsub, diffusion=0.9, decay=0.02, dt=0.5)
+    conc = rng.random((nsub, R, R, R))
+    g, o = _pair(abm, kw, np.zeros((0, 3)), np.zeros(0, np.int32), conc)
+    _same(abm, g, o, "initial")
+    for k in range(steps):
+        g.step(1)
+        o.step(1)
+        _same(abm, g, o, f"R {R}, step {k + 1}")
+
+
+def test_soma_clustering_matches_oracle(abm):
+    """Table 4.5's soma clustering size (32,000 cells of two types, two
+    substances on 85^3 points each), 100 iterations from random positions:
+    concentrations and positions bit for bit every 25 iterations."""
+    rng = np.random.default_rng(3)
+    n, R, S = 32000, 85, 340.0
+    kw = dict(space=S, resolution=R, n_substances=2, diffusion=1.0, decay=0.01, dt=1.0, secretion=1.0,
+              gradient_weight=0.75)
+    pos = rng.uniform(0, S, size=(n, 3))
+    t = (np.arange(n) % 2).astype(np.int32)
+    g, o = _pair(abm, kw, pos, t)
+    t0 = time.perf_counter()
+    for k in range(4):
+        g.step(25)
+        o.step(25)
+        _same(abm, g, o, f"iteration {25 * (k + 1)}")
+    assert np.array_equal(g.query(abm.SOMA_TYPE), t)
+    print(f"soma clustering: 100 iterations equal, {time.perf_counter() - t0:.1f} s", flush=True)
+
+
+@pytest.mark.parametrize("case", ["crowded_voxel", "faces", "negative_field", "no_diffusion"])
+def test_edge_cases_match_oracle(abm, case):
+    """Many cells in one voxel (one secretion sum of a large count), cells on
+    the faces of the space, a negative field (chemotaxis steps that the
+    walls clamp), and no diffusion or decay (secretions accumulate)."""
+    rng = np.random.default_rng(9)
+    n, R, S = 5000, 24, 48.0
+    kw = dict(lo=-10.0, space=S, resolution=R, n_substances=2, diffusion=0.8, decay=0.05, dt=0.5, secretion=0.625,
+              gradient_weight=1.5)
+    pos = rng.uniform(-10.0, -10.0 + S, size=(n, 3))
+    t = rng.integers(0, 2, size=n).astype(np.int32)
+    conc = None
+    if case == "crowded_voxel":
+        pos[:3000] = pos[3000]
+    elif case == "faces":
+        pos[:1000] = rng.choice([-10.0, -10.0 + S], size=(1000, 3))
+    elif case == "negative_field":
+        conc = -rng.random((2, R, R, R)) * 10.0
+    elif case == "no_diffusion":
+        kw.update(diffusion=0.0, decay=0.0)
+    g, o = _pair(abm, kw, pos, t, conc)
+    for k in range(3):
+        g.step(4)
+        o.step(4)
+        _same(abm, g, o, f"{case}, iteration {4 * (k + 1)}")
+
+
+def test_invalid_inputs_are_refused(abm):
+    kw = dict(space=10.0, resolution=5, n_substances=1)
+    with pytest.raises(abm.AbmError):
+        abm.Soma(abm.soma_params(**kw), np.full((1, 3), 11.0), np.zeros(1, np.int32))
+    with pytest.raises(abm.AbmError):
+        abm.Soma(abm.soma_params(**kw), np.full((1, 3), 1.0), np.ones(1, np.int32))
+    with pytest.raises(abm.AbmError):
+        abm.Soma(abm.soma_params(**kw), np.zeros((0, 3)), np.zeros(0, np.int32), conc=np.full((1, 5, 5, 5), np.nan))
+    with pytest.raises(abm.AbmError):
+        abm.Soma(abm.soma_params(space=10.0, resolution=0), np.zeros((0, 3)), np.zeros(0, np.int32))
+
+
+def test_stepping_granularity_and_timing_do_not_change_results(abm):
+    rng = np.random.default_rng(5)
+    n, R, S = 3000, 40, 80.0
+    kw = dict(space=S, resolution=R, n_substances=2)
+    pos = rng.uniform(0, S, size=(n, 3))
+    t = rng.integers(0, 2, size=n).astype(np.int32)
+    a = abm.Soma(abm.soma_params(**kw), pos, t)
+    a.step(30)
+    b = abm.Soma(abm.soma_params(**kw), pos, t)
+    for _ in range(30):
+        b.step(1)
+    c = abm.Soma(abm.soma_params(**kw), pos, t)
+    c.set_timing(True)
+    c.step(30)
+    ms, k = c.kernel_time()
+    assert k == 30 and ms > 0.0
+    for h in (b, c):
+        assert np.array_equal(a.query(abm.SOMA_CONC), h.query(abm.SOMA_CONC))
+        assert np.array_equal(a.query(abm.SOMA_POS), h.query(abm.SOMA_POS))
+
+
+@pytest.mark.timeout(600)
+def test_cell_clustering_full_size_step_matches_oracle(abm):
+    """Table 5.1's cell clustering size (2e6 cells, two substances on 300^3
+    points: 5.4e7 diffusion volumes) in the benchmark's configuration: after
+    10 GPU iterations, one more on the GPU and one by the oracle from the
+    same state give the same concentrations and positions bit for bit."""
+    from paper_2503_10796_amd import inputs
+    t0 = time.perf_counter()
+    cfg = inputs.SOMA_CELL_CLUSTERING
+    pos, t = inputs.soma_population(cfg, seed=7)
+    kw = {k: cfg[k] for k in ("lo", "space", "resolution", "n_substances", "diffusion", "decay", "dt", "secretion",
+                              "gradient_weight")}
+    g = abm.Soma(abm.soma_params(**kw), pos, t)
+    g.step(10)
+    o = osoma.OracleSoma(g.query(abm.SOMA_POS), t, osoma.make_params(**kw), conc=g.query(abm.SOMA_CONC))
+    g.step(1)
+    o.step(1)
+    _same(abm, g, o, "full size")
+    print(f"cell clustering full size: {pos.shape[0]} cells, {2 * 300 ** 3} volumes equal after one step, "
+          f"{time.perf_counter() - t0:.1f} s", flush=True)
