@@ -10,7 +10,8 @@ one tumour spheroid from 1,000 cells to about 5e6; ``sweep`` and
 ``surrogate`` time the batched parameter sweep and the surrogate screening;
 ``apoptosis`` adds the Brownian step and apoptosis of Algorithm 2; ``sir``
 runs Table 4.5's large-scale measles epidemic (1.01e7 persons, 1,000
-iterations).
+iterations); ``soma`` runs Table 5.1's cell clustering (2e6 cells, two
+substances diffusing on 300^3 points).
 
 A step is one iteration of the whole hot path (grid build, force sweep,
 displacement, static flags, re-sort when due).  Prints one JSON line with the
@@ -404,6 +405,89 @@ def sir_cpu_baseline(args):
                       f"with N), OpenMP over persons, {dt:.1f} s"}
 
 
+# Algorithmic bytes of the diffusion kernel per grid point: the point read
+# once and written once (its six neighbours come from registers, LDS or L2).
+DIFFUSE_BYTES = 16
+
+
+def bench_soma(args):
+    """Table 5.1's cell clustering: 2e6 cells secreting and following two
+    substances on 300^3 points each (5.4e7 diffusion volumes), `steps`
+    iterations (the thesis runs 1,000)."""
+    import torch
+    from paper_2503_10796_amd import abm, inputs
+    abm.lib()
+    cfg = dict(inputs.SOMA_CELL_CLUSTERING)
+    if args.soma_resolution:
+        cfg["resolution"] = args.soma_resolution
+    kw = {k: cfg[k] for k in ("lo", "space", "resolution", "n_substances", "diffusion", "decay", "dt", "secretion",
+                              "gradient_weight")}
+    t_gen = time.perf_counter()
+    pos, t = inputs.soma_population(cfg, seed=7)
+    g = abm.Soma(abm.soma_params(**kw), pos, t)
+    n = pos.shape[0]
+    del pos
+    volumes = cfg["n_substances"] * cfg["resolution"] ** 3
+    log(f"[bench] soma: {n} cells, {volumes} diffusion volumes, set up in {time.perf_counter() - t_gen:.1f} s")
+    g.set_timing(True)
+    g.step(args.warmup)
+    torch.cuda.synchronize()
+    g.kernel_time()
+    t0 = time.perf_counter()
+    g.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_ms, k_n = g.kernel_time()
+    k_avg_s = k_ms / max(k_n, 1) / 1e3
+    achieved = volumes * DIFFUSE_BYTES / k_avg_s / 1e9
+    log(f"[bench] soma: {args.steps} iterations in {elapsed:.3f} s, diffusion kernel {k_avg_s * 1e3:.3f} ms")
+    out = {
+        "metric": "extracellular diffusion with soma clustering (Eq 4.3, Algorithms 6-7): diffusion volume updates/s",
+        "value": volumes * args.steps / elapsed, "unit": "volume updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"cell clustering (Table 5.1): {n} cells of two types uniform in a "
+                               f"{cfg['space']:.0f} um cube, two substances on {cfg['resolution']}^3 points, "
+                               f"diffusion {cfg['diffusion']} um^2/step, decay {cfg['decay']}/step, secretion "
+                               f"{cfg['secretion']}, gradient weight {cfg['gradient_weight']} um",
+                   "cells": n, "volumes": volumes, "cell_updates_per_s": n * args.steps / elapsed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_diffuse",
+                     "kernel_ms": k_avg_s * 1e3, "algorithmic_bytes_per_launch": volumes * DIFFUSE_BYTES},
+        "paper_context": "Table 4.5: soma clustering, 32,000 cells and 1,240,000 diffusion volumes, 6,000 "
+                         "iterations in 12.91 s on 72 CPU cores (5.8e8 volume updates/s)",
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host")
+        out["cpu_baseline"] = soma_cpu_baseline(args)
+    print(json.dumps(out), flush=True)
+
+
+def soma_cpu_baseline(args):
+    """The diffusion oracle on the same model at Table 4.5's soma clustering
+    size (32,000 cells, two substances on 85^3 points)."""
+    sys.path.insert(0, ROOT)
+    from oracle import soma as osoma
+    from paper_2503_10796_amd import inputs
+    cfg = dict(inputs.SOMA_CELL_CLUSTERING)
+    cfg.update(resolution=85, space=340.0, n_cells=32000)
+    kw = {k: cfg[k] for k in ("lo", "space", "resolution", "n_substances", "diffusion", "decay", "dt", "secretion",
+                              "gradient_weight")}
+    pos, t = inputs.soma_population(cfg, seed=7)
+    o = osoma.OracleSoma(pos, t, osoma.make_params(**kw))
+    o.step(1)
+    t0 = time.perf_counter()
+    o.step(args.soma_cpu_iters)
+    dt = time.perf_counter() - t0
+    volumes = 2 * 85 ** 3
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": volumes * args.soma_cpu_iters / dt, "unit": "volume updates/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"the same model at Table 4.5's soma clustering size (32,000 cells, {volumes} volumes), "
+                      f"{args.soma_cpu_iters} iterations after one untimed one, FP64, OpenMP over grid planes "
+                      f"(cells serial), {dt:.1f} s"}
+
+
 def bench_surrogate(args):
     """Surrogate screening: train on windows of a batched sweep, judge on the
     simulated histograms of held-out parameter sets, time the screening."""
@@ -601,13 +685,17 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--agents", type=int, default=100_000_000)
-    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate", "spheroid", "apoptosis", "sir"],
+    ap.add_argument("--workload", choices=["uniform", "relaxed", "sweep", "surrogate", "spheroid", "apoptosis", "sir",
+                                           "soma"],
                     default="uniform",
                     help="uniform / relaxed: mechanics at scale (the headline line); sweep: batched parameter "
                          "sweep vs the per-simulation path; surrogate: screening speedup and error; spheroid: "
                          "one tumour spheroid grown to about 5e6 agents; apoptosis: the uniform population with "
                          "the Brownian step and apoptosis of Algorithm 2; sir: Table 4.5's large-scale measles "
-                         "epidemic (use --steps 1000)")
+                         "epidemic (use --steps 1000); soma: Table 5.1's cell clustering with diffusion")
+    ap.add_argument("--soma-resolution", type=int, default=None,
+                    help="soma: grid points per axis (default 300, Table 5.1)")
+    ap.add_argument("--soma-cpu-iters", type=int, default=1000)
     ap.add_argument("--sir-scale", type=int, default=5000,
                     help="sir: persons as a multiple of Table 4.3's measles model (5000: 1.01e7 persons)")
     ap.add_argument("--sir-boundary", choices=["toroidal", "closed"], default="toroidal")
@@ -672,6 +760,9 @@ def main():
         return
     if args.workload == "sir":
         bench_sir(args)
+        return
+    if args.workload == "soma":
+        bench_soma(args)
         return
     from paper_2503_10796_amd import abm
 

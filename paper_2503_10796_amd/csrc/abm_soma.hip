@@ -24,7 +24,9 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "abm_device.h"
@@ -34,7 +36,7 @@ namespace soma {
 
 constexpr int kThreads = 256;
 constexpr int kTX = 64, kTY = 16, kRows = kTY / 4;  // tile: 64 x 16 points, 4 rows per thread
-constexpr int kZChunk = 32;                           // planes per work group
+constexpr int kZChunk = 16;                           // planes per work group
 constexpr int kXcds = 8;
 constexpr int64_t kMaxRes = 2048;
 constexpr int kMaxSubstances = 16;
@@ -55,6 +57,8 @@ struct Dev {
     int32_t *type;
     int64_t *vox;      // substance * V + voxel of each cell
     uint32_t *rank;    // rank of the cell among the cells of its voxel
+    int64_t *orig;     // creation index of the cell in each storage slot
+    double *stage;     // 3 x n: queries in creation order
     int64_t tiles_x, tiles_y, tiles_z, tiles;  // stencil work groups per substance
 };
 
@@ -111,45 +115,69 @@ __global__ __launch_bounds__(kThreads) void k_soma_secrete(Dev d) {
     }
 }
 
+// Cells back in creation order: interleaved positions or types.
+__global__ void k_soma_unsort_pos(Dev d, double *dst) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.n; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = d.orig[j];
+        dst[3 * i] = d.pos[j];
+        dst[3 * i + 1] = d.pos[d.n + j];
+        dst[3 * i + 2] = d.pos[2 * d.n + j];
+    }
+}
+__global__ void k_soma_unsort_type(Dev d, int32_t *dst) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < d.n; j += (int64_t)gridDim.x * blockDim.x)
+        dst[d.orig[j]] = d.type[j];
+}
+
 // Eq 4.3 on every substance (see the file comment for the tiling).
-__global__ __launch_bounds__(kThreads) void k_diffuse(Dev d) {
+__global__ __launch_bounds__(kThreads, 6) void k_diffuse(Dev d) {
 #pragma clang fp contract(off)
     __shared__ double pl[kTY + 2][kTX + 2];
     // tiles dealt to XCDs in contiguous ranges (work group b runs on XCD b mod 8)
-    const int64_t nt = d.tiles * d.nsub;
-    const int64_t per = (nt + kXcds - 1) / kXcds;
-    const int64_t t = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int nt = (int)(d.tiles * d.nsub);
+    const int per = (nt + kXcds - 1) / kXcds;
+    const int t = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
     if (t >= nt) return;
-    const int64_t sub = t / d.tiles;
-    int64_t r = t - sub * d.tiles;
-    const int64_t tx = r % d.tiles_x;
-    r /= d.tiles_x;
-    const int64_t ty = r % d.tiles_y;
-    const int64_t tz = r / d.tiles_y;
+    const int tiles = (int)d.tiles, txs = (int)d.tiles_x, tys = (int)d.tiles_y;
+    const int sub = t / tiles;
+    int r = t - sub * tiles;
+    const int tx = r % txs;
+    r /= txs;
+    const int ty = r % tys;
+    const int tz = r / tys;
+    const int R = d.R;
+    const int64_t plane = (int64_t)R * R;
     const int par = d.ctl->par;
     const double *__restrict__ src = d.u[par] + sub * d.V;
     double *__restrict__ dst = d.u[par ^ 1] + sub * d.V;
     const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;  // wave ly holds rows ly, ly + 4, ly + 8, ly + 12
-    const int64_t x = tx * kTX + lx;
-    const int64_t y0 = ty * kTY;
-    const int64_t z0 = tz * kZChunk;
-    const int64_t z1 = z0 + kZChunk < d.R ? z0 + kZChunk : d.R;
-    int64_t yr[kRows];
-    for (int k = 0; k < kRows; ++k) yr[k] = y0 + ly + 4 * k;
-    double zm[kRows], zc[kRows], zp[kRows];
+    const int x = tx * kTX + lx;
+    const int y0 = ty * kTY;
+    const int z0 = tz * kZChunk;
+    const int z1 = z0 + kZChunk < R ? z0 + kZChunk : R;
+    // in-plane offsets of this thread's points, of its x halo (lanes 0 and 1)
+    // and of its y halo (waves 0 and 3); -1: beyond the grid (zero)
+    const int hxx = tx * kTX + (lx == 0 ? -1 : kTX);
+    const int hyy = ly == 0 ? y0 - 1 : y0 + kTY;
+    int off[kRows], hoff[kRows];
     for (int k = 0; k < kRows; ++k) {
-        zm[k] = at(d, src, x, yr[k], z0 - 1);
-        zc[k] = at(d, src, x, yr[k], z0);
-        zp[k] = at(d, src, x, yr[k], z0 + 1);
+        const int y = y0 + ly + 4 * k;
+        off[k] = (x < R && y < R) ? y * R + x : -1;
+        hoff[k] = (lx < 2 && hxx >= 0 && hxx < R && y < R) ? y * R + hxx : -1;
     }
-    // halo of the current plane: x halo (lanes 0 and 1 of every wave, its
-    // four rows) and y halo (waves 0 and 3: the rows below and above)
-    const int64_t hxx = tx * kTX + (lx == 0 ? -1 : kTX);
-    const int64_t hyy = ly == 0 ? y0 - 1 : y0 + kTY;
-    double hx[kRows], hy = 0.0;
-    for (int k = 0; k < kRows; ++k) hx[k] = lx < 2 ? at(d, src, hxx, yr[k], z0) : 0.0;
-    if (ly == 0 || ly == 3) hy = at(d, src, x, hyy, z0);
-    for (int64_t z = z0; z < z1; ++z) {
+    const int yoff = ((ly == 0 || ly == 3) && hyy >= 0 && hyy < R && x < R) ? hyy * R + x : -1;
+    auto ld = [&](int o, int z) -> double {
+        return (o >= 0 && z >= 0 && z < R) ? src[(int64_t)z * plane + o] : 0.0;
+    };
+    double zm[kRows], zc[kRows], zp[kRows], hx[kRows];
+    for (int k = 0; k < kRows; ++k) {
+        zm[k] = ld(off[k], z0 - 1);
+        zc[k] = ld(off[k], z0);
+        zp[k] = ld(off[k], z0 + 1);
+        hx[k] = ld(hoff[k], z0);
+    }
+    double hy = ld(yoff, z0);
+    for (int z = z0; z < z1; ++z) {
         for (int k = 0; k < kRows; ++k) {
             pl[1 + ly + 4 * k][1 + lx] = zc[k];
             if (lx < 2) pl[1 + ly + 4 * k][lx == 0 ? 0 : kTX + 1] = hx[k];
@@ -157,13 +185,14 @@ __global__ __launch_bounds__(kThreads) void k_diffuse(Dev d) {
         if (ly == 0) pl[0][1 + lx] = hy;
         if (ly == 3) pl[kTY + 1][1 + lx] = hy;
         __syncthreads();
-        // loads of the next plane's halo and the plane after next, in flight during the update
-        double nhx[kRows], nhy = 0.0, nzp[kRows];
+        // loads of the next plane's halo and of the plane after next, in flight during the update
+        double nzp[kRows];
         for (int k = 0; k < kRows; ++k) {
-            nhx[k] = lx < 2 ? at(d, src, hxx, yr[k], z + 1) : 0.0;
-            nzp[k] = at(d, src, x, yr[k], z + 2);
+            nzp[k] = ld(off[k], z + 2);
+            hx[k] = ld(hoff[k], z + 1);
         }
-        if (ly == 0 || ly == 3) nhy = at(d, src, x, hyy, z + 1);
+        hy = ld(yoff, z + 1);
+        double *dz = dst + (int64_t)z * plane;
         for (int k = 0; k < kRows; ++k) {
             const int row = 1 + ly + 4 * k;
             const double c = zc[k];
@@ -171,16 +200,14 @@ __global__ __launch_bounds__(kThreads) void k_diffuse(Dev d) {
             v = v + d.c * ((pl[row][lx + 2] - 2.0 * c) + pl[row][lx]);
             v = v + d.c * ((pl[row + 1][lx + 1] - 2.0 * c) + pl[row - 1][lx + 1]);
             v = v + d.c * ((zp[k] - 2.0 * c) + zm[k]);
-            if (x < d.R && yr[k] < d.R) dst[x + (int64_t)d.R * (yr[k] + (int64_t)d.R * z)] = v;
+            if (off[k] >= 0) dz[off[k]] = v;
         }
         __syncthreads();
         for (int k = 0; k < kRows; ++k) {
             zm[k] = zc[k];
             zc[k] = zp[k];
             zp[k] = nzp[k];
-            hx[k] = nhx[k];
         }
-        hy = nhy;
     }
 }
 
@@ -189,20 +216,6 @@ __global__ void k_soma_end(Dev d) {
     d.ctl->iter += 1;
 }
 
-__global__ void k_soma_interleave(const double *src, double *dst, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        dst[3 * i] = src[i];
-        dst[3 * i + 1] = src[n + i];
-        dst[3 * i + 2] = src[2 * n + i];
-    }
-}
-__global__ void k_soma_deinterleave(const double *src, double *dst, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        dst[i] = src[3 * i];
-        dst[n + i] = src[3 * i + 1];
-        dst[2 * n + i] = src[3 * i + 2];
-    }
-}
 __global__ void k_soma_zero(uint32_t *p, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
@@ -236,7 +249,7 @@ struct Carver {
 };
 
 struct Layout {
-    size_t ctl, u0, u1, cnt, pos, type, vox, rank, total;
+    size_t ctl, u0, u1, cnt, pos, type, vox, rank, orig, stage, total;
 };
 
 bool params_ok(const abm_soma_params &p) {
@@ -262,6 +275,8 @@ bool make_layout(const abm_soma_params &p, int64_t n, Layout &L) {
     L.type = c.take<int32_t>(N);
     L.vox = c.take<int64_t>(N);
     L.rank = c.take<uint32_t>(N);
+    L.orig = c.take<int64_t>(N);
+    L.stage = c.take<double>(3 * N);
     L.total = c.off + 256;
     return true;
 }
@@ -364,6 +379,8 @@ extern "C" int abm_soma_create(const abm_soma_params *p, int64_t n, const double
     d.type = (int32_t *)(base + L.type);
     d.vox = (int64_t *)(base + L.vox);
     d.rank = (uint32_t *)(base + L.rank);
+    d.orig = (int64_t *)(base + L.orig);
+    d.stage = (double *)(base + L.stage);
     d.tiles_x = (R + sk::kTX - 1) / sk::kTX;
     d.tiles_y = (R + sk::kTY - 1) / sk::kTY;
     d.tiles_z = (R + sk::kZChunk - 1) / sk::kZChunk;
@@ -375,20 +392,28 @@ extern "C" int abm_soma_create(const abm_soma_params *p, int64_t n, const double
     else hipLaunchKernelGGL(sk::k_soma_zero, dim3(sk::grid_for(2 * pts, 65536)), dim3(sk::kThreads), 0, st,
                             (uint32_t *)d.u[0], 2 * pts);
     if (e == hipSuccess && n > 0) {
-        // positions: interleaved upload into the voxel list (free until the first step), de-interleaved
-        if ((size_t)n * 3 * sizeof(double) <= (size_t)pts * sizeof(uint32_t)) {
-            e = hipMemcpyAsync(d.cnt, pos, sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess)
-                hipLaunchKernelGGL(sk::k_soma_deinterleave, dim3(sk::grid_for(n, 65536)), dim3(sk::kThreads), 0, st,
-                                   (const double *)d.cnt, d.pos, n);
-        } else {
-            std::vector<double> blocks((size_t)n * 3);
-            for (int64_t i = 0; i < n; ++i)
-                for (int a = 0; a < 3; ++a) blocks[(size_t)a * n + i] = pos[3 * i + a];
-            e = hipMemcpyAsync(d.pos, blocks.data(), sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
+        // cells stored in the order of their substance and voxel (x fastest):
+        // cells that are near each other read the same lines of the grid
+        std::vector<int64_t> key((size_t)n), perm((size_t)n);
+        auto vaxis = [&](double v) {
+            double q = floor((v - d.lo) / d.dx);
+            return q < 0.0 ? (int64_t)0 : (q > (double)(R - 1) ? R - 1 : (int64_t)q);
+        };
+        for (int64_t i = 0; i < n; ++i)
+            key[i] = (int64_t)type[i] * V + vaxis(pos[3 * i]) + R * (vaxis(pos[3 * i + 1]) + R * vaxis(pos[3 * i + 2]));
+        std::iota(perm.begin(), perm.end(), (int64_t)0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return key[a] < key[b]; });
+        std::vector<double> blocks((size_t)n * 3);
+        std::vector<int32_t> ts((size_t)n);
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t i = perm[j];
+            for (int a = 0; a < 3; ++a) blocks[(size_t)a * n + j] = pos[3 * i + a];
+            ts[j] = type[i];
         }
-        if (e == hipSuccess) e = hipMemcpyAsync(d.type, type, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(d.pos, blocks.data(), sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d.type, ts.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d.orig, perm.data(), sizeof(int64_t) * (size_t)n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);  // the host arrays end with this scope
     }
     if (e != hipSuccess) {
         delete s;
@@ -452,29 +477,20 @@ extern "C" int abm_soma_query(abm_soma *s, int field, void *dst, int dst_on_devi
     sk::Ctl c;
     SOMACHK(hipMemcpyAsync(&c, d.ctl, sizeof c, hipMemcpyDeviceToHost, st));
     SOMACHK(hipStreamSynchronize(st));
-    if (field == ABM_SOMA_POS) {
+    if (field == ABM_SOMA_POS || field == ABM_SOMA_TYPE) {
         if (cap < d.n) return set_error(ABM_ERR_ARG, "destination too small");
         if (d.n == 0) return ABM_OK;
-        // the other concentration buffer is free between iterations
-        double *tmp = d.u[c.par ^ 1];
-        if ((size_t)d.V * (size_t)d.nsub < (size_t)d.n * 3) {
-            std::vector<double> blocks((size_t)d.n * 3);
-            SOMACHK(hipMemcpyAsync(blocks.data(), d.pos, sizeof(double) * 3 * (size_t)d.n, hipMemcpyDeviceToHost, st));
-            SOMACHK(hipStreamSynchronize(st));
-            std::vector<double> inter((size_t)d.n * 3);
-            for (int64_t i = 0; i < d.n; ++i)
-                for (int a = 0; a < 3; ++a) inter[3 * i + a] = blocks[(size_t)a * d.n + i];
-            SOMACHK(hipMemcpyAsync(dst, inter.data(), sizeof(double) * 3 * (size_t)d.n,
-                                   dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
-        } else {
-            hipLaunchKernelGGL(sk::k_soma_interleave, dim3(sk::grid_for(d.n, 65536)), dim3(sk::kThreads), 0, st,
-                               (const double *)d.pos, tmp, d.n);
-            SOMACHK(hipMemcpyAsync(dst, tmp, sizeof(double) * 3 * (size_t)d.n, kind, st));
-        }
-    } else if (field == ABM_SOMA_TYPE) {
-        if (cap < d.n) return set_error(ABM_ERR_ARG, "destination too small");
-        if (d.n == 0) return ABM_OK;
-        SOMACHK(hipMemcpyAsync(dst, d.type, sizeof(int32_t) * (size_t)d.n, kind, st));
+        const size_t bytes = field == ABM_SOMA_POS ? sizeof(double) * 3 * (size_t)d.n : sizeof(int32_t) * (size_t)d.n;
+        void *tmp = d.stage;
+        if (field == ABM_SOMA_POS)
+            hipLaunchKernelGGL(sk::k_soma_unsort_pos, dim3(sk::grid_for(d.n, 65536)), dim3(sk::kThreads), 0, st, d,
+                               (double *)tmp);
+        else
+            hipLaunchKernelGGL(sk::k_soma_unsort_type, dim3(sk::grid_for(d.n, 65536)), dim3(sk::kThreads), 0, st, d,
+                               (int32_t *)tmp);
+        hipError_t e = hipMemcpyAsync(dst, tmp, bytes, kind, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return set_error(ABM_ERR_HIP, hipGetErrorString(e));
     } else if (field == ABM_SOMA_CONC) {
         const int64_t pts = d.V * d.nsub;
         if (cap < pts) return set_error(ABM_ERR_ARG, "destination too small");

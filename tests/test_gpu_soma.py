@@ -40,7 +40,7 @@ def _same(abm, g, o, what):
 @pytest.mark.parametrize("R,nsub,steps", [(37, 2, 20), (130, 1, 5), (1, 1, 3), (64, 1, 4)])
 def test_diffusion_matches_oracle(abm, R, nsub, steps):
     """Eq 4.3 alone from random concentrations, on grids that are not
-    multiples of the 64 x 16 x 32 work-group tile (and on one point)."""
+    multiples of the 64 x 16 x 16 work-group tile (and on one point)."""
     rng = np.random.default_rng(R)
     kw = dict(space=2.0 * R, resolution=R, n_substances=nsub, diffusion=0.9, decay=0.02, dt=0.5)
     conc = rng.random((nsub, R, R, R))
