@@ -201,7 +201,38 @@ def bench_sweep(args):
         "batched_s": t_batch, "per_simulation_s": None if args.batched_only else t_single,
         "speedup_vs_per_simulation": None if args.batched_only else t_single / t_batch,
     }
+    if not args.no_cpu_baseline and not args.batched_only:
+        log("[bench] timing the oracle on the host")
+        out["cpu_baseline"] = sweep_cpu_baseline(args, cfg)
     print(json.dumps(out), flush=True)
+
+
+def sweep_cpu_baseline(args, cfg):
+    """The oracle on a bounded sample of the sweep: its first simulations,
+    one after another, over the first iterations (the oracle has no batching:
+    simulations are independent)."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    from oracle import sim as osim
+    from paper_2503_10796_amd import inputs
+    sims, iters = list(range(args.sweep_cpu_sims)), args.sweep_cpu_iters
+    updates, dt = 0.0, 0.0
+    for s in sims:
+        pos, diam, vol, growth = cfg.state(s)
+        counts = cfg.counts(s, vol, growth)
+        o = osim.OracleSim(pos, diam, osim.make_params(box_len=0.0, div_vol=inputs.division_volume(float(cfg.d_div[s])),
+                                                       adherence=float(cfg.adherence[s]), detect_static=True,
+                                                       seed=cfg.seed, sim_id=s),
+                           vol=vol, growth=growth, cap=int(counts[iters]) + 16)
+        t0 = time.perf_counter()
+        o.step(iters)
+        dt += time.perf_counter() - t0
+        updates += float(np.asarray(counts[:iters]).sum())
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": updates / dt, "unit": "agent updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"simulations {sims[0]}..{sims[-1]} of the same sweep, one after another, over their first "
+                      f"{iters} iterations ({updates:.3g} updates), FP64, OpenMP over agents, {dt:.1f} s"}
 
 
 def lineage_counts(vol, growth, vdiv, iters):
@@ -269,7 +300,34 @@ def bench_spheroid(args):
         "progress": [{"iteration": it, "seconds": t, "agents": n} for it, t, n in marks],
         "r_gyr_um_end": float(rg[0]), "r_max_um_end": float(rm[0]),
     }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host")
+        out["cpu_baseline"] = spheroid_cpu_baseline(args)
     print(json.dumps(out), flush=True)
+
+
+def spheroid_cpu_baseline(args):
+    """The oracle on the same spheroid (same seed and growth scale) over its
+    first iterations, while the population is small enough to finish in
+    seconds."""
+    sys.path.insert(0, ROOT)
+    from oracle import sim as osim
+    from paper_2503_10796_amd import inputs
+    S, iters = args.spheroid_scale, args.spheroid_cpu_iters
+    pos, diam, vol, growth = inputs.spheroid(1000, seed=3, growth_scale=S)
+    vdiv = inputs.division_volume(12.0)
+    counts = lineage_counts(vol, growth, vdiv, iters)
+    o = osim.OracleSim(pos, diam, osim.make_params(box_len=0.0, div_vol=vdiv, seed=3), vol=vol, growth=growth,
+                       cap=int(counts[-1]) + 16)
+    t0 = time.perf_counter()
+    o.step(iters)
+    dt = time.perf_counter() - t0
+    updates = float(counts[:iters].sum())
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": updates / dt, "unit": "agent updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"the same spheroid over its first {iters} iterations (1000 -> {int(counts[-1])} agents, "
+                      f"{updates:.3g} updates), FP64, OpenMP over agents, {dt:.1f} s"}
 
 
 def bench_apoptosis(args):
@@ -704,6 +762,9 @@ def main():
     ap.add_argument("--spheroid-scale", type=float, default=8.0,
                     help="spheroid: factor on the growth rates (8.0 reaches about 5e6 agents at 600 iterations)")
     ap.add_argument("--spheroid-iters", type=int, default=600, help="spheroid: iterations")
+    ap.add_argument("--spheroid-cpu-iters", type=int, default=350)
+    ap.add_argument("--sweep-cpu-sims", type=int, default=8)
+    ap.add_argument("--sweep-cpu-iters", type=int, default=100)
     ap.add_argument("--sims", type=int, default=256, help="sweep: simulations")
     ap.add_argument("--sweep-iters", type=int, default=300, help="sweep: iterations per simulation")
     ap.add_argument("--batched-only", action="store_true",

@@ -305,9 +305,16 @@ __global__ __launch_bounds__(kThreads) void k_sir_apply(Dev d) {
 }
 
 // Every person to its slot in box order.
+// One person per thread; work group b runs on XCD b mod 8, and the groups of
+// XCD k take the k-th contiguous eighth of the persons in order, so the slots
+// that neighbouring persons write (near each other: persons move about one
+// box) fill whole lines in one L2.
 __global__ __launch_bounds__(kThreads) void k_sir_scatter(Dev d) {
     const int64_t n = d.n;
-    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+    const int64_t per_xcd = gridDim.x / 8;
+    const int64_t lb = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    const int64_t i = lb * kThreads + threadIdx.x;
+    if (i < n) {
         const int64_t j = (int64_t)d.start[d.key[i]] + d.rank[i];
         d.pos[j] = d.tmp[i];
         d.pos[n + j] = d.tmp[n + i];
@@ -359,7 +366,8 @@ void launch_sort(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_sir_tiles, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sir_top, dim3(1), dim3(kTopThreads), 0, s, d);
     hipLaunchKernelGGL(k_sir_apply, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d);
-    if (d.n > 0) hipLaunchKernelGGL(k_sir_scatter, dim3(grid_for(d.n, 65536)), dim3(kThreads), 0, s, d);
+    if (d.n > 0)
+        hipLaunchKernelGGL(k_sir_scatter, dim3(((d.n + kThreads - 1) / kThreads + 7) / 8 * 8), dim3(kThreads), 0, s, d);
 }
 
 void launch_behave(const Dev &d, hipStream_t s) {
