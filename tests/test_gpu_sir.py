@@ -221,3 +221,29 @@ def test_large_scale_sampled_persons_match_oracle(abm):
     print(f"large scale: {u0.size} persons, counts at iteration 80 {counts.tolist()}, {checked} checked "
           f"({infected_now} newly infected), {time.perf_counter() - t0:.1f} s", flush=True)
     assert checked > 500 and infected_now > 0
+
+
+def test_large_scale_epidemic_follows_the_sir_equations(abm):
+    """At 1.01e7 persons the run is nearly deterministic: the infected share
+    of the GPU run follows the SIR equations of Fig 4.17A (peak 0.725 of the
+    persons at step 117) as closely as the oracle's small runs do."""
+    from scipy.integrate import solve_ivp
+    cfg = inputs.scaled_sir(inputs.SIR_MEASLES, 5000)
+    pos, st = inputs.sir_population(cfg["n_susceptible"], cfg["n_infected"], cfg["space"], seed=21)
+    gp, _ = _params(abm, cfg, 21, space=cfg["space"])
+    g = abm.Sir(gp, pos, st, hist_cap=512)
+    del pos, st
+    h = g.step(400, counts=True)
+    n = cfg["n_susceptible"] + cfg["n_infected"]
+    b, gam = cfg["beta"], cfg["gamma"]
+    y = solve_ivp(lambda _, v: [-b * v[0] * v[1] / n, b * v[0] * v[1] / n - gam * v[1], gam * v[1]], (0, 400),
+                  [cfg["n_susceptible"], cfg["n_infected"], 0.0], t_eval=np.arange(1, 401), rtol=1e-10,
+                  atol=1e-8).y.T / n
+    inf = h[:, 1] / n
+    print(f"1.01e7 persons: peak infected {inf.max():.4f} at step {int(inf.argmax()) + 1} (equations "
+          f"{y[:, 1].max():.4f} at {int(y[:, 1].argmax()) + 1}), largest gap {np.abs(inf - y[:, 1]).max():.4f}",
+          flush=True)
+    assert np.all(h.sum(axis=1) == n)
+    assert abs(inf.max() - y[:, 1].max()) <= 0.03
+    assert abs(int(inf.argmax()) - int(y[:, 1].argmax())) <= 10
+    assert np.abs(inf - y[:, 1]).max() <= 0.1
