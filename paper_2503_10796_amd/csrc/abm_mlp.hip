@@ -160,6 +160,90 @@ __global__ void k_weights_bf16(const float *theta, __bf16 *wbf, Layers Ls) {
     }
 }
 
+// Inference of the whole network in one kernel, for networks whose padded
+// widths are at most kFuseMax: a work group (4 waves) carries 16 rows of the
+// batch through every layer, with the activations in LDS (BF16, zero padded
+// to the next layer's K) and the weights read from L2.  Each wave takes the
+// 16-column output tiles w, w + 4, ... of a layer, four at a time, with the
+// B fragments of all K steps of the four tiles loaded before the first MFMA
+// (so the L2 latency is paid once per layer, not once per K step).  The MFMA
+// operands and their K order are those of k_gemm, and the epilogues are the
+// same expressions, so the outputs equal the layer-by-layer path bit for bit.
+constexpr int kFuseRows = 16, kFuseMax = 256, kFuseLd = kFuseMax + 8;
+
+__global__ void __launch_bounds__(256) k_mlp_fused(const float *__restrict__ x, float *__restrict__ y, int batch,
+                                                    const __bf16 *__restrict__ wbf, const float *__restrict__ theta,
+                                                    Layers Lsa) {
+    __shared__ __attribute__((aligned(16))) __bf16 act[2][kFuseRows][kFuseLd];
+    __shared__ Layers Ls;  // indexed by the layer below: kept in LDS, not in private memory
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) Ls = Lsa;
+    __syncthreads();
+    const int row0 = blockIdx.x * kFuseRows;
+    const __bf16 zero = (__bf16)0.0f;
+    {  // the input rows, converted and zero padded to ldk[0] (rows past the batch: zero)
+        const int in = Ls.in[0], ld = Ls.ldk[0];
+        for (int t = tid; t < kFuseRows * ld; t += 256) {
+            const int r = t / ld, c = t % ld;
+            act[0][r][c] = (row0 + r < batch && c < in) ? (__bf16)x[(size_t)(row0 + r) * in + c] : zero;
+        }
+    }
+    __syncthreads();
+    for (int l = 0; l < Ls.nl; ++l) {
+        const int cur = l & 1, nxt = cur ^ 1;
+        const int K = Ls.ldk[l], N = Ls.out[l], nsteps = K / kBK;
+        const bool last = l == Ls.nl - 1;
+        const __bf16 *W = wbf + Ls.wbf_off[l];  // [N][K], zero padded
+        const float *bias = theta + Ls.boff[l];
+        const int ntiles = (N + 15) / 16;
+        for (int j0 = w; j0 < ntiles; j0 += 16) {
+            const int jt[4] = {j0, j0 + 4, j0 + 8, j0 + 12};
+            bf16x8 bw[4][kFuseMax / kBK];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n = jt[q] * 16 + (lane & 15);
+                const bool ok = jt[q] < ntiles && n < N;
+#pragma unroll
+                for (int st = 0; st < kFuseMax / kBK; ++st) {
+                    if (st < nsteps && ok) bw[q][st] = *(const bf16x8 *)&W[(size_t)n * K + st * kBK + 8 * (lane >> 4)];
+                    else bw[q][st] = bf16x8{zero, zero, zero, zero, zero, zero, zero, zero};
+                }
+            }
+            f32x4 acc[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < kFuseMax / kBK; ++st) {
+                if (st >= nsteps) break;
+                const bf16x8 a = *(const bf16x8 *)&act[cur][lane & 15][st * kBK + 8 * (lane >> 4)];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[q][st], acc[q], 0, 0, 0);
+            }
+            // lane holds column (lane & 15) and rows 4 * (lane >> 4) + e of each tile
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n = jt[q] * 16 + (lane & 15);
+                if (jt[q] >= ntiles || n >= N) continue;
+                const float b = bias[n];
+                for (int e = 0; e < 4; ++e) {
+                    const int m = 4 * (lane >> 4) + e;
+                    if (last) {
+                        if (row0 + m < batch) y[(size_t)(row0 + m) * N + n] = acc[q][e] + b;
+                    } else {
+                        act[nxt][m][n] = (__bf16)gelu(acc[q][e] + b);
+                    }
+                }
+            }
+        }
+        if (!last) {
+            // zero the padding of the next layer's K (columns N .. ldk[l + 1])
+            const int ld = Ls.ldk[l + 1];
+            for (int t = tid; t < kFuseRows * (ld - N); t += 256) act[nxt][t / (ld - N)][N + t % (ld - N)] = zero;
+        }
+        __syncthreads();
+    }
+}
+
 // He-normal weights (std sqrt(2 / fan_in)), zero biases.  Normal deviates by
 // Box-Muller from Philox4x32-10, counter (parameter index, 0, 0, 0), key = seed.
 __global__ void k_init(float *theta, Layers Ls, uint64_t seed) {
@@ -509,6 +593,14 @@ extern "C" int abm_mlp_infer(abm_mlp *m, const float *x, float *y, int batch) {
     if (rc) return rc;
     if (!x || !y) return set_error(ABM_ERR_ARG, "null argument");
     const Layers &Ls = m->Ls;
+    bool fits = true;
+    for (int l = 0; l < Ls.nl; ++l) fits = fits && Ls.ldk[l] <= kFuseMax && Ls.out[l] <= kFuseMax;
+    if (fits) {
+        hipLaunchKernelGGL(k_mlp_fused, dim3((batch + kFuseRows - 1) / kFuseRows), dim3(256), 0, m->stream, x, y, batch,
+                           m->wbf, m->theta, Ls);
+        MLPCHK(hipGetLastError());
+        return ABM_OK;
+    }
     hipLaunchKernelGGL(k_to_bf16, dim3(std::min(4096, (batch * Ls.ldk[0] + 255) / 256)), dim3(256), 0, m->stream, x,
                        m->hbf[0], batch, Ls.in[0], Ls.ldk[0]);
     forward(m, batch);
