@@ -1559,7 +1559,7 @@ __global__ void __launch_bounds__(1024) k_tile_scan(Dev d, const int64_t *begin,
     if (ABM_ABORTED(d)) return;
     __shared__ uint32_t sh[16];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int s = 0; s < d.n_sims; ++s) {
+    for (int s = blockIdx.x; s < d.n_sims; s += gridDim.x) {  // one work group per simulation
         int64_t b0 = begin[s], b1 = begin[s + 1];
         uint32_t carry = 0;
         for (int64_t c = b0; c < b1; c += blockDim.x) {
@@ -1884,7 +1884,7 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
     if (any_growth) {
         hipLaunchKernelGGL(k_div_plan, dim3(1), dim3(64), 0, st, d);
         hipLaunchKernelGGL(k_uscan_tiles, dim3(grid_boxes), dim3(256), 0, st, d);
-        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, d, (const int64_t *)d.utile_begin,
+        hipLaunchKernelGGL(k_tile_scan, dim3(d.n_sims), dim3(1024), 0, st, d, (const int64_t *)d.utile_begin,
                            (const uint32_t *)d.tile_sum, d.tile_off, 0);
         hipLaunchKernelGGL(k_div_check, dim3(1), dim3(256), 0, st, d);
         hipLaunchKernelGGL(k_uscan_apply, dim3(grid_boxes), dim3(256), 0, st, d);
@@ -1896,7 +1896,7 @@ void launch_after_sweep(const Dev &d, hipStream_t st, int grid_agents, int grid_
                            (const int64_t *)d.btile_begin);
     }
     if (any_death) {
-        hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, st, d, (const int64_t *)d.tile_begin,
+        hipLaunchKernelGGL(k_tile_scan, dim3(d.n_sims), dim3(1024), 0, st, d, (const int64_t *)d.tile_begin,
                            (const uint32_t *)d.rm_sum, d.rm_off, 1);
         hipLaunchKernelGGL(k_rm_plan, dim3(1), dim3(64), 0, st, d);
         hipLaunchKernelGGL(k_rm_apply, dim3(grid_agents), dim3(256), 0, st, d);

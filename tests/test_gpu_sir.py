@@ -247,3 +247,21 @@ def test_large_scale_epidemic_follows_the_sir_equations(abm):
     assert abs(inf.max() - y[:, 1].max()) <= 0.03
     assert abs(int(inf.argmax()) - int(y[:, 1].argmax())) <= 10
     assert np.abs(inf - y[:, 1]).max() <= 0.1
+
+
+def test_counts_through_a_short_history_ring(abm):
+    """A history of 4 iterations returns the counts of a 25-iteration step in
+    chunks of 3 (the end of each iteration clears the next slot), equal to
+    the counts of a run with a long history and to the oracle's."""
+    cfg = inputs.SIR_MEASLES
+    pos, st = inputs.sir_population(500, 50, 40.0, seed=6)
+    gp, op = _params(abm, cfg, 6, space=40.0)
+    short = abm.Sir(gp, pos, st, hist_cap=4)
+    long_ = abm.Sir(gp, pos, st, hist_cap=64)
+    o = osir.OracleSIR(pos, st, op)
+    hs = np.concatenate([short.step(25, counts=True), short.step(7, counts=True)])
+    hl = long_.step(32, counts=True)
+    assert np.array_equal(hs, hl)
+    assert np.array_equal(hs, o.step(32))
+    with pytest.raises(abm.AbmError):  # a history needs at least two slots
+        abm.Sir(gp, pos, st, hist_cap=1)
