@@ -16,8 +16,13 @@
  *   - periodic Morton-order re-sort of agent storage (Sec 5.4.2, Fig 5.4);
  *   - copy semantics: every agent reads the start-of-iteration state and new
  *     agents appear in the next iteration (Sec 5.2.1).
+ *   - Brownian step and apoptosis with parallel removal (Algorithm 2,
+ *     Sec 5.3.2, Table 4.2).
  * Plus batched independent simulations (parameter sweeps, Sec 4.3 execution
- * modes C-E) and a surrogate MLP trained with BF16 matrix-core kernels.
+ * modes C-E), a surrogate MLP trained with BF16 matrix-core kernels, the SIR
+ * epidemiology model with toroidal or closed space (Algorithms 3-5,
+ * Sec 4.4.11) and extracellular diffusion with soma clustering (Eq 4.3,
+ * Algorithms 6-7).
  *
  * Conventions for every entry point:
  *   - Return value: ABM_OK (0) or a negative ABM_ERR_* code; the message of
