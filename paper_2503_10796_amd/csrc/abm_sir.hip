@@ -15,7 +15,11 @@
 //   k_sir_tiles / k_sir_top / k_sir_apply
 //                  exclusive scan of the box counts into box starts (and the
 //                  counts cleared for the next iteration)
-//   k_sir_scatter  every person to its slot: box start + rank
+//   k_sir_dest / k_sir_gather
+//                  the source of every slot (slot = box start + rank), then
+//                  every slot gathers its person: the writes of the sorted
+//                  state are contiguous, the scattered part is 4 bytes per
+//                  person
 //   k_sir_end      iteration counter and the next history slot
 // All of it is captured once into a HIP graph and replayed.  The order of
 // persons inside a box depends on the order of the atomics, but nothing
@@ -62,6 +66,7 @@ struct Dev {
     uint8_t *state, *state_t;
     uint32_t *uid, *uid_t;
     uint32_t *key, *rank;        // box of the new position, rank within it
+    uint32_t *src;               // person (in the temporary order) of every sorted slot
     uint32_t *count;             // nbox
     uint32_t *start;             // nbox + 1
     uint32_t *tile;              // ntiles: tile sums, then their exclusive prefix
@@ -305,17 +310,25 @@ __global__ __launch_bounds__(kThreads) void k_sir_apply(Dev d) {
 }
 
 // Every person to its slot in box order.
-// One person per thread; work group b runs on XCD b mod 8, and the groups of
-// XCD k take the k-th contiguous eighth of the persons in order, so the slots
-// that neighbouring persons write (near each other: persons move about one
-// box) fill whole lines in one L2.
-__global__ __launch_bounds__(kThreads) void k_sir_scatter(Dev d) {
+// The source of every slot of the new box order.
+__global__ __launch_bounds__(kThreads) void k_sir_dest(Dev d) {
+    const int64_t n = d.n;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        d.src[(int64_t)d.start[d.key[i]] + d.rank[i]] = (uint32_t)i;
+}
+
+// Every slot gathers its person from the temporary arrays.  One slot per
+// thread; work group b runs on XCD b mod 8 and the groups of XCD k take the
+// k-th contiguous eighth of the slots in order, so that the lines of the
+// temporary arrays that neighbouring slots read (their persons came from
+// nearby boxes) stay in one L2.
+__global__ __launch_bounds__(kThreads) void k_sir_gather(Dev d) {
     const int64_t n = d.n;
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t lb = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    const int64_t i = lb * kThreads + threadIdx.x;
-    if (i < n) {
-        const int64_t j = (int64_t)d.start[d.key[i]] + d.rank[i];
+    const int64_t j = lb * kThreads + threadIdx.x;
+    if (j < n) {
+        const int64_t i = d.src[j];
         d.pos[j] = d.tmp[i];
         d.pos[n + j] = d.tmp[n + i];
         d.pos[2 * n + j] = d.tmp[2 * n + i];
@@ -366,8 +379,10 @@ void launch_sort(const Dev &d, hipStream_t s) {
     hipLaunchKernelGGL(k_sir_tiles, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d);
     hipLaunchKernelGGL(k_sir_top, dim3(1), dim3(kTopThreads), 0, s, d);
     hipLaunchKernelGGL(k_sir_apply, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d);
-    if (d.n > 0)
-        hipLaunchKernelGGL(k_sir_scatter, dim3(((d.n + kThreads - 1) / kThreads + 7) / 8 * 8), dim3(kThreads), 0, s, d);
+    if (d.n > 0) {
+        hipLaunchKernelGGL(k_sir_dest, dim3(grid_for(d.n, 65536)), dim3(kThreads), 0, s, d);
+        hipLaunchKernelGGL(k_sir_gather, dim3(((d.n + kThreads - 1) / kThreads + 7) / 8 * 8), dim3(kThreads), 0, s, d);
+    }
 }
 
 void launch_behave(const Dev &d, hipStream_t s) {
@@ -391,7 +406,7 @@ struct Carver {
 };
 
 struct Layout {
-    size_t ctl, pos, tmp, state, state_t, uid, uid_t, key, rank, count, start, tile, hist, total;
+    size_t ctl, pos, tmp, state, state_t, uid, uid_t, key, rank, src, count, start, tile, hist, total;
 };
 
 bool geometry(const abm_sir_params &p, int64_t &D, double &Lb) {
@@ -434,6 +449,7 @@ bool make_layout(const abm_sir_params &p, int64_t n, int hist_cap, Layout &L, in
     L.uid_t = c.take<uint32_t>(N);
     L.key = c.take<uint32_t>(N);
     L.rank = c.take<uint32_t>(N);
+    L.src = c.take<uint32_t>(N);
     L.count = c.take<uint32_t>((size_t)nbox + 16);
     L.start = c.take<uint32_t>((size_t)nbox + 16);
     L.tile = c.take<uint32_t>((size_t)ntiles);
@@ -541,6 +557,7 @@ extern "C" int abm_sir_create(const abm_sir_params *p, int64_t n, const double *
     d.uid_t = (uint32_t *)(base + L.uid_t);
     d.key = (uint32_t *)(base + L.key);
     d.rank = (uint32_t *)(base + L.rank);
+    d.src = (uint32_t *)(base + L.src);
     d.count = (uint32_t *)(base + L.count);
     d.start = (uint32_t *)(base + L.start);
     d.tile = (uint32_t *)(base + L.tile);
