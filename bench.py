@@ -373,7 +373,36 @@ def bench_apoptosis(args):
                    "agents_start_timed": n0, "agents_end": n1,
                    "removed_per_iteration": (n0 - n1) / args.steps},
     }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host")
+        out["cpu_baseline"] = apoptosis_cpu_baseline(args)
     print(json.dumps(out), flush=True)
+
+
+def apoptosis_cpu_baseline(args):
+    """The oracle on a bounded sample of the same workload: the uniform
+    population at the same density with the same Brownian step, apoptosis
+    parameters and age distribution."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    from oracle import sim as osim
+    from paper_2503_10796_amd import inputs
+    n = args.cpu_sample_agents
+    pos, diam = inputs.at_density(n, seed=1)
+    age = np.random.default_rng(7).integers(0, 100, size=n).astype(np.int32)
+    o = osim.OracleSim(pos, diam, osim.make_params(box_len=15.0, seed=9, brownian_rate=0.005, death_prob=0.033,
+                                                   min_age=87), age=age)
+    o.step(1)
+    n0 = o.n
+    t0 = time.perf_counter()
+    o.step(args.cpu_sample_iters)
+    dt = time.perf_counter() - t0
+    updates = 0.5 * (n0 + o.n) * args.cpu_sample_iters
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": updates / dt, "unit": "agent updates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{n} agents of the same workload, {args.cpu_sample_iters} iterations after one untimed "
+                      f"iteration ({n0} -> {o.n} agents), FP64, OpenMP over agents, {dt:.1f} s"}
 
 
 # Algorithmic bytes of the SIR person kernel per person: position 24, state 1
