@@ -92,8 +92,8 @@ def test_influenza_matches_oracle(abm):
 
 @pytest.mark.parametrize("case", ["one_box", "two_boxes", "faces", "coincident", "certain_infection", "static"])
 def test_edge_cases_match_oracle(abm, case):
-    """Degenerate grids and inputs: a space smaller than four radii (one box
-    per axis), two boxes per axis on the torus (both neighbours are the same
+    """Degenerate grids and inputs: a space smaller than six radii (one box
+    per axis: boxes are three radii long), two boxes per axis on the torus (both neighbours are the same
     box), persons exactly on the faces of the space, persons at identical
     positions, infection probability 1 without recovery, no movement."""
     rng = np.random.default_rng(11)
@@ -102,7 +102,7 @@ def test_edge_cases_match_oracle(abm, case):
     if case == "one_box":
         space, kw = 10.0, {}
     elif case == "two_boxes":
-        space, kw = 14.0, {}
+        space, kw = 22.0, {}
     elif case == "certain_infection":
         space, kw = 40.0, dict(infection_prob=1.0, recovery_prob=0.0)
     elif case == "static":
