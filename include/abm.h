@@ -319,7 +319,8 @@ int abm_mlp_destroy(abm_mlp *m);
 
 /* Fields of abm_sir_query: positions (double, n x 3 interleaved), states
  * (uint8), uids (uint32).  Rows are in the handle's storage order (persons
- * sorted by grid box), the same order for every field of one query state. */
+ * are re-sorted by grid box every few iterations), the same order for every
+ * field between two steps. */
 #define ABM_SIR_POS 0
 #define ABM_SIR_STATE 1
 #define ABM_SIR_UID 2
@@ -362,10 +363,12 @@ int abm_sir_query(abm_sir *s, int field, void *dst, int dst_on_device, int64_t c
 /* Iterations done and persons per state now (host). */
 int abm_sir_counts(abm_sir *s, int64_t *iteration, int64_t counts[3]);
 
-/* Grid of the neighbour search: boxes per axis and box length (>= 2 radius). */
+/* Grid of the neighbour search (an index of the infected persons, rebuilt
+ * every iteration): boxes per axis and box length (>= 2 radius). */
 int abm_sir_grid(abm_sir *s, int64_t *dims, double *box_len);
 
-/* Timing of the person kernel (infection, recovery, movement, binning):
+/* Timing of the person kernel (infection, recovery, movement, binning of the
+ * persons infected after it):
  * with timing on, every iteration brackets it with HIP events on the
  * handle's stream; abm_sir_kernel_time returns the total and the count of the
  * iterations timed since the last call, and resets them. */

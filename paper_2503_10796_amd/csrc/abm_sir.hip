@@ -1,30 +1,36 @@
 // abm_sir.hip -- SIR epidemiology on the GPU (Sec 4.6.3, Algorithms 3-5,
 // Table 4.3) with toroidal or closed space boundaries (Sec 4.4.11).
 //
-// Persons live in a cubic space [0, S]^3.  Their state is kept sorted by the
-// box of a uniform grid whose box length Lb is at least twice the infection
-// radius (three radii where the space allows), so that every person within the radius of a point lies in the
-// point's own box or in the one neighbour box per axis on the side of the
-// box's half the point is in: eight boxes, not 27.  One iteration:
-//   k_sir_behave   per person, in storage order: infection (Algorithm 3) from
-//                  the start-of-iteration states of the eight boxes, recovery
-//                  (Algorithm 4), random step and boundary (Algorithm 5);
-//                  writes the new person in the same order to the temporary
-//                  arrays with the box of its new position and its rank in
-//                  that box (one atomic on the box count); counts per state
+// Persons live in a cubic space [0, S]^3 and are updated in place.  Only
+// infected persons can pass on an infection, so the neighbourhood search of
+// Algorithm 3 runs over an index of the infected persons alone: their
+// start-of-iteration positions, copied in the order of the boxes of a uniform
+// grid whose box length Lb is at least twice the infection radius (three radii
+// where the space allows).  Every infected person within the radius of a point
+// then lies in the point's own box or in the one neighbour box per axis on the
+// side of the box's half the point is in: eight boxes, not 27.  Late in an
+// epidemic nearly all persons have recovered and the index is small.
+// One iteration:
+//   k_sir_behave   per person, in storage order: infection (Algorithm 3)
+//                  against the index, recovery (Algorithm 4), random step and
+//                  boundary (Algorithm 5), written in place; a person infected
+//                  after its behaviours gets the box of its new position and
+//                  its rank in that box (one atomic on the box count); counts
+//                  per state
 //   k_sir_tiles / k_sir_top / k_sir_apply
 //                  exclusive scan of the box counts into box starts (and the
-//                  counts cleared for the next iteration)
-//   k_sir_dest / k_sir_gather
-//                  the source of every slot (slot = box start + rank), then
-//                  every slot gathers its person: the writes of the sorted
-//                  state are contiguous, the scattered part is 4 bytes per
-//                  person
+//                  counts cleared for the next binning)
+//   k_sir_iscatter the new index: every infected person's position to its
+//                  slot (box start + rank)
 //   k_sir_end      iteration counter and the next history slot
-// All of it is captured once into a HIP graph and replayed.  The order of
-// persons inside a box depends on the order of the atomics, but nothing
-// computed depends on it (the infection test is an OR over neighbours, every
-// draw is keyed by the person's uid), so results are deterministic.
+// Every kResortEvery iterations the persons themselves are sorted by box
+// (the same scan, a destination pass and a gather), so that persons next to
+// each other in storage stay close in space and the searches and index
+// writes of a wave touch few lines.  Each of the two iteration forms is
+// captured once into a HIP graph and replayed.  The order of persons inside
+// a box depends on the order of the atomics, but nothing computed depends on
+// it (the infection test is an OR over neighbours, every draw is keyed by the
+// person's uid), so results are deterministic.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -48,6 +54,7 @@ constexpr int kScanTile = 4096;     // boxes per scan tile: 4 rounds of 256 thre
 constexpr int kTopThreads = 1024;   // the single work group of the tile-offset scan
 constexpr int64_t kMaxDims = 1600;  // boxes per axis: D^3 < 2^32
 constexpr int kBehaveGrid = 4096;   // persistent work groups of the person kernel (16 per CU)
+constexpr int kResortEvery = 64;    // iterations between two sorts of the persons by box
 
 struct alignas(64) Ctl {
     int64_t iter;
@@ -61,15 +68,19 @@ struct Dev {
     uint64_t seed;
     uint32_t sim_id;
     Ctl *ctl;
-    double *pos;                 // storage order (sorted by box): x block, y block, z block
-    double *tmp;                 // after the behaviours, in the same order as pos
-    uint8_t *state, *state_t;
-    uint32_t *uid, *uid_t;
-    uint32_t *key, *rank;        // box of the new position, rank within it
-    uint32_t *src;               // person (in the temporary order) of every sorted slot
-    uint32_t *count;             // nbox
-    uint32_t *start;             // nbox + 1
+    double *pos;                 // persons in storage order: x block, y block, z block
+    uint8_t *state;
+    uint32_t *uid;
+    double *tmp;                 // staging of the person sort (and of queries)
+    uint8_t *state_t;
+    uint32_t *uid_t;
+    uint32_t *key, *rank;        // box of a position and rank within it (index, person sort)
+    uint32_t *src;               // person sort: person (in the staging order) of every sorted slot
+    uint32_t *count;             // nbox: binning counters, cleared by the scan
+    uint32_t *start;             // nbox + 1: box starts of the index of infected persons
+    uint32_t *pstart;            // nbox + 1: box starts of the person sort
     uint32_t *tile;              // ntiles: tile sums, then their exclusive prefix
+    double *ipos;                // the index: infected persons' positions in box order (x, y, z per slot)
     unsigned long long *hist;    // hist_cap x 3
 };
 
@@ -104,14 +115,17 @@ __device__ inline double bound(const Dev &d, double v) {
 }
 
 // Algorithm 3's neighbourhood test: an infected person strictly within the
-// radius of (x, y, z) in the start-of-iteration state.  Per axis the own box
-// and the neighbour box on the side of the point's half of it: Lb >= 2 r (1 +
-// 2^-20), so the far side is out of reach with a margin far above the
-// rounding of the box coordinate.
+// radius of (x, y, z) in the start-of-iteration state (the index holds the
+// infected persons only).  Per axis the own box and the neighbour box on the
+// side of the point's half of it: Lb >= 2 r (1 + 2^-20), so the far side is
+// out of reach with a margin far above the rounding of the box coordinate.
+// The starts and ends of the (up to) eight boxes are loaded first, all in
+// flight together, then their entries are scanned.
 __device__ bool infected_near(const Dev &d, double x, double y, double z) {
 #pragma clang fp contract(off)
     const double c[3] = {x, y, z};
-    int nb[3][2], cnt[3];
+    uint32_t nb[3][2];
+    bool two[3];
     for (int a = 0; a < 3; ++a) {
         const int b = box_axis(d, c[a]);
         const double o = c[a] - (double)b * d.Lb;
@@ -123,25 +137,28 @@ __device__ bool infected_near(const Dev &d, double x, double y, double z) {
         } else {
             ok = other >= 0 && other < d.D;
         }
-        nb[a][0] = b;
-        nb[a][1] = other;
-        cnt[a] = ok ? 2 : 1;
+        nb[a][0] = (uint32_t)b;
+        nb[a][1] = ok ? (uint32_t)other : (uint32_t)b;  // a valid box either way; unused unless ok
+        two[a] = ok;
     }
-    const int64_t n = d.n;
-    for (int iz = 0; iz < cnt[2]; ++iz)
-        for (int iy = 0; iy < cnt[1]; ++iy)
-            for (int ix = 0; ix < cnt[0]; ++ix) {
-                const uint32_t box =
-                    (uint32_t)nb[0][ix] + (uint32_t)d.D * ((uint32_t)nb[1][iy] + (uint32_t)d.D * (uint32_t)nb[2][iz]);
-                const uint32_t j0 = d.start[box], j1 = d.start[box + 1];
-                for (uint32_t j = j0; j < j1; ++j) {
-                    if (d.state[j] != kInfected) continue;
-                    const double dx = axis_offset(d, x, d.pos[j]);
-                    const double dy = axis_offset(d, y, d.pos[n + j]);
-                    const double dz = axis_offset(d, z, d.pos[2 * n + j]);
-                    if (fma(dz, dz, fma(dy, dy, dx * dx)) < d.r2) return true;
-                }
-            }
+    uint32_t j0[8], j1[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int ix = k & 1, iy = (k >> 1) & 1, iz = k >> 2;
+        const uint32_t box = nb[0][ix] + (uint32_t)d.D * (nb[1][iy] + (uint32_t)d.D * nb[2][iz]);
+        const bool use = (ix == 0 || two[0]) && (iy == 0 || two[1]) && (iz == 0 || two[2]);
+        j0[k] = d.start[box];
+        const uint32_t e = d.start[box + 1];
+        j1[k] = use ? e : j0[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        for (uint32_t j = j0[k]; j < j1[k]; ++j) {
+            const double dx = axis_offset(d, x, d.ipos[3 * (size_t)j]);
+            const double dy = axis_offset(d, y, d.ipos[3 * (size_t)j + 1]);
+            const double dz = axis_offset(d, z, d.ipos[3 * (size_t)j + 2]);
+            if (fma(dz, dz, fma(dy, dy, dx * dx)) < d.r2) return true;
+        }
     return false;
 }
 
@@ -161,7 +178,25 @@ __device__ inline void count_states(bool active, uint8_t st, uint32_t *cnt) {
     }
 }
 
-// One iteration of the behaviours of every person (Algorithms 3, 4, 5).
+// Persons of one work group in the kernels that run per person in storage
+// order: group b runs on XCD b mod 8, and the groups of XCD k take tiles of
+// the k-th contiguous eighth of the persons in turn.  Between two person
+// sorts storage order follows the boxes, so an XCD's searches and index
+// writes stay in one slab of the space and share its L2.  The grid is a
+// multiple of 8 work groups.
+struct XcdTiles {
+    int64_t lo, hi, first, stride;
+    __device__ XcdTiles(int64_t n) {
+        const int64_t chunk = ((n + 7) / 8 + kThreads - 1) / kThreads * kThreads;
+        lo = (int64_t)(blockIdx.x & 7) * chunk;
+        hi = lo + chunk < n ? lo + chunk : n;
+        first = lo + (int64_t)(blockIdx.x >> 3) * kThreads;
+        stride = (int64_t)(gridDim.x >> 3) * kThreads;
+    }
+};
+
+// One iteration of the behaviours of every person (Algorithms 3, 4, 5), in
+// place: the search reads the index, never the persons' arrays.
 __global__ __launch_bounds__(kThreads) void k_sir_behave(Dev d) {
 #pragma clang fp contract(off)
     __shared__ uint32_t cnt[3];
@@ -169,10 +204,10 @@ __global__ __launch_bounds__(kThreads) void k_sir_behave(Dev d) {
     __syncthreads();
     const int64_t iter = d.ctl->iter;
     const int64_t n = d.n;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < n; base += stride) {
+    const XcdTiles tl(n);
+    for (int64_t base = tl.first; base < tl.hi; base += tl.stride) {
         const int64_t i = base + threadIdx.x;
-        const bool active = i < n;
+        const bool active = i < tl.hi;
         uint8_t st = 0;
         if (active) {
             const double x = d.pos[i], y = d.pos[n + i], z = d.pos[2 * n + i];
@@ -194,14 +229,15 @@ __global__ __launch_bounds__(kThreads) void k_sir_behave(Dev d) {
             const double nx = bound(d, x + (v[0] / norm) * d.speed);
             const double ny = bound(d, y + (v[1] / norm) * d.speed);
             const double nz = bound(d, z + (v[2] / norm) * d.speed);
-            const uint32_t k = box_key(d, nx, ny, nz);
-            d.rank[i] = atomicAdd(&d.count[k], 1u);
-            d.key[i] = k;
-            d.tmp[i] = nx;
-            d.tmp[n + i] = ny;
-            d.tmp[2 * n + i] = nz;
-            d.state_t[i] = st;
-            d.uid_t[i] = u;
+            if (st == kInfected) {  // into the next iteration's index
+                const uint32_t k = box_key(d, nx, ny, nz);
+                d.rank[i] = atomicAdd(&d.count[k], 1u);
+                d.key[i] = k;
+            }
+            d.pos[i] = nx;
+            d.pos[n + i] = ny;
+            d.pos[2 * n + i] = nz;
+            d.state[i] = st;
         }
         count_states(active, st, cnt);
     }
@@ -210,7 +246,43 @@ __global__ __launch_bounds__(kThreads) void k_sir_behave(Dev d) {
         atomicAdd(&d.hist[(iter % d.hist_cap) * 3 + threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
 }
 
-// Box and rank of every person of the temporary arrays (initial sort).
+// Box and rank of every infected person (the index at creation).
+__global__ __launch_bounds__(kThreads) void k_sir_ibin(Dev d) {
+    const int64_t n = d.n;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        if (d.state[i] != kInfected) continue;
+        const uint32_t k = box_key(d, d.pos[i], d.pos[n + i], d.pos[2 * n + i]);
+        d.rank[i] = atomicAdd(&d.count[k], 1u);
+        d.key[i] = k;
+    }
+}
+
+// Every infected person's position to its slot of the index.
+__global__ __launch_bounds__(kThreads) void k_sir_iscatter(Dev d) {
+    const int64_t n = d.n;
+    const XcdTiles tl(n);
+    for (int64_t i = tl.first + threadIdx.x; i < tl.hi; i += tl.stride) {
+        if (d.state[i] != kInfected) continue;
+        const size_t j = (size_t)d.start[d.key[i]] + d.rank[i];
+        d.ipos[3 * j] = d.pos[i];
+        d.ipos[3 * j + 1] = d.pos[n + i];
+        d.ipos[3 * j + 2] = d.pos[2 * n + i];
+    }
+}
+
+// The persons into the staging arrays (before a person sort).
+__global__ __launch_bounds__(kThreads) void k_sir_stash(Dev d) {
+    const int64_t n = d.n;
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        d.tmp[i] = d.pos[i];
+        d.tmp[n + i] = d.pos[n + i];
+        d.tmp[2 * n + i] = d.pos[2 * n + i];
+        d.state_t[i] = d.state[i];
+        d.uid_t[i] = d.uid[i];
+    }
+}
+
+// Box and rank of every person of the staging arrays (person sort).
 __global__ __launch_bounds__(kThreads) void k_sir_bin(Dev d) {
     const int64_t n = d.n;
     for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
@@ -242,8 +314,9 @@ __global__ __launch_bounds__(kThreads) void k_sir_tiles(Dev d) {
     if (threadIdx.x == 0) d.tile[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-// Exclusive prefix of the tile sums, in place (one work group).
-__global__ __launch_bounds__(kTopThreads) void k_sir_top(Dev d) {
+// Exclusive prefix of the tile sums, in place (one work group); the end of
+// the last box is the total.
+__global__ __launch_bounds__(kTopThreads) void k_sir_top(Dev d, uint32_t *start) {
     __shared__ uint32_t sh[kTopThreads / 64];
     __shared__ uint32_t carry_sh;
     if (threadIdx.x == 0) carry_sh = 0;
@@ -270,13 +343,13 @@ __global__ __launch_bounds__(kTopThreads) void k_sir_top(Dev d) {
         if (threadIdx.x == 0) carry_sh = carry + total;
         __syncthreads();
     }
-    if (threadIdx.x == 0) d.start[d.nbox] = (uint32_t)d.n;
+    if (threadIdx.x == 0) start[d.nbox] = carry_sh;
 }
 
 // Box starts of one tile (its offset plus the exclusive prefix of its
 // counts), in four rounds of 1,024 boxes with 16-byte loads and stores; the
 // counts are cleared for the next binning.
-__global__ __launch_bounds__(kThreads) void k_sir_apply(Dev d) {
+__global__ __launch_bounds__(kThreads) void k_sir_apply(Dev d, uint32_t *start) {
     __shared__ uint32_t sh[kThreads / 64];
     const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
     uint32_t carry = d.tile[blockIdx.x];
@@ -295,13 +368,13 @@ __global__ __launch_bounds__(kThreads) void k_sir_apply(Dev d) {
         const uint32_t pre = carry + block_excl_scan_4(v, sh, total);
         const uint32_t s0 = pre, s1 = s0 + v[0], s2 = s1 + v[1], s3 = s2 + v[2];
         if (full) {
-            *reinterpret_cast<uint4 *>(d.start + b) = make_uint4(s0, s1, s2, s3);
+            *reinterpret_cast<uint4 *>(start + b) = make_uint4(s0, s1, s2, s3);
             *reinterpret_cast<uint4 *>(d.count + b) = make_uint4(0u, 0u, 0u, 0u);
         } else {
             const uint32_t sv[4] = {s0, s1, s2, s3};
             for (int k = 0; k < 4; ++k)
                 if (b + k < d.nbox) {
-                    d.start[b + k] = sv[k];
+                    start[b + k] = sv[k];
                     d.count[b + k] = 0u;
                 }
         }
@@ -309,18 +382,17 @@ __global__ __launch_bounds__(kThreads) void k_sir_apply(Dev d) {
     }
 }
 
-// Every person to its slot in box order.
-// The source of every slot of the new box order.
+// Person sort: the source of every slot of the new box order.
 __global__ __launch_bounds__(kThreads) void k_sir_dest(Dev d) {
     const int64_t n = d.n;
     for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-        d.src[(int64_t)d.start[d.key[i]] + d.rank[i]] = (uint32_t)i;
+        d.src[(int64_t)d.pstart[d.key[i]] + d.rank[i]] = (uint32_t)i;
 }
 
-// Every slot gathers its person from the temporary arrays.  One slot per
-// thread; work group b runs on XCD b mod 8 and the groups of XCD k take the
-// k-th contiguous eighth of the slots in order, so that the lines of the
-// temporary arrays that neighbouring slots read (their persons came from
+// Person sort: every slot gathers its person from the staging arrays.  One
+// slot per thread; work group b runs on XCD b mod 8 and the groups of XCD k
+// take the k-th contiguous eighth of the slots in order, so that the lines of
+// the staging arrays that neighbouring slots read (their persons came from
 // nearby boxes) stay in one L2.
 __global__ __launch_bounds__(kThreads) void k_sir_gather(Dev d) {
     const int64_t n = d.n;
@@ -373,12 +445,26 @@ inline int grid_for(int64_t n, int cap) {
     int64_t g = (n + kThreads - 1) / kThreads;
     return (int)(g < 1 ? 1 : (g > cap ? cap : g));
 }
+// The same rounded up to a multiple of 8 work groups (XcdTiles kernels).
+inline int grid_for_xcd(int64_t n, int cap) { return (grid_for(n, cap) + 7) / 8 * 8; }
 
-// The grid scan and the scatter (shared by creation and every iteration).
-void launch_sort(const Dev &d, hipStream_t s) {
+// Exclusive scan of the box counts into `start` (the counts are cleared).
+void launch_scan(const Dev &d, uint32_t *start, hipStream_t s) {
     hipLaunchKernelGGL(k_sir_tiles, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d);
-    hipLaunchKernelGGL(k_sir_top, dim3(1), dim3(kTopThreads), 0, s, d);
-    hipLaunchKernelGGL(k_sir_apply, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d);
+    hipLaunchKernelGGL(k_sir_top, dim3(1), dim3(kTopThreads), 0, s, d, start);
+    hipLaunchKernelGGL(k_sir_apply, dim3((unsigned)d.ntiles), dim3(kThreads), 0, s, d, start);
+}
+
+// The index of infected persons from their binning.
+void launch_index(const Dev &d, hipStream_t s) {
+    launch_scan(d, d.start, s);
+    if (d.n > 0) hipLaunchKernelGGL(k_sir_iscatter, dim3(grid_for_xcd(d.n, 65536)), dim3(kThreads), 0, s, d);
+}
+
+// The persons of the staging arrays into pos / state / uid in box order.
+void launch_person_sort(const Dev &d, hipStream_t s) {
+    if (d.n > 0) hipLaunchKernelGGL(k_sir_bin, dim3(grid_for(d.n, 65536)), dim3(kThreads), 0, s, d);
+    launch_scan(d, d.pstart, s);
     if (d.n > 0) {
         hipLaunchKernelGGL(k_sir_dest, dim3(grid_for(d.n, 65536)), dim3(kThreads), 0, s, d);
         hipLaunchKernelGGL(k_sir_gather, dim3(((d.n + kThreads - 1) / kThreads + 7) / 8 * 8), dim3(kThreads), 0, s, d);
@@ -386,11 +472,17 @@ void launch_sort(const Dev &d, hipStream_t s) {
 }
 
 void launch_behave(const Dev &d, hipStream_t s) {
-    if (d.n > 0) hipLaunchKernelGGL(k_sir_behave, dim3(grid_for(d.n, kBehaveGrid)), dim3(kThreads), 0, s, d);
+    if (d.n > 0) hipLaunchKernelGGL(k_sir_behave, dim3(grid_for_xcd(d.n, kBehaveGrid)), dim3(kThreads), 0, s, d);
 }
 
-void launch_rest(const Dev &d, hipStream_t s) {
-    launch_sort(d, s);
+// Everything after the person kernel; with `resort` the persons are sorted
+// by box at the end.
+void launch_rest(const Dev &d, bool resort, hipStream_t s) {
+    launch_index(d, s);
+    if (resort && d.n > 0) {
+        hipLaunchKernelGGL(k_sir_stash, dim3(grid_for(d.n, 65536)), dim3(kThreads), 0, s, d);
+        launch_person_sort(d, s);
+    }
     hipLaunchKernelGGL(k_sir_end, dim3(1), dim3(1), 0, s, d);
 }
 
@@ -406,7 +498,7 @@ struct Carver {
 };
 
 struct Layout {
-    size_t ctl, pos, tmp, state, state_t, uid, uid_t, key, rank, src, count, start, tile, hist, total;
+    size_t ctl, pos, tmp, state, state_t, uid, uid_t, key, rank, src, count, start, pstart, tile, ipos, hist, total;
 };
 
 bool geometry(const abm_sir_params &p, int64_t &D, double &Lb) {
@@ -457,7 +549,9 @@ bool make_layout(const abm_sir_params &p, int64_t n, int hist_cap, Layout &L, in
     L.src = c.take<uint32_t>(N);
     L.count = c.take<uint32_t>((size_t)nbox + 16);
     L.start = c.take<uint32_t>((size_t)nbox + 16);
+    L.pstart = c.take<uint32_t>((size_t)nbox + 16);
     L.tile = c.take<uint32_t>((size_t)ntiles);
+    L.ipos = c.take<double>(3 * N);
     L.hist = c.take<unsigned long long>((size_t)hist_cap * 3);
     L.total = c.off + 256;
     return true;
@@ -474,7 +568,9 @@ struct abm_sir {
     sirk::Dev d;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t exec[3] = {};  // 0: a whole iteration; 1: the person kernel; 2: the rest
+    // 0: a whole iteration, 1: the person kernel, 2: the rest; 3 and 4: the
+    // same as 0 and 2 with the person sort at the end
+    hipGraphExec_t exec[5] = {};
     int64_t iter = 0;
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -492,8 +588,9 @@ static int capture(abm_sir *s, int part) {
     if (s->exec[part]) return ABM_OK;
     if (!s->cap_stream) SIRCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     SIRCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-    if (part == 0 || part == 1) sirk::launch_behave(s->d, s->cap_stream);
-    if (part == 0 || part == 2) sirk::launch_rest(s->d, s->cap_stream);
+    if (part == 0 || part == 1 || part == 3) sirk::launch_behave(s->d, s->cap_stream);
+    if (part == 0 || part == 2) sirk::launch_rest(s->d, false, s->cap_stream);
+    if (part == 3 || part == 4) sirk::launch_rest(s->d, true, s->cap_stream);
     hipGraph_t g;
     hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
     if (e != hipSuccess) return set_error(ABM_ERR_HIP, hipGetErrorString(e));
@@ -565,7 +662,9 @@ extern "C" int abm_sir_create(const abm_sir_params *p, int64_t n, const double *
     d.src = (uint32_t *)(base + L.src);
     d.count = (uint32_t *)(base + L.count);
     d.start = (uint32_t *)(base + L.start);
+    d.pstart = (uint32_t *)(base + L.pstart);
     d.tile = (uint32_t *)(base + L.tile);
+    d.ipos = (double *)(base + L.ipos);
     d.hist = (unsigned long long *)(base + L.hist);
     s->stream = (hipStream_t)hip_stream;
     hipStream_t st = s->stream;
@@ -586,8 +685,10 @@ extern "C" int abm_sir_create(const abm_sir_params *p, int64_t n, const double *
     hipLaunchKernelGGL(sirk::k_sir_zero, dim3(sirk::grid_for(2 * (int64_t)hist_cap * 3, 65536)), dim3(sirk::kThreads), 0, st,
                        (uint32_t *)d.hist, 2 * (int64_t)hist_cap * 3);
     hipLaunchKernelGGL(sirk::k_sir_zero, dim3(1), dim3(64), 0, st, (uint32_t *)d.ctl, (int64_t)(sizeof(sirk::Ctl) / 4));
-    if (n > 0) hipLaunchKernelGGL(sirk::k_sir_bin, dim3(sirk::grid_for(n, 65536)), dim3(sirk::kThreads), 0, st, d);
-    sirk::launch_sort(d, st);
+    // persons sorted by box, then the index of the infected ones
+    sirk::launch_person_sort(d, st);
+    if (n > 0) hipLaunchKernelGGL(sirk::k_sir_ibin, dim3(sirk::grid_for(n, 65536)), dim3(sirk::kThreads), 0, st, d);
+    sirk::launch_index(d, st);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return undo(set_error(ABM_ERR_HIP, hipGetErrorString(e)));
@@ -600,8 +701,11 @@ extern "C" int abm_sir_step(abm_sir *s, int n_iter, int64_t *counts) {
     if (!s || n_iter < 0) return set_error(ABM_ERR_ARG, "bad handle or iteration count");
     if (n_iter == 0) return ABM_OK;
     int rc = s->timing ? capture(s, 1) : capture(s, 0);
-    if (!rc && s->timing) rc = capture(s, 2);
+    if (!rc) rc = s->timing ? capture(s, 2) : capture(s, 3);
+    if (!rc && s->timing) rc = capture(s, 4);
     if (rc) return rc;
+    // iteration t ends with the person sort when t + 1 is a multiple of kResortEvery
+    auto resort = [&](int64_t t) { return (t + 1) % sirk::kResortEvery == 0; };
     const int cap = s->d.hist_cap;
     std::vector<unsigned long long> h;
     for (int done = 0; done < n_iter;) {
@@ -618,7 +722,7 @@ extern "C" int abm_sir_step(abm_sir *s, int n_iter, int64_t *counts) {
                 SIRCHK(hipEventRecord(s->ev[2 * it], s->stream));
                 SIRCHK(hipGraphLaunch(s->exec[1], s->stream));
                 SIRCHK(hipEventRecord(s->ev[2 * it + 1], s->stream));
-                SIRCHK(hipGraphLaunch(s->exec[2], s->stream));
+                SIRCHK(hipGraphLaunch(s->exec[resort(s->iter + it) ? 4 : 2], s->stream));
             }
             SIRCHK(hipStreamSynchronize(s->stream));
             for (int it = 0; it < chunk; ++it) {
@@ -628,7 +732,7 @@ extern "C" int abm_sir_step(abm_sir *s, int n_iter, int64_t *counts) {
             }
             s->n_timed += chunk;
         } else {
-            for (int it = 0; it < chunk; ++it) SIRCHK(hipGraphLaunch(s->exec[0], s->stream));
+            for (int it = 0; it < chunk; ++it) SIRCHK(hipGraphLaunch(s->exec[resort(s->iter + it) ? 3 : 0], s->stream));
         }
         if (counts) {
             h.resize((size_t)cap * 3);
