@@ -265,3 +265,34 @@ def test_counts_through_a_short_history_ring(abm):
     assert np.array_equal(hs, o.step(32))
     with pytest.raises(abm.AbmError):  # a history needs at least two slots
         abm.Sir(gp, pos, st, hist_cap=1)
+
+
+def _box_keys(pos, dims, box_len):
+    """Linear box of every position (x fastest), by the grid's FP64 division."""
+    b = np.clip(np.floor(pos / box_len), 0, dims - 1).astype(np.int64)
+    return b[:, 0] + dims * (b[:, 1] + dims * b[:, 2])
+
+
+def test_persons_are_stored_in_box_order_after_each_person_sort(abm):
+    """Results do not depend on the storage order, so a broken person sort
+    would only cost speed; this checks the order itself.  Right after
+    creation and after the sort that ends every 64th iteration, the box
+    keys of the stored persons never decrease, and the persons are the same
+    uids as the oracle's with the same states and positions."""
+    cfg = dict(inputs.SIR_MEASLES)
+    pos, st = inputs.sir_population(6000, 60, 150.0, seed=14)
+    gp, op = _params(abm, cfg, 14, space=150.0)
+    g = abm.Sir(gp, pos, st, hist_cap=8)
+    o = osir.OracleSIR(pos, st, op)
+    dims, box_len = g.grid()
+    assert dims > 4
+    assert np.all(np.diff(_box_keys(g.query(abm.SIR_POS), dims, box_len)) >= 0), "not in box order at creation"
+    for k in range(2):
+        g.step(64)
+        o.step(64)
+        keys = _box_keys(g.query(abm.SIR_POS), dims, box_len)
+        assert np.all(np.diff(keys) >= 0), f"not in box order after iteration {64 * (k + 1) - 1}"
+        _same_state(abm, g, o, f"after {64 * (k + 1)} iterations")
+    g.step(5)  # between two sorts the persons drift out of order
+    o.step(5)
+    _same_state(abm, g, o, "after 133 iterations")
