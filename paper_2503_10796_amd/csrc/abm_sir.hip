@@ -196,8 +196,11 @@ struct XcdTiles {
 };
 
 // One iteration of the behaviours of every person (Algorithms 3, 4, 5), in
-// place: the search reads the index, never the persons' arrays.
-__global__ __launch_bounds__(kThreads) void k_sir_behave(Dev d) {
+// place: the search reads the index, never the persons' arrays.  Eight
+// waves per SIMD (the launch bound keeps the scalar registers below the
+// limit of seven): the early iterations wait on the searches' loads, and
+// more waves hide more of that latency.
+__global__ __launch_bounds__(kThreads, 8) void k_sir_behave(Dev d) {
 #pragma clang fp contract(off)
     __shared__ uint32_t cnt[3];
     if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
