@@ -504,6 +504,16 @@ __device__ inline void acc_reduce_streams(Acc &a, int g) {
 
 // Box-wise path of the production sweep: candidates per wave and chunk.
 constexpr int kDenseChunk = 192;
+// Targets per sub-pass: the up to 64 targets of a pass are grouped by the
+// octant of their box, and each group of kSubTargets tests only the
+// candidates within reach of its own bounding box.
+constexpr int kSubTargets = 16;
+// Margin of that cull in U units, above the FP32 rounding of the distance
+// from a candidate to the box (about 2^-22 relative of at most 2^30 U).
+constexpr float kCullMargin = 1024.0f;
+// Target slot word: bits 0-30 the slot, bit 31 a target without pairs
+// (static, or past the pass's targets).
+constexpr uint32_t kTsSlot = 0x7fffffffu, kTsIdle = 0x80000000u;
 // Candidates per box (its 27-box neighbourhood) beyond which the box-wise
 // path leaves the box's targets to the FP64 path: below it the packed error
 // and force-sum words of a target cannot overflow.
@@ -513,17 +523,17 @@ constexpr uint32_t kDenseMaxCand = 16000;
 // (2^-24 units, rounded up) << 32 | lower bound of sum |F_N| (2^-12 units).
 constexpr int kDenseWords = 5;
 
-// Drain of the box-wise path: lane l takes queue entry l (target lane |
+// Drain of the box-wise path: lane l takes queue entry l (target index |
 // candidate index in the staged chunk << 6) and adds the pair's contact
 // force, counts and bounds to the target's LDS accumulators.  Candidates are
-// staged in the frame of the targets' box; cs holds their slots (the target
-// of lane tl has slot tslot0 + tl: a target is not its own candidate).
+// staged in the frame of the targets' box; cs holds their slots and ts the
+// targets' (low 31 bits: a target is not its own candidate).
 __device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const Pay *ob, const Pay *buf, const uint32_t *cs,
-                                   uint32_t tslot0, unsigned long long *acc, float kU, float gU) {
+                                   const uint32_t *ts, unsigned long long *acc, float kU, float gU) {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t ent = lane < cnt ? qw[lane] : 0u;
     const uint32_t tl = ent & 63u, j = ent >> 6;
-    const bool valid = lane < cnt && cs[j] != tslot0 + tl;
+    const bool valid = lane < cnt && cs[j] != (ts[tl] & kTsSlot);
     const Pay own = ob[tl];
     const Pay c = buf[j];
     const double dx = (double)(own.x - c.x), dy = (double)(own.y - c.y), dz = (double)(own.z - c.z);
@@ -556,12 +566,15 @@ constexpr int kDensePassGroups = 8;  // pass p (64 targets) of a box is in group
 
 struct DenseWave {
     Pay buf[kDenseChunk];                      // staged candidates, in the frame of the targets' box
-    Pay ob[64];                                // the targets of the pass
+    Pay ob[64];                                // the targets of the pass, grouped by octant
     uint32_t cs[kDenseChunk];                  // slots of the staged candidates
+    uint32_t ts[64];                           // slot word of each target (kTsSlot, kTsIdle)
     unsigned long long acc[kDenseWords * 64];  // per target, see kDenseWords
     uint32_t pre[28];                          // prefix of the candidate counts of the 27 boxes (entry 27: total)
     uint32_t src[27];                          // first slot of each of the 27 boxes
-    uint32_t queue[2 * 64];                    // survivors: target lane | staged candidate << 6
+    uint32_t queue[2 * 64];                    // survivors: target index | staged candidate << 6
+    int32_t sbox[64 / kSubTargets][8];         // per sub-pass: min x, y, z, max x, y, z, largest radius (bits)
+    uint8_t cl[kDenseChunk];                   // the chunk's candidates within a sub-pass's reach
 };
 
 // The passes of group pg of box (gx, gy, gz): targets pg * 64 .. pg * 64 + 63,
@@ -578,7 +591,9 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
     const float kU = S.kU, gU = S.gU;
     const int64_t lin = linear_box(gx, gy, gz, S.dims);
     Pay *buf = W.buf, *ob = W.ob;
-    uint32_t *cs = W.cs, *pre = W.pre, *src = W.src, *qw = W.queue;
+    uint32_t *cs = W.cs, *pre = W.pre, *src = W.src, *qw = W.queue, *ts = W.ts;
+    uint8_t *cl = W.cl;
+    int32_t(*sbox)[8] = W.sbox;
     unsigned long long *acc = W.acc;
     // prefix of the candidate counts of the 27 boxes (lane b: box b, x fastest)
     uint32_t nnb = 0, srcb = 0;
@@ -602,32 +617,62 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
     if (lane < 27) src[lane] = srcb;
     __builtin_amdgcn_wave_barrier();
     for (uint32_t p0 = (uint32_t)pg * 64u; p0 < cnt; p0 += 64u * (uint32_t)kDensePassGroups) {
-        // gsz targets in this pass, 64 / gsz streams each (the lanes past
-        // gsz * nstream idle); the queue needs no cross-lane sums, so any
-        // target count fills the lanes
-        const int gsz = cnt - p0 < 64u ? (int)(cnt - p0) : 64;
-        const int nstream = 64 / gsz;
-        const int tl = lane % gsz, sid = lane / gsz;
-        const bool tv = sid < nstream;
+        const int gsz = cnt - p0 < 64u ? (int)(cnt - p0) : 64;  // targets in this pass
+        const bool tv = lane < gsz;
         const uint32_t tslot0 = tbeg + p0;
-        const uint32_t slot = tslot0 + (tv ? (uint32_t)tl : 0u);
+        const uint32_t slot = tslot0 + (tv ? (uint32_t)lane : 0u);
         const int64_t i = d.sorted_idx[slot];
         const uint8_t fl = d.flags[lp][i];
         const bool stat = tv && S.detect_static && (fl & kStatic);
         const bool act = tv && !stat;
-        if (stat && sid == 0) skip_static<false>(d, S, i, P, lp, fl, lin);
+        if (stat) skip_static<false>(d, S, i, P, lp, fl, lin);
         if (huge) {
-            if (act && sid == 0) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
+            if (act) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
             continue;
         }
         const Pay own = d.payload[slot];
-        __builtin_amdgcn_wave_barrier();
-        if (sid == 0) {
-            ob[tl] = own;
-            for (int w = 0; w < kDenseWords; ++w) acc[kDenseWords * tl + w] = 0;
+        // targets grouped by the octant of their box (the top bit of each
+        // box-relative coordinate; only the grouping depends on it)
+        const int oct = tv ? (int)((((uint32_t)own.x >> 27) & 1u) | (((uint32_t)own.y >> 26) & 2u) |
+                                   (((uint32_t)own.z >> 25) & 4u))
+                           : 8;
+        uint32_t gpos = 0;
+        for (int k = 0; k < 8; ++k) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(oct == k);
+            if (oct > k) gpos += (uint32_t)__popcll(m);
+            if (oct == k) gpos += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         }
         __builtin_amdgcn_wave_barrier();
-        const float owg = own.r + kReach;
+        if (tv) {
+            ob[gpos] = own;
+            ts[gpos] = slot | (act ? 0u : kTsIdle);
+            for (int w = 0; w < kDenseWords; ++w) acc[kDenseWords * gpos + w] = 0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // bounding box and largest radius of every sub-pass's targets (lane l:
+        // grouped target l; lanes past the targets repeat the last one)
+        const int nsub = (gsz + kSubTargets - 1) / kSubTargets;
+        {
+            const Pay t = ob[tv ? lane : (uint32_t)(gsz - 1)];
+            int32_t lo[3] = {t.x, t.y, t.z}, hi[3] = {t.x, t.y, t.z};
+            float rr = t.r;
+            for (int off = 1; off < kSubTargets; off <<= 1) {
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = min(lo[a], __shfl_xor(lo[a], off));
+                    hi[a] = max(hi[a], __shfl_xor(hi[a], off));
+                }
+                rr = fmaxf(rr, __shfl_xor(rr, off));
+            }
+            const int sp = lane / kSubTargets;
+            if (lane % kSubTargets == 0 && sp < nsub) {
+                for (int a = 0; a < 3; ++a) {
+                    sbox[sp][a] = lo[a];
+                    sbox[sp][3 + a] = hi[a];
+                }
+                sbox[sp][6] = __float_as_int(rr);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
         uint32_t qn = 0;  // wave-uniform queue fill
         for (uint32_t cb0 = 0; cb0 < T; cb0 += kDenseChunk) {
             const uint32_t mc = T - cb0 < (uint32_t)kDenseChunk ? T - cb0 : (uint32_t)kDenseChunk;
@@ -670,42 +715,83 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            for (uint32_t j0 = 0; j0 < mc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
-                const uint32_t j = j0 + (uint32_t)sid;
-                const bool in = j < mc && act;
-                const Pay cc = buf[j < mc ? j : 0u];
-                const float ddx = (float)(own.x - cc.x), ddy = (float)(own.y - cc.y), ddz = (float)(own.z - cc.z);
-                const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
-                const float sg = owg + cc.r;
-                const bool hit = in && d2 < sg * sg;
-                // (all lanes test one candidate here, so many trips have no
-                // survivor at all: the append is skipped on those)
-                const uint64_t mh = __builtin_amdgcn_ballot_w64(hit);
-                if (mh) {
-                    if (hit)
-                        qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(mh >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mh, 0u))] =
-                            (uint32_t)tl | (j << 6);
-                    qn += (uint32_t)__popcll(mh);
-                    if (qn >= 64) {
-                        __builtin_amdgcn_wave_barrier();
-                        drain_dense(qw, 64u, ob, buf, cs, tslot0, acc, kU, gU);
-                        __builtin_amdgcn_wave_barrier();
-                        qn -= 64;
-                        if ((uint32_t)lane < qn) qw[lane] = qw[64 + lane];
-                        __builtin_amdgcn_wave_barrier();
+            for (int sp = 0; sp < nsub; ++sp) {
+                const int sb = sp * kSubTargets;
+                const int sgsz = gsz - sb < kSubTargets ? gsz - sb : kSubTargets;
+                const int nstream = 64 / sgsz;
+                const int tl = sb + lane % sgsz, sid = lane / sgsz;
+                // the chunk's candidates within reach of the sub-pass's box: a
+                // pair test below can succeed only if the candidate is closer
+                // to some target than that target's radius + its own + kReach
+                const int32_t b0x = sbox[sp][0], b0y = sbox[sp][1], b0z = sbox[sp][2];
+                const int32_t b1x = sbox[sp][3], b1y = sbox[sp][4], b1z = sbox[sp][5];
+                const float rreach = __int_as_float(sbox[sp][6]) + (kReach + kCullMargin);
+                uint32_t nc = 0;  // wave-uniform
+#pragma unroll
+                for (int h = 0; h < 3; ++h) {
+                    const uint32_t q = (uint32_t)lane + 64u * (uint32_t)h;
+                    bool keep = false;
+                    if (q < mc) {
+                        const Pay c = buf[q];
+                        const float ex = (float)max(max(b0x - c.x, c.x - b1x), 0);
+                        const float ey = (float)max(max(b0y - c.y, c.y - b1y), 0);
+                        const float ez = (float)max(max(b0z - c.z, c.z - b1z), 0);
+                        const float rc = rreach + c.r;
+                        keep = fmaf(ez, ez, fmaf(ey, ey, ex * ex)) < rc * rc;
+                    }
+                    const uint64_t km = __builtin_amdgcn_ballot_w64(keep);
+                    if (keep)
+                        cl[nc + __builtin_amdgcn_mbcnt_hi((uint32_t)(km >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)km, 0u))] = (uint8_t)q;
+                    nc += (uint32_t)__popcll(km);
+                }
+                __builtin_amdgcn_wave_barrier();
+                const Pay ot = ob[tl];
+                const bool at = sid < nstream && !(ts[tl] & kTsIdle);
+                const float owg = ot.r + kReach;
+                for (uint32_t j0 = 0; j0 < nc; j0 += (uint32_t)nstream) {  // same trip count on all lanes
+                    const uint32_t jj = j0 + (uint32_t)sid;
+                    const bool in = jj < nc && at;
+                    const uint32_t j = cl[jj < nc ? jj : 0u];
+                    const Pay cc = buf[j];
+                    const float ddx = (float)(ot.x - cc.x), ddy = (float)(ot.y - cc.y), ddz = (float)(ot.z - cc.z);
+                    const float d2 = fmaf(ddz, ddz, fmaf(ddy, ddy, ddx * ddx));
+                    const float sg = owg + cc.r;
+                    const bool hit = in && d2 < sg * sg;
+                    // (many trips have no survivor at all: the append is skipped on those)
+                    const uint64_t mh = __builtin_amdgcn_ballot_w64(hit);
+                    if (mh) {
+                        if (hit)
+                            qw[qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(mh >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)mh, 0u))] =
+                                (uint32_t)tl | (j << 6);
+                        qn += (uint32_t)__popcll(mh);
+                        if (qn >= 64) {
+                            __builtin_amdgcn_wave_barrier();
+                            drain_dense(qw, 64u, ob, buf, cs, ts, acc, kU, gU);
+                            __builtin_amdgcn_wave_barrier();
+                            qn -= 64;
+                            if ((uint32_t)lane < qn) qw[lane] = qw[64 + lane];
+                            __builtin_amdgcn_wave_barrier();
+                        }
                     }
                 }
+                __builtin_amdgcn_wave_barrier();  // the next sub-pass rewrites cl
             }
             if (qn) {  // the chunk is restaged next: drain the rest now
                 __builtin_amdgcn_wave_barrier();
-                drain_dense(qw, qn, ob, buf, cs, tslot0, acc, kU, gU);
+                drain_dense(qw, qn, ob, buf, cs, ts, acc, kU, gU);
                 qn = 0;
             }
             __builtin_amdgcn_wave_barrier();
         }
-        if (!act || sid != 0) continue;
-        const unsigned long long *a = acc + kDenseWords * tl;
+        // commit: lane l takes grouped target l
+        if (!tv) continue;
+        const uint32_t tw = ts[lane];
+        if (tw & kTsIdle) continue;
+        const int64_t ic = d.sorted_idx[tw & kTsSlot];
+        const uint8_t flc = d.flags[lp][ic];
+        const unsigned long long *a = acc + kDenseWords * lane;
         const unsigned long long ac = a[3], am = a[4];
         bool unc = (ac >> 32) != 0;
         if (!unc) {
@@ -714,12 +800,12 @@ __device__ void sweep_box_dense(const Dev &d, const SimDesc &S, DenseWave &W, in
             const double fz = (double)(long long)a[2] * kFixUnit;
             const int nc = (int)(uint32_t)ac;
             if (fp32_certified(S, fx, fy, fz, (double)(am >> 32) * 0x1.0p-24, (double)(uint32_t)am * 0x1.0p-12))
-                commit_agent<false>(d, S, i, P, lp, fl, d.pos[P][i], d.pos[P][A + i], d.pos[P][2 * A + i], fx, fy, fz,
-                                    nc, 0, nc, m, lin);
+                commit_agent<false>(d, S, ic, P, lp, flc, d.pos[P][ic], d.pos[P][A + ic], d.pos[P][2 * A + ic], fx, fy,
+                                    fz, nc, 0, nc, m, lin);
             else
                 unc = true;
         }
-        if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)i;
+        if (unc) d.fix_list[atomicAdd(&d.ctl->n_fix, 1u)] = (uint32_t)ic;
     }
 }
 
