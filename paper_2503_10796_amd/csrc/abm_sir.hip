@@ -120,7 +120,9 @@ __device__ inline double bound(const Dev &d, double v) {
 // side of the point's half of it: Lb >= 2 r (1 + 2^-20), so the far side is
 // out of reach with a margin far above the rounding of the box coordinate.
 // The starts and ends of the (up to) eight boxes are loaded first, all in
-// flight together, then their entries are scanned.
+// flight together; then the boxes are scanned two at a time in lock-step, so
+// that two entry loads are in flight (more cost the occupancy that hides the
+// latency of the searches).
 __device__ bool infected_near(const Dev &d, double x, double y, double z) {
 #pragma clang fp contract(off)
     const double c[3] = {x, y, z};
@@ -152,13 +154,22 @@ __device__ bool infected_near(const Dev &d, double x, double y, double z) {
         j1[k] = use ? e : j0[k];
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        for (uint32_t j = j0[k]; j < j1[k]; ++j) {
-            const double dx = axis_offset(d, x, d.ipos[3 * (size_t)j]);
-            const double dy = axis_offset(d, y, d.ipos[3 * (size_t)j + 1]);
-            const double dz = axis_offset(d, z, d.ipos[3 * (size_t)j + 2]);
-            if (fma(dz, dz, fma(dy, dy, dx * dx)) < d.r2) return true;
+    for (int k = 0; k < 8; k += 2) {
+        uint32_t ja = j0[k], jb = j0[k + 1];
+        while (ja < j1[k] || jb < j1[k + 1]) {
+            const bool ia = ja < j1[k], ib = jb < j1[k + 1];
+            const size_t sa = ia ? ja : 0u, sb = ib ? jb : 0u;  // slot 0 exists (n >= 1 slots); read but ignored
+            const double ax = d.ipos[3 * sa], ay = d.ipos[3 * sa + 1], az = d.ipos[3 * sa + 2];
+            const double bx = d.ipos[3 * sb], by = d.ipos[3 * sb + 1], bz = d.ipos[3 * sb + 2];
+            const double dax = axis_offset(d, x, ax), day = axis_offset(d, y, ay), daz = axis_offset(d, z, az);
+            const double dbx = axis_offset(d, x, bx), dby = axis_offset(d, y, by), dbz = axis_offset(d, z, bz);
+            if ((ia && fma(daz, daz, fma(day, day, dax * dax)) < d.r2) ||
+                (ib && fma(dbz, dbz, fma(dby, dby, dbx * dbx)) < d.r2))
+                return true;
+            ja += ia ? 1u : 0u;
+            jb += ib ? 1u : 0u;
         }
+    }
     return false;
 }
 
