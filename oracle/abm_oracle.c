@@ -176,7 +176,7 @@ void orc_draw(uint64_t seed, uint32_t tag, uint32_t sim_id, uint64_t uid, uint64
 
 static double uniform_open(uint32_t w) { return ((double)w + 0.5) * 0x1.0p-32; }
 
-/* Algorithm 2, lines 1-3: a vector of three uniforms in (-1, 1), divided by
+/* The Brownian step of Algorithm 2: a vector of three uniforms in (-1, 1), divided by
  * its Euclidean norm, times the displacement rate.  (The normalised cube
  * vector is what the algorithm computes; it is not uniform on the sphere.) */
 void orc_brownian(uint64_t seed, uint32_t sim_id, uint64_t uid, uint64_t iter, double rate, double d[3])
@@ -189,7 +189,7 @@ void orc_brownian(uint64_t seed, uint32_t sim_id, uint64_t uid, uint64_t iter, d
     for (int a = 0; a < 3; ++a) d[a] = (v[a] / norm) * rate;
 }
 
-/* Algorithm 2, line 4: removal of a cell of at least min_age iterations. */
+/* Algorithm 2's removal of a cell of at least min_age iterations. */
 int orc_dies(const orc_params *p, uint64_t uid, uint64_t iter, int32_t age)
 {
     if (!(p->death_prob > 0.0) || age < p->min_age) return 0;
@@ -198,7 +198,7 @@ int orc_dies(const orc_params *p, uint64_t uid, uint64_t iter, int32_t age)
     return uniform_open(o[0]) < p->death_prob;
 }
 
-/* Algorithm 2, line 11: the division draw of a cell at the division size. */
+/* Algorithm 2's division draw of a cell at the division size. */
 int orc_divides(const orc_params *p, uint64_t uid, uint64_t iter)
 {
     uint32_t o[4];
@@ -464,10 +464,9 @@ int orc_step(orc_state *s, const orc_params *p)
     if (p->detect_static && p->brownian_rate > 0.0) return -3;
 
     /* the decisions of Algorithm 2 from the start-of-iteration state, first,
-       so that a capacity overflow leaves the state untouched: removal
-       (line 4), then, for the cells that stay, division (lines 9-12: grow
-       below the division volume, else divide with the division
-       probability) */
+       so that a capacity overflow leaves the state untouched: removal,
+       then, for the cells that stay, division (grow below the division
+       volume, else divide with the division probability) */
     uint8_t *dies = (uint8_t *)calloc((size_t)n, 1);
     uint8_t *divs = (uint8_t *)calloc((size_t)n, 1);
     if (!dies || !divs) { free(dies); free(divs); return -1; }
@@ -526,7 +525,7 @@ int orc_step(orc_state *s, const orc_params *p)
                 orc_displacement(fo.f, p->adherence, p->dt, p->mass, p->max_disp, d);
             }
             s->dx[i] = d[0]; s->dy[i] = d[1]; s->dz[i] = d[2];
-            /* Algorithm 2, lines 1-3: the Brownian step, then the mechanical
+            /* Algorithm 2: the Brownian step first, then the mechanical
                displacement: x' = (x + b) + d */
             double b[3] = {0.0, 0.0, 0.0};
             if (p->brownian_rate > 0.0) orc_brownian(p->seed, p->sim_id, s->uid[i], (uint64_t)s->iter, p->brownian_rate, b);
@@ -556,7 +555,7 @@ int orc_step(orc_state *s, const orc_params *p)
     memcpy(s->z, nzp, sizeof(double) * (size_t)n);
     free(nx); free(ny); free(nzp);
 
-    /* Algorithm 2, line 8: the cells that stay age by one iteration */
+    /* Algorithm 2: the cells that stay age by one iteration */
     for (int64_t i = 0; i < n; ++i)
         if (!dies[i]) s->age[i] += 1;
 
@@ -683,7 +682,7 @@ int orc_step(orc_state *s, const orc_params *p)
         for (int64_t i = 0; i < m; ++i) s->is_static[i] = 0;
     }
 
-    /* removals (Algorithm 2, line 5) take effect for the next iteration: the
+    /* removals (Algorithm 2) take effect for the next iteration: the
        cells that stay keep their order (daughters, never removed in the
        iteration that creates them, follow) */
     if (ndead > 0) {

@@ -165,7 +165,7 @@ __device__ inline void agent_draw(uint64_t seed, uint32_t tag, uint32_t sim, uin
 }
 __device__ inline double uniform_open(uint32_t w) { return ((double)w + 0.5) * 0x1.0p-32; }
 
-// Brownian step of Algorithm 2 (lines 1-3): three uniforms in (-1, 1), divided
+// Brownian step of Algorithm 2: three uniforms in (-1, 1), divided
 // by their Euclidean norm, times the displacement rate (correctly rounded FP64
 // division and square root, no contraction).
 __device__ inline void brownian_step(uint64_t seed, uint32_t sim, uint64_t uid, uint64_t iter, double rate,

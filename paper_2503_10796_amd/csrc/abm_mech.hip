@@ -1542,10 +1542,9 @@ __device__ inline void division_direction(uint64_t seed, uint32_t sim, uint64_t 
 }
 
 // Fate of every cell from the start-of-iteration state (Algorithm 2): removal
-// (line 4: at least min_age iterations old and the death draw below the
-// death probability), then, for the cells that stay, division (lines 9-12:
-// at or above the division volume and the division draw below the division
-// probability).  A removed cell is no change for the static rule (Sec 5.5,
+// (at least min_age iterations old and the death draw below the death
+// probability), then, for the cells that stay, division (at or above the
+// division volume and the division draw below the division probability).  A removed cell is no change for the static rule (Sec 5.5,
 // condition iv): its change bits are cleared.  Each agent tile also writes
 // its number of removals (rm_sum) for the compaction's scan; the totals come
 // from the scans, not from atomics.

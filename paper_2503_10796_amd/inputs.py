@@ -146,7 +146,7 @@ def sir_population(n_susceptible, n_infected, space, seed=0):
 # substances on 300^3 points), 1,000 iterations.  The thesis gives the
 # secretion quantity (1) and the gradient weight (0.75) of the model
 # (Sec 4.7.1); the space (1,200 um: 4 um voxels, 1.16 cells per 1000 um^3),
-# diffusion coefficient, decay and time step are this build's choice
+# diffusion coefficient, decay and time step are chosen here
 # (stable: 6 nu dt / dx^2 = 0.375).
 SOMA_CELL_CLUSTERING = dict(lo=0.0, space=1200.0, resolution=300, n_substances=2, diffusion=1.0, decay=0.01,
                             dt=1.0, secretion=1.0, gradient_weight=0.75, n_cells=2_000_000, steps=1000)

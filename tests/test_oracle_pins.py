@@ -431,7 +431,7 @@ def test_mlp_forward_on_a_network_computed_by_hand():
 
 # --- Algorithm 2 cell behaviour: Brownian step, apoptosis, division probability ------------
 def test_brownian_step_has_the_rate_as_length_and_symmetric_moments():
-    """Lines 1-3 of Algorithm 2: a normalised vector times the displacement
+    """The Brownian step of Algorithm 2: a normalised vector times the displacement
     rate, so every step is rate long (to rounding); the cube is symmetric
     under sign flips and axis swaps, so the mean direction is 0 and each
     squared component averages 1/3 (5 sigma over 1e5 draws)."""
@@ -457,7 +457,7 @@ def _far_apart(n, seed):
 
 
 def test_apoptosis_removes_the_expected_share_and_only_old_cells():
-    """Line 4: a cell of at least min_age iterations is removed with the death
+    """Algorithm 2's apoptosis: a cell of at least min_age iterations is removed with the death
     probability.  Of 20,000 eligible cells about N p are removed (5 sigma of
     the binomial); cells younger than min_age never are; survivors keep
     their order and uids and age by one; the removed cells are gone."""
@@ -484,7 +484,7 @@ def test_apoptosis_removes_the_expected_share_and_only_old_cells():
 
 
 def test_division_probability_divides_the_expected_share():
-    """Line 11: a cell at the division volume divides with the division
+    """Algorithm 2's division: a cell at the division volume divides with the division
     probability; one whose draw fails neither grows nor divides; a daughter
     starts at age 0 and the mother keeps her (incremented) age."""
     n = 8000
