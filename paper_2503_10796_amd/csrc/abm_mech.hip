@@ -555,13 +555,16 @@ __device__ inline void drain_dense(const uint32_t *qw, uint32_t cnt, const Pay *
 // as (unit, core box, pass group) items, one per core box with targets and
 // pass group, for k_sweep_dense, so that the boxes of the densest units spread
 // over the whole chip instead of over the four waves of one block.
-// Within an item the lanes hold (target, stream) pairs of one core box over
-// the box's shared candidates.  The candidates of all 27 boxes are staged in
-// chunks of up to kDenseChunk per wave, all of a chunk's loads in flight
-// together, and shifted into the frame of the targets' box.  Each lane only
-// tests the pair against its contact reach; survivors go to a per-wave queue
-// and the contact math runs on full 64-pair drains (and on the rest at the end
-// of each chunk), with exact fixed-point LDS accumulators per target.
+// Within an item, the up to 64 targets of a pass are grouped by the octant of
+// their box and split into sub-passes of kSubTargets.  The candidates of all
+// 27 boxes are staged in chunks of up to kDenseChunk per wave, all of a
+// chunk's loads in flight together, and shifted into the frame of the
+// targets' box; each sub-pass first keeps the chunk's candidates within reach
+// of its targets' bounding box, then its lanes hold (target, stream) pairs
+// over them.  Each lane only tests the pair against its contact reach;
+// survivors go to a per-wave queue and the contact math runs on full 64-pair
+// drains (and on the rest at the end of each chunk), with exact fixed-point
+// LDS accumulators per target.
 constexpr int kDensePassGroups = 8;  // pass p (64 targets) of a box is in group p % 8
 
 struct DenseWave {
