@@ -43,7 +43,7 @@ def test_c0_every_iteration_matches_oracle_single_step(abm, detect_static, workl
 
 @pytest.mark.parametrize("detect_static,workload", [(False, "c0"), (True, "relaxed_lattice"), (False, "crowded"),
                                                      (True, "crowded"), (False, "dense"), (False, "dense_small"),
-                                                     (False, "packed"), (False, "coincident")])
+                                                     (False, "packed"), (False, "coincident"), (False, "lattice")])
 def test_production_path_single_step_matches_oracle(abm, detect_static, workload):
     """The launch configuration of the benchmark (no diagnostics: half shell,
     row culling, reach tests and unit skipping active; ABM_RECORD only adds
@@ -61,7 +61,12 @@ def test_production_path_single_step_matches_oracle(abm, detect_static, workload
     stage and setup (the box-wise path then finishes the unit).  The
     coincident workload puts 32 agents exactly on top of others and 32 at
     1e-9 um from others: their directions are undecidable in FP32 and go to
-    the FP64 path."""
+    the FP64 path.  The lattice workload (4 um agents 3 um apart, about 150
+    per box in three passes, jittered by up to 0.01 um per axis: overlaps of
+    1 um, far from the zero of the force) gives every agent contacts with its
+    six face neighbours across the octant planes of its box, where the
+    box-wise path splits a box's targets into groups and culls each group's
+    candidates against the group's bounding box."""
     if workload == "c0":
         pos, diam = c0()
     elif workload == "relaxed_lattice":
@@ -74,6 +79,12 @@ def test_production_path_single_step_matches_oracle(abm, detect_static, workload
         pos, diam = inputs.plain(4096, 90.0, seed=9, dmin=3.0, dmax=5.0)
     elif workload == "packed":
         pos, diam = inputs.plain(4096, 55.0, seed=9)
+    elif workload == "lattice":
+        g = np.arange(16, dtype=np.float64) * 3.0
+        zz, yy, xx = np.meshgrid(g, g, g, indexing="ij")
+        pos = np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+        pos += np.random.default_rng(4).uniform(-0.01, 0.01, size=pos.shape)
+        diam = np.full(pos.shape[0], 4.0)
     else:  # coincident
         pos, diam = c0()
         pos = pos.copy()
